@@ -1,0 +1,292 @@
+"""Pins for the CPU oracle: closed forms, invariants, library routines, brute force.
+
+Each test ties one oracle function to something other than itself (the
+mathematics, an independent library routine, a published test vector, or a
+construction whose answer is known), chosen so that a plausible slip in the
+oracle (a dropped term, a wrong sign, an off-by-one, a transposed operand)
+fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+import datagen
+from oracle import sketchmp_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ z-norm
+def test_znorm_moments_and_constant_dim():
+    T = datagen.tiny_series(1, 5, 300)
+    T[3] = 7.25  # constant dimension
+    Tb, mu, sd = O.znorm_dims(T)
+    for j in (0, 1, 2, 4):
+        assert abs(Tb[j].mean()) < 1e-13
+        assert abs(Tb[j].var() - 1.0) < 1e-12          # population variance
+    assert np.all(Tb[3] == 0.0) and sd[3] == 0.0
+    assert np.allclose(mu, T.mean(axis=1), rtol=1e-14, atol=1e-12)
+    assert np.allclose(sd, T.std(axis=1), rtol=1e-13)   # numpy std is ddof=0
+
+
+def test_znorm_affine_invariant():
+    T = datagen.tiny_series(2, 3, 200)
+    a = np.array([[3.0], [0.01], [250.0]])
+    b = np.array([[-4.0], [1e3], [0.5]])
+    Tb1, _, _ = O.znorm_dims(T)
+    Tb2, _, _ = O.znorm_dims(a * T + b)
+    assert np.max(np.abs(Tb1 - Tb2)) < 1e-10
+
+
+# --------------------------------------------------------------- generator
+def _golden_splitmix():
+    rows = []
+    with open(os.path.join(GOLDEN, "splitmix64_vectors.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                s, i, v = line.split()
+                rows.append((int(s), int(i), int(v)))
+    return rows
+
+
+def test_splitmix64_published_vectors():
+    rows = _golden_splitmix()
+    assert len(rows) == 8
+    for seed, i, v in rows:
+        assert O.splitmix64_output(seed, i) == v
+
+
+def test_count_sketch_structure_and_two_universality():
+    d, k = 40, 7
+    S = O.sketch_coeffs("count", k, np.arange(d), seed=11)
+    assert S.shape == (k, d)
+    assert np.all(np.sum(S != 0.0, axis=0) == 1)            # one entry per column
+    assert set(np.unique(S[S != 0.0])) <= {-1.0, 1.0}
+    # Pr[h(j) = h(j')] = 1/k and Pr[s(j) = s(j')] = 1/2 over the random draw (Appendix)
+    seeds = range(3000)
+    coll = sum(O.count_hash(s, 3, k)[0] == O.count_hash(s, 17, k)[0] for s in seeds) / 3000
+    same_sign = sum(O.count_hash(s, 3, k)[1] == O.count_hash(s, 17, k)[1] for s in seeds) / 3000
+    assert abs(coll - 1.0 / k) < 0.03
+    assert abs(same_sign - 0.5) < 0.04
+    groups = [O.count_hash(s, 5, k)[0] for s in seeds]
+    counts = np.bincount(groups, minlength=k) / 3000
+    assert np.all(np.abs(counts - 1.0 / k) < 0.03)
+
+
+def test_gaussian_coefficients_are_standard_normal():
+    from scipy import stats
+    S = O.sketch_coeffs("gauss", 16, np.arange(400), seed=5)
+    x = S.ravel()
+    assert abs(x.mean()) < 0.04
+    assert abs(x.var() - 1.0) < 0.05
+    assert stats.kstest(x, "norm").pvalue > 1e-3
+    c = np.corrcoef(S)                     # rows independent of each other
+    assert np.max(np.abs(c - np.eye(16))) < 0.2
+    # a pure function of (seed, dim id, g): reordering dims permutes columns
+    S2 = O.sketch_coeffs("gauss", 16, np.arange(400)[::-1], seed=5)
+    assert np.array_equal(S2, S[:, ::-1])
+
+
+# ----------------------------------------------------------------- sketch
+def test_sum_sketch_is_sum_of_normalised_dims():
+    T = datagen.tiny_series(3, 6, 257)
+    R, S, mu, sd = O.build(T, "sum", 1, seed=0)
+    Tb = (T - T.mean(axis=1, keepdims=True)) / T.std(axis=1, keepdims=True)
+    assert np.max(np.abs(R[0] - Tb.sum(axis=0))) < 1e-12
+
+
+def test_sketch_matches_matmul_for_every_kind():
+    T = datagen.tiny_series(4, 9, 300)
+    Tb, _, _ = O.znorm_dims(T)
+    for kind, k in (("count", 4), ("gauss", 5), ("sum", 1)):
+        S = O.sketch_coeffs(kind, k, np.arange(9), seed=77)
+        R = O.sketch(Tb, S)
+        assert np.max(np.abs(R - np.matmul(S, Tb))) < 1e-12
+
+
+def test_identity_sketch_returns_normalised_input():
+    T = datagen.tiny_series(5, 4, 100)
+    Tb, _, _ = O.znorm_dims(T)
+    assert np.array_equal(O.sketch(Tb, np.eye(4)), Tb)
+
+
+def test_lemma1_unbiased_and_variance():
+    """Lemma 1: E[s(j) R^{h(j)}_i] = T_i^(j); Var = (1/k) sum_{j' != j} (T_i^(j'))^2."""
+    rng = np.random.default_rng(0)
+    d, k, n = 12, 3, 4
+    Tb = rng.standard_normal((d, n))
+    j = 2
+    est = []
+    for seed in range(6000):
+        S = O.sketch_coeffs("count", k, np.arange(d), seed)
+        R = O.sketch(Tb, S)
+        g = int(np.nonzero(S[:, j])[0][0])
+        est.append(S[g, j] * R[g])
+    est = np.array(est)
+    var_th = (np.sum(Tb ** 2, axis=0) - Tb[j] ** 2) / k
+    se = np.sqrt(var_th / len(est))
+    assert np.all(np.abs(est.mean(axis=0) - Tb[j]) < 5 * se)
+    assert np.all(np.abs(est.var(axis=0) / var_th - 1.0) < 0.1)
+
+
+def test_update_is_linear_and_remove_add_restores():
+    T = datagen.tiny_series(6, 10, 400)
+    T_new = datagen.tiny_series(7, 3, 400)
+    ids = np.arange(10)
+    for kind, k in (("count", 3), ("gauss", 4)):
+        R, S, mu, sd = O.build(T, kind, k, seed=9, dim_ids=ids)
+        rem = [1, 6]
+        R_upd = O.update(R, kind, k, 9, T_add=T_new, add_ids=[10, 11, 12], T_rem=T[rem], rem_ids=rem,
+                         rem_mu=mu[rem], rem_sigma=sd[rem])
+        keep = [q for q in range(10) if q not in rem]
+        T_all = np.concatenate([T[keep], T_new])
+        R_ref, _, _, _ = O.build(T_all, kind, k, seed=9, dim_ids=np.concatenate([ids[keep], [10, 11, 12]]))
+        assert np.max(np.abs(R_upd - R_ref)) < 1e-12
+        R_back = O.update(R_upd, kind, k, 9, T_add=T[rem], add_ids=rem)
+        R_back = O.update(R_back, kind, k, 9, T_rem=T_new, rem_ids=[10, 11, 12],
+                          rem_mu=T_new.mean(axis=1), rem_sigma=T_new.std(axis=1))
+        assert np.max(np.abs(R_back - R)) < 1e-12
+
+
+# --------------------------------------------------------------- distance
+def test_distance_closed_forms():
+    rng = np.random.default_rng(1)
+    for m in (4, 16, 100):
+        x = rng.standard_normal(m).cumsum()
+        assert O.dist(x, 3.5 * x - 2.0) < 1e-6
+        assert abs(O.dist(x, -x) - 2.0 * math.sqrt(m)) < 1e-12
+        y = rng.standard_normal(m)
+        dxy = O.dist(x, y)
+        assert 0.0 <= dxy <= 2.0 * math.sqrt(m)
+        rho = np.corrcoef(x, y)[0, 1]
+        assert abs(dxy ** 2 - 2.0 * m * (1.0 - rho)) < 1e-9
+
+
+def test_flat_subsequence_distances():
+    m = 8
+    c = np.full(m, 2.5)
+    x = np.arange(m, dtype=float) ** 1.5
+    assert O.dist(c, c + 0.0) == 0.0
+    assert O.dist(c, x) == math.sqrt(m)
+
+
+def _scipy_profile(r, m, excl):
+    W = np.lib.stride_tricks.sliding_window_view(r, m)
+    Z = (W - W.mean(axis=1, keepdims=True)) / W.std(axis=1, keepdims=True)
+    D = cdist(Z, Z)
+    idx = np.arange(len(Z))
+    D[np.abs(idx[:, None] - idx[None, :]) < excl] = np.inf
+    return D.min(axis=1), D.argmin(axis=1)
+
+
+@pytest.mark.parametrize("n,m,excl", [(120, 8, 2), (300, 16, 4), (257, 32, 8), (90, 5, 1)])
+def test_profile_matches_scipy_cdist(n, m, excl, c_oracle):
+    r = datagen.tiny_series(n + m, 1, n, kind="rw")[0]
+    P, I = O.matrix_profile(r, m, excl)
+    Ps, Is = _scipy_profile(r, m, excl)
+    assert np.max(np.abs(P - Ps)) < 1e-9
+    assert np.array_equal(I, Is)
+    Pc, Ic = c_oracle.profile(r, m, excl)
+    assert np.max(np.abs(Pc - P)) < 1e-12
+    assert np.array_equal(Ic, I)
+    assert len(P) == n - m + 1
+    assert np.all((P >= 0) & (P <= 2 * math.sqrt(m) + 1e-12))
+
+
+def test_profile_of_single_dim_sketch_is_plain_profile(c_oracle):
+    """d = 1 with the sum (identity) sketch equals the profile of the raw series."""
+    T = datagen.tiny_series(8, 1, 500)
+    R, _, _, _ = O.build(T, "sum", 1, seed=0)
+    P1, I1 = c_oracle.profile(R[0], 20, 5)
+    P2, I2 = c_oracle.profile(T[0], 20, 5)
+    assert np.max(np.abs(P1 - P2)) < 1e-8
+    assert np.array_equal(I1, I2)
+    P3, _ = c_oracle.profile(-3.0 + 0.125 * T[0], 20, 5)
+    assert np.max(np.abs(P3 - P2)) < 1e-8
+
+
+def test_exact_repeat_gives_zero_and_exclusion_boundary(c_oracle):
+    rng = np.random.default_rng(3)
+    m, excl = 10, 12          # excl > m so the copy does not overlap its source
+    base = rng.standard_normal(60)
+    # window at 5 repeated (scaled + shifted) at 5 + excl: admissible, distance 0
+    r = base.copy()
+    r[5 + excl:5 + excl + m] = 4.0 * r[5:5 + m] + 1.0
+    P, I = c_oracle.profile(r, m, excl)
+    assert P[5] < 1e-6 and I[5] == 5 + excl
+    assert P[5 + excl] < 1e-6 and I[5 + excl] == 5
+    # the same repeat at distance excl - 1 is a trivial match: it must be excluded
+    r2 = base.copy()
+    r2[5 + excl - 1:5 + excl - 1 + m] = 4.0 * r2[5:5 + m] + 1.0
+    P2, I2 = c_oracle.profile(r2, m, excl)
+    assert P2[5] > 1e-3 and I2[5] != 5 + excl - 1
+    Pn, In = O.matrix_profile(r2, m, excl)
+    assert np.array_equal(In, I2)
+
+
+def test_flat_windows_in_profile(c_oracle):
+    rng = np.random.default_rng(4)
+    m, excl = 8, 2
+    r = rng.standard_normal(100).cumsum()
+    r[20:40] = 3.0         # flat windows 20..32 (13 of them)
+    P, I = c_oracle.profile(r, m, excl)
+    Pn, In = O.matrix_profile(r, m, excl)
+    assert np.array_equal(I, In) and np.max(np.abs(P - Pn)) < 1e-12
+    for i in range(20, 33):
+        assert P[i] == 0.0
+        assert I[i] == (20 if i - 20 >= excl else i + excl)   # smallest admissible flat j
+    # a single flat window has only non-flat partners: sqrt(m), smallest admissible j
+    r2 = rng.standard_normal(100).cumsum()
+    r2[50:58] = -1.0
+    P2, I2 = c_oracle.profile(r2, m, excl)
+    assert P2[50] == math.sqrt(m) and I2[50] == 0
+
+
+def test_row_without_partner_is_infinite(c_oracle):
+    r = datagen.tiny_series(9, 1, 20)[0]
+    m, excl = 8, 10           # n_sub = 13; rows 3..9 have no j with |i-j| >= 10
+    P, I = c_oracle.profile(r, m, excl)
+    Pn, In = O.matrix_profile(r, m, excl)
+    assert np.isinf(P[5]) and I[5] == -1
+    assert np.array_equal(np.isinf(P), np.isinf(Pn)) and np.array_equal(I, In)
+    assert all(np.isfinite(s) for _, _, s in O.top_discords(P[None], m, 5))
+
+
+# ---------------------------------------------------------------- discords
+def test_time_detection_strict_greater_keeps_first_group():
+    P = np.array([[0.1, 0.9, 0.2],
+                  [0.3, 0.9, 0.1],     # ties the best score: group 0 keeps it
+                  [0.2, 0.4, 0.5]])
+    assert O.time_detection(P) == (1, 0, 0.9)
+    P2 = np.array([[0.1, 0.2], [0.4, 0.3]])
+    assert O.time_detection(P2) == (0, 1, 0.4)
+    assert O.time_detection(np.zeros((3, 4))) == (0, 0, 0.0)
+
+
+def test_top_discords_ordering_and_masking():
+    m = 3
+    P = np.zeros((2, 20))
+    P[0, 5] = 9.0
+    P[1, 6] = 8.0       # within |i - 5| < 3 of the first pick: masked
+    P[1, 12] = 7.0
+    P[0, 8] = 7.0       # first maximum among 8 and 12 after masking is 8 (smallest i)
+    P[0, 15] = np.inf   # no admissible partner: never reported
+    out = O.top_discords(P, m, 4)
+    assert [(i, g) for i, g, _ in out] == [(5, 0), (8, 0), (12, 1), (0, 0)]
+    assert [s for _, _, s in out][:3] == [9.0, 7.0, 7.0]
+    # the greedy list's first element is Algorithm 2's answer
+    i, g, s = O.time_detection(np.where(np.isinf(P), 0, P))
+    assert (i, g, s) == out[0]
+
+
+def test_planted_discord_is_recovered_on_c0(c_oracle):
+    w = datagen.make("c0")
+    R, S, mu, sd = O.build(w.T, w.kind, w.k, w.sketch_seed)
+    P, I = c_oracle.profile(R[0], w.m, w.excl)
+    top = O.top_discords(P[None], w.m, 10)
+    (_, _, o, _), = w.planted
+    assert abs(top[0][0] - o) <= w.m // 2
+    assert len(top) == 10 and all(top[q][2] >= top[q + 1][2] for q in range(9))
