@@ -1,0 +1,178 @@
+/*
+ * sketchmp: sketched matrix-profile discord mining on MI355X (gfx950).
+ *
+ * C-ABI of the HIP library libsketchmp.so.  The four calls of the method are
+ *   sketch_build        z-normalise every dimension and sketch d series into k
+ *                       (paper Section III-A, Algorithm 1);
+ *   sketch_update_dims  add / remove dimensions of a built sketch (Section III-C);
+ *   mp_selfjoin         z-normalised self-join matrix profile of every sketched
+ *                       series (Def. 3, Def. 6, self-join variant of Section III-B);
+ *   top_discords        discord time detection over the k profiles and the
+ *                       ordered non-overlapping discord list (Algorithm 2;
+ *                       Sections IV-B and IV-C).
+ *
+ * Conventions for every call:
+ *   - A multidimensional series T in R^{d x n} (Def. 1) is row-major: dimension j
+ *     occupies T[j*ldt .. j*ldt + N).  Several independent series may be
+ *     concatenated along time: ``offsets`` (HOST array of n_series+1 int64,
+ *     non-decreasing, offsets[0] = 0) gives series s the columns
+ *     [offsets[s], offsets[s+1]).  Every per-series output uses the same columns.
+ *   - Pointers named *_dev, and all bulk data (T, R, P, I, workspace, outputs
+ *     of top_discords) are DEVICE pointers on the current HIP device.  Pointers
+ *     documented as host are host memory.  The caller owns every buffer.
+ *   - ``stream`` is a hipStream_t (NULL = default stream).  Calls are
+ *     asynchronous: the return code covers argument validation and kernel
+ *     launch; device faults surface at the caller's next synchronisation.
+ *   - ``workspace`` is caller-provided device scratch of at least the size the
+ *     matching *_workspace query returns (256-byte aligned).  Its contents need
+ *     not be initialised and are clobbered.
+ *   - Return value: SKMP_OK (0) or a negative SKMP_E* code; a message for the
+ *     last failure on the calling thread is available from skmp_last_error().
+ *     On error nothing has been launched.
+ */
+#ifndef SKETCHMP_H
+#define SKETCHMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SKMP_OK 0
+#define SKMP_EINVAL (-1)     /* invalid argument */
+#define SKMP_ENOMEM (-2)     /* workspace too small */
+#define SKMP_EDEVICE (-3)    /* HIP runtime error */
+#define SKMP_ENONFINITE (-4) /* non-finite input (only when SKMP_FLAG_CHECK_FINITE is set) */
+#define SKMP_ENOTFOUND (-5)  /* unknown dimension id */
+
+/* sketch kinds (Section III-A): R = S * Tbar with S in R^{k x d} */
+#define SKMP_SUM 0   /* k = 1, every coefficient +1 (Fig. 1) */
+#define SKMP_COUNT 1 /* count sketch: column j has s(j) in {-1,+1} at row h(j) */
+#define SKMP_GAUSS 2 /* dense N(0,1) projection */
+
+/* input dtypes */
+#define SKMP_F64 0
+#define SKMP_F32 1
+
+/* self-join precisions */
+#define SKMP_FP64 0   /* FP64 diagonal recurrence */
+#define SKMP_FP32 1   /* FP32 MFMA tiles, FP64 seeds and polish */
+#define SKMP_BF16X3 2 /* BF16 hi+lo split MFMA tiles, FP32 accumulation */
+#define SKMP_FP16X3 3 /* FP16 hi+lo split MFMA tiles, FP32 accumulation */
+
+/* flags for sketch_build / sketch_update_dims */
+#define SKMP_FLAG_CHECK_FINITE 1u /* synchronise and reject NaN/Inf input */
+
+/* Message describing the last failure on this thread ("" if none). */
+const char* skmp_last_error(void);
+
+/* Library version string. */
+const char* skmp_version(void);
+
+/*
+ * Sketch coefficients S (k x d, row-major, HOST output of k*d doubles) for the
+ * dimensions with identifiers dim_ids[0..d) (host; NULL means 0..d-1).
+ * Coefficients are pure functions of (kind, k, seed, dimension id):
+ *   count: h(id) = ((a*id + b) mod p) mod k, s(id) = 1 - 2*(((a2*id + b2) mod p) mod 2),
+ *          p = 2^61 - 1, with (a, b, a2, b2) the first four SplitMix64(seed)
+ *          outputs reduced as 1 + o mod (p-1) / o mod p (a 2-universal family,
+ *          Section III-A and the Appendix);
+ *   gauss: Box-Muller N(0,1) from SplitMix64(seed) outputs 2c+1 and 2c+2,
+ *          c = id*64 + g;
+ *   sum:   k must be 1, every entry +1.
+ * Ids must lie in [0, 2^61 - 1); k in [1, 64].
+ */
+int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64_t* dim_ids, int64_t d, double* S_host);
+
+/* Workspace bytes needed by sketch_build (offsets host, as in sketch_build); 0 on bad arguments. */
+size_t sketch_build_workspace(int64_t d, int64_t n_series, const int64_t* offsets, int32_t k);
+
+/*
+ * Normalise and sketch (Section III-A, Algorithm 1).
+ *   T        device, d x N (N = offsets[n_series]), row stride ldt >= N, dtype SKMP_F64 or SKMP_F32.
+ *   d        number of dimensions (>= 1).
+ *   dim_ids  host, d identifiers (NULL: 0..d-1); they key the coefficients.
+ *   k, kind, seed  as in sketch_coeffs.
+ *   R        device out, k x N doubles, row stride ldr >= N:
+ *            R[g][t] = sum_j S[g][j] * (T[j][t] - mu_sj) / sigma_sj for t in series s,
+ *            where mu_sj, sigma_sj are the mean and population standard deviation
+ *            of dimension j over series s (sigma = 0 contributes 0).
+ *   dim_stats device out, n_series x d x 2 doubles: (mu_sj, sigma_sj).
+ */
+int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt, int64_t n_series, const int64_t* offsets,
+                 const int64_t* dim_ids, int32_t k, int32_t kind, uint64_t seed, uint32_t flags, double* R,
+                 int64_t ldr, double* dim_stats, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by sketch_update_dims for a series of n samples; 0 on bad arguments. */
+size_t sketch_update_workspace(int64_t n, int64_t d_add, int64_t d_rem, int32_t k);
+
+/*
+ * Add and/or remove dimensions of a single-series sketch in place (Section III-C):
+ *   R^(g) += S_g,add * Tbar_add  -  S_g,rem * Tbar_rem.
+ *   R        device, k x n, row stride ldr (as written by sketch_build with n_series = 1).
+ *   T_add    device, d_add x n (row stride ldt), new dimensions; they must span
+ *            all n samples (the paper advises against partial-membership
+ *            dimensions).  add_ids host, d_add new identifiers.
+ *   add_stats device out, d_add x 2 doubles (mu, sigma) of the added dimensions.
+ *   T_rem    device, d_rem x n (row stride ldt), the samples of the removed
+ *            dimensions; rem_ids host; rem_stats device, d_rem x 2 doubles,
+ *            the (mu, sigma) those dimensions had when they were added.
+ *   changed_groups host out (may be NULL): bit g set iff R^(g) changed
+ *            (count sketch: the groups h(id); sum / gauss: every group).
+ * Either side may be empty (d_add = 0 or d_rem = 0).
+ */
+int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, int32_t kind, uint64_t seed, int32_t dtype,
+                       int64_t ldt, const void* T_add, int64_t d_add, const int64_t* add_ids, double* add_stats,
+                       const void* T_rem, int64_t d_rem, const int64_t* rem_ids, const double* rem_stats,
+                       uint32_t flags, uint64_t* changed_groups, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by mp_selfjoin (offsets host, as in mp_selfjoin). */
+size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m, int32_t prec);
+
+/*
+ * Self-join matrix profile of every sketched series (Def. 6 with
+ * T_test = T_train, Section III-B), z-normalised Euclidean distance (Def. 3).
+ *   R        device, k x N doubles, row stride ldr (sketch_build output).
+ *   m        subsequence length, 4 <= m; every series needs n_s >= m.
+ *   excl     trivial-match exclusion: (i, j) is excluded iff |i - j| < excl; 1 <= excl.
+ *   prec     SKMP_FP64 | SKMP_FP32 | SKMP_BF16X3 | SKMP_FP16X3.
+ *   refresh  mixed precisions: rows between exact FP64 recomputations of the
+ *            running covariance (0 = default 256); ignored for SKMP_FP64.
+ *   group_mask bit g selects group g (~0 = all); unselected rows of P/I are untouched.
+ *   P        device out, k x N doubles, row stride ldp: P[g][offsets[s] + i] for
+ *            i < n_s - m + 1 is the distance from subsequence i of R^(g) in
+ *            series s to its nearest admissible neighbour; +inf if none.
+ *   I        device out, k x N int64, row stride ldp: that neighbour's index
+ *            within the series (0-based), -1 if none.
+ * Subsequence statistics use the population sigma; a subsequence whose sigma
+ * is <= 1e-10 * max|R^(g)| over its series is flat and normalises to the zero
+ * vector (dist(flat, flat) = 0, dist(flat, other) = sqrt(m)).  Reported P values
+ * are recomputed in FP64 from explicit differences for the reported neighbour.
+ */
+int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P, int64_t* I,
+                int64_t ldp, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by top_discords. */
+size_t top_discords_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m);
+
+/*
+ * Ordered list of non-overlapping discords per series (Algorithm 2, Sections IV-B/C).
+ * A[i] = max over groups of P[g][i] (the first group on ties, the strict ">"
+ * of Algorithm 2); repeatedly take the first maximum of A among unmasked
+ * finite entries and mask |i - i*| < halfwidth (0 = m).
+ *   idx, group, score device out, n_series x top_k; n_found device out, n_series.
+ * Entries past n_found[s] are -1 / -1 / NaN.
+ */
+int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                 int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group, double* score, int32_t* n_found,
+                 void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKETCHMP_H */

@@ -24,7 +24,7 @@ blocking, fusion or reordering beyond what the definition states:
 Readings where the paper is silent (each one is listed in the design doc):
 
 * z-normalisation uses the population standard deviation; a constant
-  dimension (sigma = 0) normalises to all zeros.
+  dimension (sigma <= FLAT_REL * max|value|) normalises to all zeros.
 * a subsequence is *flat* when its population sigma is <= FLAT_REL times the
   largest |value| of its series; a flat subsequence normalises to the zero
   vector, so dist(flat, flat) = 0 and dist(flat, non-flat) = sqrt(m) exactly.
@@ -59,7 +59,9 @@ def znorm_dims(T: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Per-dimension z-normalisation, Section III-A.
 
     Returns (Tbar, mu, sigma) with mu_j the mean and sigma_j the population
-    standard deviation of row j.  sigma_j == 0 gives an all-zero row.
+    standard deviation of row j.  A dimension whose sigma is at most FLAT_REL
+    times its largest |value| is constant: sigma_j is reported as 0 and its
+    normalised row is all zeros.
     """
     T = np.asarray(T, dtype=np.float64)
     d, n = T.shape
@@ -71,6 +73,8 @@ def znorm_dims(T: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         mu[j] = math.fsum(x) / n
         dev = x - mu[j]
         sd[j] = math.sqrt(math.fsum(dev * dev) / n)
+        if sd[j] <= FLAT_REL * float(np.max(np.abs(x))):
+            sd[j] = 0.0
         if sd[j] > 0.0:
             Tbar[j] = dev / sd[j]
     return Tbar, mu, sd

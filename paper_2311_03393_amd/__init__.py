@@ -1,0 +1,222 @@
+"""Python binding of libsketchmp (sketched matrix-profile discord mining on MI355X).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libsketchmp.so`` (built by ``paper_2311_03393_amd.build``).  PyTorch supplies
+device memory and the current stream.  There is no fallback: if the library
+is missing, or no GPU is present, every call raises.
+
+Functions mirror the C-ABI in ``include/sketchmp.h``:
+
+* ``sketch_build``        normalise and sketch (Section III-A, Algorithm 1)
+* ``sketch_update_dims``  add / remove dimensions (Section III-C)
+* ``mp_selfjoin``         self-join matrix profile of each sketched series
+* ``top_discords``        Algorithm 2 plus the ordered discord list
+* ``sketch_coeffs``       the coefficient matrix S (host computation)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsketchmp.so")
+
+SUM, COUNT, GAUSS = 0, 1, 2
+KINDS = {"sum": SUM, "count": COUNT, "gauss": GAUSS}
+F64, F32 = 0, 1
+FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
+FLAG_CHECK_FINITE = 1
+
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTFOUND"}
+
+# every symbol include/sketchmp.h declares
+EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
+            "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
+            "top_discords_workspace", "top_discords")
+
+
+class SketchMPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp, _i32, _i64, _u32, _u64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_size_t)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def lib():
+    """Load libsketchmp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2311_03393_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.skmp_last_error.restype = ctypes.c_char_p
+        L.skmp_version.restype = ctypes.c_char_p
+        L.sketch_coeffs.argtypes = [_i32, _i32, _u64, _i64p, _i64, _dp]
+        L.sketch_build_workspace.argtypes = [_i64, _i64, _i64p, _i32]
+        L.sketch_build_workspace.restype = _sz
+        L.sketch_build.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64p, _i64p, _i32, _i32, _u64, _u32, _vp, _i64,
+                                   _vp, _vp, _sz, _vp]
+        L.sketch_update_workspace.argtypes = [_i64, _i64, _i64, _i32]
+        L.sketch_update_workspace.restype = _sz
+        L.sketch_update_dims.argtypes = [_vp, _i64, _i64, _i32, _i32, _u64, _i32, _i64, _vp, _i64, _i64p, _vp,
+                                         _vp, _i64, _i64p, _vp, _u32, _u64p, _vp, _sz, _vp]
+        L.mp_selfjoin_workspace.argtypes = [_i64, _i64p, _i32, _i32, _i32]
+        L.mp_selfjoin_workspace.restype = _sz
+        L.mp_selfjoin.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _i64, _vp,
+                                  _sz, _vp]
+        L.top_discords_workspace.argtypes = [_i64, _i64p, _i32, _i32]
+        L.top_discords_workspace.restype = _sz
+        L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
+                                   _vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise SketchMPError(rc, lib().skmp_last_error().decode())
+
+
+def _i64arr(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+
+
+def _ptr64(a: np.ndarray):
+    return a.ctypes.data_as(_i64p)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("sketchmp needs a GPU (no HIP device visible)")
+    return torch
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_ws_cache = {}
+
+
+def _workspace(torch, nbytes: int, device):
+    key = (str(device),)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def version() -> str:
+    return lib().skmp_version().decode()
+
+
+def sketch_coeffs(kind: str, k: int, seed: int, dim_ids: Sequence[int]) -> np.ndarray:
+    """Coefficient matrix S (k x d) drawn by the library (host computation)."""
+    ids = _i64arr(dim_ids)
+    S = np.empty((k, ids.size), dtype=np.float64)
+    _check(lib().sketch_coeffs(KINDS[kind], k, seed, _ptr64(ids), ids.size, S.ctypes.data_as(_dp)))
+    return S
+
+
+def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_finite: bool = False):
+    """Normalise every dimension per series and sketch: returns (R k x N, dim_stats n_series x d x 2)."""
+    torch = _torch()
+    assert T.is_cuda and T.dim() == 2 and T.stride(1) == 1
+    dtype = {torch.float64: F64, torch.float32: F32}[T.dtype]
+    d, N = T.shape
+    offs = _i64arr(offsets)
+    n_series = offs.size - 1
+    ids = None if dim_ids is None else _i64arr(dim_ids)
+    R = torch.empty((k, N), dtype=torch.float64, device=T.device)
+    stats = torch.empty((n_series, d, 2), dtype=torch.float64, device=T.device)
+    ws_n = lib().sketch_build_workspace(d, n_series, _ptr64(offs), k)
+    ws = _workspace(torch, ws_n, T.device)
+    _check(lib().sketch_build(T.data_ptr(), dtype, d, T.stride(0), n_series, _ptr64(offs),
+                              None if ids is None else _ptr64(ids), k, KINDS[kind], seed,
+                              FLAG_CHECK_FINITE if check_finite else 0, R.data_ptr(), R.stride(0), stats.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream(torch)))
+    return R, stats
+
+
+def sketch_update_dims(R, kind: str, k: int, seed: int, T_add=None, add_ids=(), T_rem=None, rem_ids=(),
+                       rem_stats=None, check_finite: bool = False):
+    """Add / remove dimensions in place (Section III-C); returns (add_stats, changed_group_mask)."""
+    torch = _torch()
+    n = R.shape[1]
+    add_ids = _i64arr(add_ids)
+    rem_ids = _i64arr(rem_ids)
+    d_add, d_rem = add_ids.size, rem_ids.size
+    ref = T_add if d_add else T_rem
+    dtype = F64 if (ref is None or ref.dtype == torch.float64) else F32
+    ldt = ref.stride(0) if ref is not None else n
+    if d_add and d_rem:
+        assert T_add.dtype == T_rem.dtype and T_add.stride(0) == T_rem.stride(0)
+    add_stats = torch.empty((max(d_add, 1), 2), dtype=torch.float64, device=R.device)
+    mask = ctypes.c_uint64(0)
+    ws_n = lib().sketch_update_workspace(n, d_add, d_rem, k)
+    ws = _workspace(torch, ws_n, R.device)
+    _check(lib().sketch_update_dims(R.data_ptr(), R.stride(0), n, k, KINDS[kind], seed, dtype, ldt,
+                                    T_add.data_ptr() if d_add else None, d_add, _ptr64(add_ids),
+                                    add_stats.data_ptr() if d_add else None,
+                                    T_rem.data_ptr() if d_rem else None, d_rem, _ptr64(rem_ids),
+                                    rem_stats.data_ptr() if d_rem else None,
+                                    FLAG_CHECK_FINITE if check_finite else 0, ctypes.byref(mask), ws.data_ptr(),
+                                    ws.numel(), _stream(torch)))
+    return add_stats[:d_add], int(mask.value)
+
+
+def mp_selfjoin_workspace(offsets, k: int, m: int, prec: str = "fp64") -> int:
+    offs = _i64arr(offsets)
+    return int(lib().mp_selfjoin_workspace(offs.size - 1, _ptr64(offs), k, m, PRECISIONS[prec]))
+
+
+def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0,
+                group_mask: Optional[int] = None, P=None, I=None, workspace=None):
+    """Self-join matrix profile per sketched series: returns (P k x N float64, I k x N int64)."""
+    torch = _torch()
+    offs = _i64arr(offsets)
+    n_series = offs.size - 1
+    N = int(offs[-1])
+    if P is None:
+        P = torch.full((k, N), float("nan"), dtype=torch.float64, device=R.device)
+    if I is None:
+        I = torch.full((k, N), -2, dtype=torch.int64, device=R.device)
+    assert P.stride(0) == I.stride(0)
+    if workspace is None:
+        ws_n = lib().mp_selfjoin_workspace(n_series, _ptr64(offs), k, m, PRECISIONS[prec])
+        workspace = _workspace(torch, ws_n, R.device)
+    mask = (1 << 64) - 1 if group_mask is None else int(group_mask)
+    _check(lib().mp_selfjoin(R.data_ptr(), R.stride(0), n_series, _ptr64(offs), k, m, excl, PRECISIONS[prec],
+                             refresh, mask, P.data_ptr(), I.data_ptr(), P.stride(0), workspace.data_ptr(),
+                             workspace.numel(), _stream(torch)))
+    return P, I
+
+
+def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0):
+    """Ordered non-overlapping discords per series: (idx, group, score, n_found) device tensors."""
+    torch = _torch()
+    offs = _i64arr(offsets)
+    n_series = offs.size - 1
+    idx = torch.empty((n_series, top_k), dtype=torch.int64, device=P.device)
+    grp = torch.empty((n_series, top_k), dtype=torch.int32, device=P.device)
+    score = torch.empty((n_series, top_k), dtype=torch.float64, device=P.device)
+    nf = torch.empty((n_series,), dtype=torch.int32, device=P.device)
+    ws_n = lib().top_discords_workspace(n_series, _ptr64(offs), k, m)
+    ws = _workspace(torch, ws_n, P.device)
+    _check(lib().top_discords(P.data_ptr(), P.stride(0), n_series, _ptr64(offs), k, m, top_k, halfwidth,
+                              idx.data_ptr(), grp.data_ptr(), score.data_ptr(), nf.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream(torch)))
+    return idx, grp, score, nf

@@ -1,0 +1,604 @@
+// Self-join matrix profile of the sketched series (paper Def. 3, Def. 6 and the
+// self-join variant of Section III-B), FP64 diagonal kernel + shared stages.
+//
+// Stages (all on the caller's stream):
+//   fill      zero the key arrays, queue head and flat-window summaries;
+//   scale     max |r| per (series, group): the flat-window threshold;
+//   substats  per window x: mean, 1/(sqrt(m) sigma) (0 if flat), and the
+//             difference terms df_x = (r[x+m] - r[x]) / 2,
+//             dg_x = (r[x+m] - mu[x+1]) + (r[x] - mu[x]), all FP64;
+//   tiles     the diagonal recurrence of the centred covariance
+//             C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i, seeded exactly in
+//             FP64, rho = C / (m sigma_i sigma_j), row and column maxima with the
+//             partner encoded in the low mantissa bits of (rho + 2);
+//   merge     pick the best row / column key, apply the flat-window rule and
+//             recompute the reported distance exactly from explicit differences.
+//
+// Tile geometry (one wave64 per work unit):  a band holds 64*C consecutive
+// diagonals, lane t owning diagonals db + t*C + q (q < C).  At step u lane t
+// sits on row i = u - t, so the 64 lanes touch 64 distinct rows and, through
+// the sliding window of C columns each lane keeps, 64 distinct retiring
+// columns: per-step partial maxima go to LDS with ds_max_u64 without
+// conflicts.  Every TL steps the LDS partials are flushed into the global key
+// arrays with 64-bit atomic max.  A work unit is one strip of S steps of one
+// band of one (series, group); the queue hands units out dynamically.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <climits>
+#include <string>
+#include <vector>
+
+#include "skmp_common.hpp"
+
+namespace skmp {
+
+__global__ void fill_u64(unsigned long long* p, unsigned long long v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void fill_i32(int32_t* p, int32_t v, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// chunk (256 padded windows of one (series, group slot)) -> (s, gi, x0)
+struct ChunkPos {
+  int s, gi;
+  int64_t x0;  // first window index (may be negative, down to -PADL)
+};
+
+__device__ __forceinline__ ChunkPos decode_chunk(const SJState& st, int64_t chunk) {
+  ChunkPos c;
+  c.s = find_series(st.plan, st.n_series, chunk, &SeriesPlan::chunk_base);
+  const SeriesPlan& sp = st.plan[c.s];
+  const int64_t per_group = (sp.n_sub + PADL + PADR + 255) / 256;
+  const int64_t local = chunk - sp.chunk_base;
+  c.gi = (int)(local / per_group);
+  c.x0 = (local - (int64_t)c.gi * per_group) * 256 - PADL;
+  return c;
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(SJState st) {
+  const ChunkPos c = decode_chunk(st, blockIdx.x);
+  const SeriesPlan& sp = st.plan[c.s];
+  const int64_t t = c.x0 + threadIdx.x;
+  const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
+  double v = (t >= 0 && t < sp.n) ? fabs(r[t]) : 0.0;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
+  if ((threadIdx.x & 63) == 0 && v > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long*>(st.scale) + (int64_t)c.s * st.groups.count + c.gi,
+              (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ __launch_bounds__(256) void substats_kernel(SJState st) {
+  extern __shared__ double sh_r[];  // 256 + m + 1 samples
+  const ChunkPos c = decode_chunk(st, blockIdx.x);
+  const SeriesPlan& sp = st.plan[c.s];
+  const int m = st.m;
+  const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
+  const int span = 256 + m + 1;
+  for (int q = threadIdx.x; q < span; q += 256) {
+    const int64_t t = c.x0 + q;
+    sh_r[q] = (t >= 0 && t < sp.n) ? r[t] : 0.0;
+  }
+  __syncthreads();
+  const int64_t x = c.x0 + threadIdx.x;
+  const int64_t sidx = (int64_t)c.gi * st.gstride + sp.stat_base + PADL + x;
+  if (x < 0 || x >= sp.n_sub) {
+    st.dfdg[sidx] = make_double2(0.0, 0.0);
+    st.invn[sidx] = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
+    st.mu[sidx] = 0.0;
+    return;
+  }
+  const double* w = sh_r + threadIdx.x;
+  const double inv_m = 1.0 / m;
+  double s = 0.0;
+  for (int q = 0; q < m; ++q) s += w[q];
+  const double mu = s * inv_m;
+  double v = 0.0;
+  for (int q = 0; q < m; ++q) {
+    const double e = w[q] - mu;
+    v = fma(e, e, v);
+  }
+  const double sd = sqrt(v * inv_m);
+  const double scale = st.scale[(int64_t)c.s * st.groups.count + c.gi];
+  const bool flat = sd <= FLAT_REL * scale;
+  double df = 0.0, dg = 0.0;
+  if (x + 1 < sp.n_sub) {
+    double s1 = 0.0;
+    for (int q = 1; q <= m; ++q) s1 += w[q];
+    const double mu1 = s1 * inv_m;
+    df = 0.5 * (w[m] - w[0]);
+    dg = (w[m] - mu1) + (w[0] - mu);
+  }
+  st.dfdg[sidx] = make_double2(df, dg);
+  st.invn[sidx] = flat ? 0.0 : 1.0 / (sd * sqrt((double)m));
+  st.mu[sidx] = mu;
+  if (flat) {
+    const int64_t sg = (int64_t)c.s * st.groups.count + c.gi;
+    atomicMin(st.flat_first + sg, (int32_t)x);
+    atomicMax(st.flat_last + sg, (int32_t)x);
+    atomicMin(st.flat_blk + (int64_t)c.gi * st.blk_stride + sp.blk_base + (x >> 8), (int32_t)x);
+  }
+}
+
+// v_max_f64 without the canonicalising copy the compiler adds to IEEE fmax for
+// operands it cannot prove canonical (the keys are bit-manipulated).  IEEE-mode
+// max returns the non-NaN operand, which masks padded cells.
+__device__ __forceinline__ double vmax(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+__device__ __forceinline__ double embed(double x, uint32_t keep, uint32_t code) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const uint32_t lo = ((uint32_t)b & keep) | code;
+  return __longlong_as_double((long long)((b & 0xFFFFFFFF00000000ull) | lo));
+}
+
+__device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned long long)__double_as_longlong(k); }
+
+template <int C>
+struct LaneState {
+  double Cq[C];
+  double cdf[C], cdg[C], cinv[C];
+  double colacc[C];
+};
+
+template <int C, bool EDGE>
+__device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, const uint32_t (&code)[C], uint32_t keep, int ngroups,
+                                              int row0, int jbase, const double2* __restrict__ dfdg,
+                                              const double* __restrict__ invn, unsigned long long* rowk,
+                                              unsigned long long* colk, int t) {
+  for (int gidx = 0; gidx < ngroups; ++gidx) {
+#pragma unroll
+    for (int p = 0; p < C; ++p) {
+      const int us = gidx * C + p;
+      const int i = row0 + us;
+      const double2 rs = dfdg[i];
+      const double rinv = invn[i];
+      const int jn = jbase + us + C - 1;
+      const int sn = (p + C - 1) % C;
+      const double2 cs = dfdg[jn];
+      ls.cdf[sn] = cs.x;
+      ls.cdg[sn] = cs.y;
+      ls.cinv[sn] = invn[jn];
+      double rowp = 0.0;
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const int sl = (p + q) % C;
+        const double a = ls.Cq[q] * ls.cinv[sl];
+        double key = fma(a, rinv, 2.0);
+        key = embed(key, keep, code[q]);
+        if (q == 0) rowp = EDGE ? vmax(0.0, key) : key;
+        else rowp = vmax(rowp, key);
+        if (q == C - 1) ls.colacc[sl] = EDGE ? vmax(0.0, key) : key;
+        else ls.colacc[sl] = vmax(ls.colacc[sl], key);
+        ls.Cq[q] = fma(rs.x, ls.cdg[sl], ls.Cq[q]);
+        ls.Cq[q] = fma(ls.cdf[sl], rs.y, ls.Cq[q]);
+      }
+      atomicMax(&rowk[us + 63 - t], kbits(rowp));
+      atomicMax(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
+    }
+  }
+}
+
+template <int C, int TL>
+__global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
+  constexpr int NROW = TL + 64;
+  constexpr int NCOL = TL + 64 * C;
+  constexpr int LBITS = (64 * C <= 512) ? 9 : ((64 * C <= 1024) ? 10 : 11);
+  constexpr uint32_t LMAX = (1u << LBITS) - 1;
+  static_assert(TL % C == 0, "tile length must be a multiple of C");
+  __shared__ unsigned long long rowk[NROW];
+  __shared__ unsigned long long colk[NCOL];
+  const int t = threadIdx.x;
+  for (int x = t; x < NROW; x += 64) rowk[x] = 0ull;
+  for (int x = t; x < NCOL; x += 64) colk[x] = 0ull;
+  __syncthreads();
+  const uint32_t keep = ~LMAX;
+  uint32_t code[C];
+#pragma unroll
+  for (int q = 0; q < C; ++q) code[q] = LMAX - (uint32_t)(t * C + q);
+  const unsigned long long GMAX = (1ull << st.key_bits) - 1;
+  const int m = st.m;
+
+  for (;;) {
+    unsigned int unit = 0;
+    if (t == 0) unit = atomicAdd(st.counter, 1u);
+    unit = __shfl(unit, 0);
+    if ((int64_t)unit >= st.total_units) break;
+    const int s = find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base);
+    const SeriesPlan sp = st.plan[s];
+    const int64_t local = (int64_t)unit - sp.unit_base;
+    const int64_t per_group = (int64_t)sp.nb * sp.ns;
+    const int gi = (int)(local / per_group);
+    const int64_t rem = local - (int64_t)gi * per_group;
+    const int sigma = (int)(rem / sp.nb);
+    const int b = (int)(rem - (int64_t)sigma * sp.nb);
+    const int n_sub = (int)sp.n_sub;
+    const int db = st.excl + b * 64 * C;
+    const int Ub = n_sub - db;
+    const int u_begin = sigma * st.strip;
+    if (u_begin >= Ub) continue;
+    const int u_end = min(u_begin + st.strip, Ub);
+
+    const int64_t sbase = (int64_t)gi * st.gstride + sp.stat_base + PADL;
+    const double2* __restrict__ dfdg = st.dfdg + sbase;
+    const double* __restrict__ invn = st.invn + sbase;
+    const double* __restrict__ mu = st.mu + sbase;
+    const double* __restrict__ r = st.R + (int64_t)st.groups.g[gi] * st.ldr + sp.col;
+    unsigned long long* gro = st.rowkey + sbase;
+    unsigned long long* gco = st.colkey + sbase;
+
+    LaneState<C> ls;
+    // exact FP64 seeds at the strip start: lane t's first row is u_begin - t
+    {
+      const int rr = max(u_begin - t, 0);
+      const int j0 = rr + db + t * C;
+      const double mr = mu[rr];
+#pragma unroll
+      for (int q = 0; q < C; ++q) ls.Cq[q] = 0.0;
+      double mj[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) mj[q] = (j0 + q < n_sub) ? mu[j0 + q] : 0.0;
+      const int nvalid = min(C, max(0, n_sub - j0));
+      for (int x = 0; x < m; ++x) {
+        const double a = r[rr + x] - mr;
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+          if (q < nvalid) ls.Cq[q] = fma(a, r[j0 + q + x] - mj[q], ls.Cq[q]);
+      }
+    }
+    // column window: columns J + q (q < C-1) in slots q, J = u_begin + db + t (C-1)
+    {
+      const int J = u_begin + db + t * (C - 1);
+#pragma unroll
+      for (int q = 0; q < C - 1; ++q) {
+        const double2 cs = dfdg[J + q];
+        ls.cdf[q] = cs.x;
+        ls.cdg[q] = cs.y;
+        ls.cinv[q] = invn[J + q];
+        ls.colacc[q] = 0.0;
+      }
+    }
+
+    for (int u0 = u_begin; u0 < u_end; u0 += TL) {
+      const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
+      const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
+      const int row0 = u0 - t;
+      const int jbase = u0 + db + t * (C - 1);
+      if (edge)
+        sj_run_groups<C, true>(ls, code, keep, ngroups, row0, jbase, dfdg, invn, rowk, colk, t);
+      else
+        sj_run_groups<C, false>(ls, code, keep, ngroups, row0, jbase, dfdg, invn, rowk, colk, t);
+      const bool last = (u0 + TL >= u_end);
+      if (last) {
+        // retire the columns still open in the window (phase 0 after full groups)
+#pragma unroll
+        for (int q = 0; q < C - 1; ++q)
+          atomicMax(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
+      }
+      __syncthreads();
+      // flush rows [u0 - 63, u0 + TL) and columns [u0 + db, u0 + db + NCOL)
+      for (int xr = t; xr < NROW; xr += 64) {
+        const unsigned long long key = rowk[xr];
+        if (key) {
+          rowk[xr] = 0ull;
+          const int x = u0 - 63 + xr;
+          if (x >= 0 && x < n_sub) {
+            const int delta = db + (int)(LMAX - (uint32_t)(key & LMAX));
+            const unsigned long long gk = (key & ~GMAX) | (GMAX - (unsigned long long)delta);
+            atomicMax(gro + x, gk);
+          }
+        }
+      }
+      for (int xr = t; xr < NCOL; xr += 64) {
+        const unsigned long long key = colk[xr];
+        if (key) {
+          colk[xr] = 0ull;
+          const int j = u0 + db + xr;
+          if (j < n_sub) {
+            const int delta = db + (int)(LMAX - (uint32_t)(key & LMAX));
+            const unsigned long long gk = (key & ~GMAX) | (GMAX - (unsigned long long)delta);
+            atomicMax(gco + j, gk);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------ merge
+__device__ int smallest_flat_at_or_after(const SJState& st, const double* invn, const int32_t* fblk, int64_t y,
+                                         int64_t last) {
+  if (y > last) return -1;
+  int64_t blk = y >> 8;
+  // partial first block: scan elements
+  const int64_t first_end = (blk + 1) << 8;
+  if (fblk[blk] != INT_MAX && fblk[blk] <= last) {
+    for (int64_t z = y; z < first_end && z <= last; ++z)
+      if (invn[z] == 0.0) return (int)z;
+  }
+  for (++blk; (blk << 8) <= last; ++blk)
+    if (fblk[blk] != INT_MAX) return fblk[blk];
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64_t* I, int64_t ldp) {
+  const ChunkPos c = decode_chunk(st, blockIdx.x);
+  const SeriesPlan& sp = st.plan[c.s];
+  const int64_t x = c.x0 + threadIdx.x;
+  if (x < 0 || x >= sp.n_sub) return;
+  const int m = st.m;
+  const int excl = st.excl;
+  const int64_t n_sub = sp.n_sub;
+  const int g = st.groups.g[c.gi];
+  const int64_t sbase = (int64_t)c.gi * st.gstride + sp.stat_base + PADL;
+  const double* invn = st.invn + sbase;
+  const double* mu = st.mu + sbase;
+  const double* r = st.R + (int64_t)g * st.ldr + sp.col;
+  const unsigned long long GMAX = (1ull << st.key_bits) - 1;
+  const unsigned long long rk = st.rowkey[sbase + x], ck = st.colkey[sbase + x];
+  int64_t partner = -1;
+  if (ck != 0ull && ck >= rk) partner = x - (int64_t)(GMAX - (ck & GMAX));
+  else if (rk != 0ull) partner = x + (int64_t)(GMAX - (rk & GMAX));
+
+  const double sqrt_m = sqrt((double)m);
+  const int64_t sg = (int64_t)c.s * st.groups.count + c.gi;
+  const int32_t ff = st.flat_first[sg], fl = st.flat_last[sg];
+  const int32_t* fblk = st.flat_blk + (int64_t)c.gi * st.blk_stride + sp.blk_base;
+  const bool xflat = invn[x] == 0.0;
+
+  // smallest admissible flat partner (|j - x| >= excl), -1 if none
+  int64_t jf = -1;
+  if (ff != INT_MAX) {
+    if ((int64_t)ff <= x - excl) jf = ff;
+    else jf = smallest_flat_at_or_after(st, invn, fblk, x + excl, fl);
+  }
+
+  double best;
+  int64_t arg;
+  if (xflat) {
+    if (jf >= 0) {
+      best = 0.0;
+      arg = jf;
+    } else {
+      arg = (x >= excl) ? 0 : ((x + excl < n_sub) ? x + excl : -1);
+      best = (arg >= 0) ? sqrt_m : INFINITY;
+    }
+  } else {
+    best = INFINITY;
+    arg = -1;
+    if (partner >= 0) {
+      if (invn[partner] == 0.0) {
+        best = sqrt_m;
+      } else {
+        // exact distance from explicit differences of the normalised windows
+        const double ax = invn[x] * sqrt_m, ap = invn[partner] * sqrt_m;
+        const double mx = mu[x], mp = mu[partner];
+        double acc = 0.0;
+        for (int q = 0; q < m; ++q) {
+          const double e = (r[x + q] - mx) * ax - (r[partner + q] - mp) * ap;
+          acc = fma(e, e, acc);
+        }
+        best = sqrt(acc);
+      }
+      arg = partner;
+    }
+    if (jf >= 0 && (sqrt_m < best || (sqrt_m == best && jf < arg))) {
+      best = sqrt_m;
+      arg = jf;
+    }
+  }
+  P[(int64_t)g * ldp + sp.col + x] = best;
+  I[(int64_t)g * ldp + sp.col + x] = arg;
+}
+
+// ------------------------------------------------------------------ host
+struct PlanInfo {
+  std::vector<SeriesPlan> sp;
+  int64_t gstride = 0, total_units_per_group = 0, total_chunks_per_group = 0, blk_stride = 0;
+  int64_t total_units = 0, total_chunks = 0;
+  int key_bits = 0;
+};
+
+static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_t excl, int kact, int C, int strip,
+                     PlanInfo& pl, bool validate) {
+  pl.sp.resize(n_series);
+  int64_t stat = 0, unit = 0, chunk = 0, blk = 0, max_nsub = 1;
+  for (int64_t s = 0; s < n_series; ++s) {
+    SeriesPlan& p = pl.sp[s];
+    p.col = offsets[s];
+    p.n = offsets[s + 1] - offsets[s];
+    if (validate && p.n < m) {
+      set_error("series " + std::to_string(s) + " is shorter than m");
+      return SKMP_EINVAL;
+    }
+    p.n_sub = std::max<int64_t>(p.n - m + 1, 1);
+    max_nsub = std::max(max_nsub, p.n_sub);
+    p.stat_base = stat;
+    stat += p.n_sub + PADL + PADR;
+    const int64_t nd = p.n_sub - excl;  // diagonals with admissible pairs
+    const int64_t D = 64 * (int64_t)C;
+    p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
+    p.ns = nd > 0 ? (int32_t)(((p.n_sub - excl) + strip - 1) / strip) : 0;
+    p.unit_base = unit;
+    unit += (int64_t)p.nb * p.ns * kact;
+    p.chunk_base = chunk;
+    chunk += ((p.n_sub + PADL + PADR + 255) / 256) * kact;
+    p.blk_base = blk;
+    blk += (p.n_sub + 255) / 256;
+  }
+  pl.gstride = stat;
+  pl.total_units = unit;
+  pl.total_chunks = chunk;
+  pl.blk_stride = blk;
+  int bits = 1;
+  while ((1ll << bits) <= max_nsub) ++bits;
+  pl.key_bits = std::max(bits, 11);
+  return SKMP_OK;
+}
+
+struct SJBuffers {
+  SeriesPlan* plan;
+  double2* dfdg;
+  double* invn;
+  double* mu;
+  unsigned long long* rowkey;
+  unsigned long long* colkey;
+  double* scale;
+  int32_t* flat_first;
+  int32_t* flat_last;
+  int32_t* flat_blk;
+  unsigned int* counter;
+};
+
+static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, SJBuffers& b) {
+  const size_t cells = (size_t)kact * (size_t)pl.gstride;
+  b.plan = cv.take<SeriesPlan>(n_series);
+  b.dfdg = cv.take<double2>(cells);
+  b.invn = cv.take<double>(cells);
+  b.mu = cv.take<double>(cells);
+  b.rowkey = cv.take<unsigned long long>(cells);
+  b.colkey = cv.take<unsigned long long>(cells);
+  b.scale = cv.take<double>((size_t)n_series * kact);
+  b.flat_first = cv.take<int32_t>((size_t)n_series * kact);
+  b.flat_last = cv.take<int32_t>((size_t)n_series * kact);
+  b.flat_blk = cv.take<int32_t>((size_t)kact * (size_t)pl.blk_stride);
+  b.counter = cv.take<unsigned int>(64);
+}
+
+// tile configuration of the FP64 kernel
+constexpr int FP64_C = 8;
+constexpr int FP64_TL = 256;
+constexpr int DEFAULT_STRIP = 2048;
+
+static int grid_for(const void* kernel, int block, size_t lds) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess || per_cu < 1) per_cu = 4;
+  return ncu * per_cu;
+}
+
+}  // namespace skmp
+
+using namespace skmp;
+
+static int active_groups(int32_t k, uint64_t group_mask, GroupList& gl) {
+  gl.count = 0;
+  for (int g = 0; g < k; ++g)
+    if ((group_mask >> g) & 1ull) gl.g[gl.count++] = (int8_t)g;
+  return gl.count;
+}
+
+extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                                        int32_t prec) {
+  (void)prec;
+  if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
+  PlanInfo pl;
+  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, FP64_C, DEFAULT_STRIP, pl, false) != SKMP_OK) return 0;
+  Carve cv(nullptr, 0);
+  SJBuffers b;
+  carve_sj(cv, pl, n_series, k, b);
+  return cv.used + 256;
+}
+
+extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
+                           int32_t m, int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P,
+                           int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(R && P && I && offsets, "null pointer argument");
+  SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(m >= 4 && m <= 2048, "m must lie in [4, 2048]");
+  SKMP_REQUIRE(excl >= 1, "excl must be >= 1 (a subsequence is its own trivial match)");
+  SKMP_REQUIRE(prec >= SKMP_FP64 && prec <= SKMP_FP16X3, "unknown precision");
+  SKMP_REQUIRE(refresh >= 0, "refresh must be >= 0");
+  SKMP_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
+  for (int64_t s = 0; s < n_series; ++s) SKMP_REQUIRE(offsets[s + 1] >= offsets[s], "offsets must be non-decreasing");
+  const int64_t N = offsets[n_series];
+  SKMP_REQUIRE(ldr >= N && ldp >= N, "row strides must be >= the total number of samples");
+  for (int64_t s = 0; s < n_series; ++s)
+    SKMP_REQUIRE(offsets[s + 1] - offsets[s] < (int64_t)INT_MAX - 2 * PADR, "series too long");
+  if (k < 64) group_mask &= (1ull << k) - 1;
+  GroupList gl;
+  if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
+  if (prec != SKMP_FP64) {
+    set_error("mixed-precision self-join is not available in this build");
+    return SKMP_EINVAL;
+  }
+  const int kact = gl.count;
+  PlanInfo pl;
+  int rc = make_plan(n_series, offsets, m, excl, kact, FP64_C, DEFAULT_STRIP, pl, true);
+  if (rc) return rc;
+  Carve cv(workspace, ws_bytes);
+  SJBuffers b;
+  carve_sj(cv, pl, n_series, kact, b);
+  if (!workspace || !cv.fits()) {
+    set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
+    return SKMP_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SKMP_CHECK_HIP(hipMemcpyAsync(b.plan, pl.sp.data(), sizeof(SeriesPlan) * n_series, hipMemcpyHostToDevice, st));
+
+  SJState s;
+  s.R = R;
+  s.ldr = ldr;
+  s.plan = b.plan;
+  s.n_series = (int32_t)n_series;
+  s.m = m;
+  s.excl = excl;
+  s.key_bits = pl.key_bits;
+  s.gstride = pl.gstride;
+  s.groups = gl;
+  s.dfdg = b.dfdg;
+  s.invn = b.invn;
+  s.mu = b.mu;
+  s.scale = b.scale;
+  s.rowkey = b.rowkey;
+  s.colkey = b.colkey;
+  s.flat_first = b.flat_first;
+  s.flat_last = b.flat_last;
+  s.flat_blk = b.flat_blk;
+  s.blk_stride = pl.blk_stride;
+  s.counter = b.counter;
+  s.total_units = pl.total_units;
+  s.total_chunks = pl.total_chunks;
+  s.strip = DEFAULT_STRIP;
+
+  const size_t cells = (size_t)kact * (size_t)pl.gstride;
+  const dim3 fb(256), fg(2048);
+  hipLaunchKernelGGL(fill_u64, fg, fb, 0, st, b.rowkey, 0ull, (int64_t)cells);
+  hipLaunchKernelGGL(fill_u64, fg, fb, 0, st, b.colkey, 0ull, (int64_t)cells);
+  hipLaunchKernelGGL(fill_u64, dim3(64), fb, 0, st, reinterpret_cast<unsigned long long*>(b.scale), 0ull,
+                     (int64_t)n_series * kact);
+  hipLaunchKernelGGL(fill_i32, dim3(64), fb, 0, st, b.flat_first, (int32_t)INT_MAX, (int64_t)n_series * kact);
+  hipLaunchKernelGGL(fill_i32, dim3(64), fb, 0, st, b.flat_last, (int32_t)-1, (int64_t)n_series * kact);
+  hipLaunchKernelGGL(fill_i32, fg, fb, 0, st, b.flat_blk, (int32_t)INT_MAX, (int64_t)kact * pl.blk_stride);
+  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(b.counter), 0, (int64_t)64);
+  SKMP_CHECK_HIP(hipGetLastError());
+
+  const dim3 cg((unsigned)pl.total_chunks);
+  hipLaunchKernelGGL(scale_kernel, cg, fb, 0, st, s);
+  hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1), st, s);
+  SKMP_CHECK_HIP(hipGetLastError());
+
+  if (pl.total_units > 0) {
+    const void* kfn = reinterpret_cast<const void*>(&sj_fp64_kernel<FP64_C, FP64_TL>);
+    const int grid = (int)std::min<int64_t>(grid_for(kfn, 64, 0), pl.total_units);
+    hipLaunchKernelGGL((sj_fp64_kernel<FP64_C, FP64_TL>), dim3(grid), dim3(64), 0, st, s);
+    SKMP_CHECK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
+  SKMP_CHECK_HIP(hipGetLastError());
+  (void)refresh;
+  return SKMP_OK;
+}

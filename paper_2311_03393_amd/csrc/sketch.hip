@@ -1,0 +1,456 @@
+// Normalise + sketch (paper Section III-A, Algorithm 1) and the add/delete
+// dimension update (Section III-C).
+//
+// Two streaming passes over T, both coalesced along time:
+//   dimstats:  per (series, dimension) mean and population sigma.  Each block
+//              reduces one 64K-sample chunk with a shifted sum (shift = the
+//              chunk's first value); chunk partials (n, mean, M2) are merged in
+//              order with Chan's pairwise update.
+//   project:   one thread per time column walks the d dimensions, normalises
+//              each value and accumulates k sketch rows in FP64:
+//              R[g][t] = sum_j S[g][j] * (T[j][t] - mu_j) / sigma_j.
+// The coefficient matrix S is drawn on the host (integer hashing and glibc
+// libm) and copied to the workspace; it is a pure function of (kind, k, seed,
+// dimension id), so an update regenerates exactly the columns it needs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "skmp_common.hpp"
+
+namespace skmp {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+// ------------------------------------------------------- coefficient draw
+static inline uint64_t splitmix64_output(uint64_t state, uint64_t i) {
+  uint64_t z = state + i * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static constexpr uint64_t P61 = (1ull << 61) - 1;
+
+static inline uint64_t mulmod61(uint64_t a, uint64_t x) {
+  unsigned __int128 p = (unsigned __int128)a * x;
+  uint64_t lo = (uint64_t)(p & P61), hi = (uint64_t)(p >> 61);
+  uint64_t s = lo + hi;  // 2^61 = 1 (mod p)
+  s = (s & P61) + (s >> 61);
+  if (s >= P61) s -= P61;
+  return s;
+}
+
+int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S) {
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(d >= 1, "d must be >= 1");
+  SKMP_REQUIRE(S != nullptr, "S is NULL");
+  SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
+  SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
+  for (int64_t j = 0; j < d; ++j) {
+    int64_t id = ids ? ids[j] : j;
+    SKMP_REQUIRE(id >= 0 && (uint64_t)id < P61, "dimension ids must lie in [0, 2^61 - 1)");
+  }
+  std::memset(S, 0, sizeof(double) * (size_t)k * (size_t)d);
+  if (kind == SKMP_SUM) {
+    for (int64_t j = 0; j < d; ++j) S[j] = 1.0;
+    return SKMP_OK;
+  }
+  if (kind == SKMP_COUNT) {
+    uint64_t a = 1 + splitmix64_output(seed, 1) % (P61 - 1);
+    uint64_t b = splitmix64_output(seed, 2) % P61;
+    uint64_t a2 = 1 + splitmix64_output(seed, 3) % (P61 - 1);
+    uint64_t b2 = splitmix64_output(seed, 4) % P61;
+    for (int64_t j = 0; j < d; ++j) {
+      uint64_t id = (uint64_t)(ids ? ids[j] : j);
+      uint64_t hv = mulmod61(a, id) + b;
+      if (hv >= P61) hv -= P61;
+      uint64_t sv = mulmod61(a2, id) + b2;
+      if (sv >= P61) sv -= P61;
+      int g = (int)(hv % (uint64_t)k);
+      S[(int64_t)g * d + j] = (sv & 1) ? -1.0 : 1.0;
+    }
+    return SKMP_OK;
+  }
+  const double two_pi = 2.0 * M_PI;
+  for (int64_t j = 0; j < d; ++j) {
+    uint64_t id = (uint64_t)(ids ? ids[j] : j);
+    for (int g = 0; g < k; ++g) {
+      uint64_t c = 2 * (id * 64 + (uint64_t)g);
+      uint64_t o1 = splitmix64_output(seed, c + 1), o2 = splitmix64_output(seed, c + 2);
+      double u1 = (double)((o1 >> 11) + 1) * 0x1.0p-53;
+      double u2 = (double)(o2 >> 11) * 0x1.0p-53;
+      S[(int64_t)g * d + j] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+    }
+  }
+  return SKMP_OK;
+}
+
+// ------------------------------------------------------------- kernels
+constexpr int STAT_CHUNK = 1 << 16;
+constexpr int STAT_THREADS = 256;
+
+__global__ void fill_u32(unsigned int* p, unsigned int v, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+struct StatPartial {
+  double n, mean, m2, maxabs;
+};
+
+template <typename TIn>
+__global__ __launch_bounds__(STAT_THREADS) void dimstats_partial(const TIn* __restrict__ T, int64_t ldt, int64_t d,
+                                                                 const int64_t* __restrict__ offsets,
+                                                                 const int64_t* __restrict__ cprefix, int n_series,
+                                                                 StatPartial* __restrict__ part,
+                                                                 unsigned int* __restrict__ nonfinite) {
+  const int64_t total_chunks = cprefix[n_series];
+  const int64_t bid = blockIdx.x;
+  const int64_t j = bid / total_chunks;
+  const int64_t c = bid - j * total_chunks;
+  // series of chunk c
+  int lo = 0, hi = n_series - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cprefix[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int s = lo;
+  const int64_t a = offsets[s] + (c - cprefix[s]) * (int64_t)STAT_CHUNK;
+  const int64_t b = min(a + (int64_t)STAT_CHUNK, offsets[s + 1]);
+  const TIn* row = T + j * ldt;
+  const double shift = (double)row[a];
+  double s1 = 0.0, s2 = 0.0, mx = 0.0;
+  unsigned int bad = 0;
+  for (int64_t t = a + threadIdx.x; t < b; t += STAT_THREADS) {
+    double x = (double)row[t];
+    bad += isfinite(x) ? 0u : 1u;
+    double e = x - shift;
+    s1 += e;
+    s2 = fma(e, e, s2);
+    mx = fmax(mx, fabs(x));
+  }
+  __shared__ double sh1[STAT_THREADS / 64], sh2[STAT_THREADS / 64], shm[STAT_THREADS / 64];
+  __shared__ unsigned int shb[STAT_THREADS / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off);
+    s2 += __shfl_down(s2, off);
+    mx = fmax(mx, __shfl_down(mx, off));
+    bad += __shfl_down(bad, off);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh1[w] = s1;
+    sh2[w] = s2;
+    shm[w] = mx;
+    shb[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = 0.0, t2 = 0.0, tm = 0.0;
+    unsigned int tb = 0;
+    for (int q = 0; q < STAT_THREADS / 64; ++q) {
+      t1 += sh1[q];
+      t2 += sh2[q];
+      tm = fmax(tm, shm[q]);
+      tb += shb[q];
+    }
+    double cnt = (double)(b - a);
+    StatPartial p;
+    p.n = cnt;
+    p.mean = shift + t1 / cnt;
+    p.m2 = fmax(t2 - t1 * (t1 / cnt), 0.0);
+    p.maxabs = tm;
+    part[bid] = p;
+    if (tb && nonfinite) atomicAdd(nonfinite, tb);
+  }
+}
+
+__global__ void dimstats_finalize(const StatPartial* __restrict__ part, const int64_t* __restrict__ cprefix,
+                                  int n_series, int64_t d, double* __restrict__ stats) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (s, j)
+  if (idx >= (int64_t)n_series * d) return;
+  const int s = (int)(idx / d);
+  const int64_t j = idx - (int64_t)s * d;
+  const int64_t total_chunks = cprefix[n_series];
+  double n = 0.0, mean = 0.0, m2 = 0.0, mx = 0.0;
+  for (int64_t c = cprefix[s]; c < cprefix[s + 1]; ++c) {
+    StatPartial p = part[j * total_chunks + c];
+    double nn = n + p.n;
+    double delta = p.mean - mean;
+    mean += delta * (p.n / nn);
+    m2 += p.m2 + delta * delta * (n * p.n / nn);
+    n = nn;
+    mx = fmax(mx, p.maxabs);
+  }
+  double sd = sqrt(m2 / n);
+  // a dimension whose sigma is negligible against its magnitude is constant
+  if (sd <= FLAT_REL * mx) sd = 0.0;
+  stats[idx * 2 + 0] = mean;
+  stats[idx * 2 + 1] = sd;
+}
+
+// mode: 0 store, +1 accumulate, -1 subtract
+template <typename TIn, int KB>
+__global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T, int64_t ldt, int64_t d, int64_t N,
+                                                      const int64_t* __restrict__ offsets, int n_series,
+                                                      const double* __restrict__ stats, const double* __restrict__ S,
+                                                      int k, double* __restrict__ R, int64_t ldr, int mode) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  int lo = 0, hi = n_series - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const double* st = stats + (int64_t)lo * d * 2;
+  double acc[KB];
+#pragma unroll
+  for (int g = 0; g < KB; ++g) acc[g] = 0.0;
+  for (int64_t j = 0; j < d; ++j) {
+    const double x = (double)T[j * ldt + t];
+    const double mu = st[2 * j], sd = st[2 * j + 1];
+    const double xb = sd > 0.0 ? (x - mu) / sd : 0.0;
+#pragma unroll
+    for (int g = 0; g < KB; ++g)
+      if (g < k) acc[g] = fma(S[(int64_t)g * d + j], xb, acc[g]);
+  }
+#pragma unroll
+  for (int g = 0; g < KB; ++g) {
+    if (g < k) {
+      double* dst = R + (int64_t)g * ldr + t;
+      if (mode == 0) *dst = acc[g];
+      else if (mode > 0) *dst += acc[g];
+      else *dst -= acc[g];
+    }
+  }
+}
+
+template <typename TIn>
+static void launch_project(const void* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
+                           const double* stats, const double* S, int k, double* R, int64_t ldr, int mode,
+                           hipStream_t st) {
+  dim3 grid((unsigned)((N + 255) / 256)), block(256);
+  const TIn* Tp = static_cast<const TIn*>(T);
+#define SKMP_PROJ(KB) \
+  hipLaunchKernelGGL((project_kernel<TIn, KB>), grid, block, 0, st, Tp, ldt, d, N, offsets, n_series, stats, S, k, R, ldr, mode)
+  if (k <= 1) SKMP_PROJ(1);
+  else if (k <= 4) SKMP_PROJ(4);
+  else if (k <= 8) SKMP_PROJ(8);
+  else if (k <= 16) SKMP_PROJ(16);
+  else if (k <= 32) SKMP_PROJ(32);
+  else SKMP_PROJ(64);
+#undef SKMP_PROJ
+}
+
+// Per-dimension statistics of the columns [offsets[s], offsets[s+1]) of every series.
+struct StatsBuffers {
+  int64_t* offsets_dev;
+  int64_t* cprefix_dev;
+  StatPartial* part;
+  unsigned int* nonfinite;
+};
+
+static size_t stats_workspace(int64_t d, int64_t n_series, int64_t total_chunks, Carve& cv, StatsBuffers* out) {
+  StatsBuffers b;
+  b.offsets_dev = cv.take<int64_t>(n_series + 1);
+  b.cprefix_dev = cv.take<int64_t>(n_series + 1);
+  b.part = cv.take<StatPartial>((size_t)d * (size_t)total_chunks);
+  b.nonfinite = cv.take<unsigned int>(64);
+  if (out) *out = b;
+  return cv.used;
+}
+
+static int run_dimstats(const void* T, int32_t dtype, int64_t ldt, int64_t d, int64_t n_series,
+                        const int64_t* offsets_host, const std::vector<int64_t>& cpre, const StatsBuffers& b,
+                        double* stats_out, bool check, hipStream_t st) {
+  SKMP_CHECK_HIP(hipMemcpyAsync(b.offsets_dev, offsets_host, sizeof(int64_t) * (n_series + 1), hipMemcpyHostToDevice, st));
+  SKMP_CHECK_HIP(hipMemcpyAsync(b.cprefix_dev, cpre.data(), sizeof(int64_t) * (n_series + 1), hipMemcpyHostToDevice, st));
+  if (check) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, st, b.nonfinite, 0u, (int64_t)1);
+  const int64_t total_chunks = cpre[n_series];
+  dim3 grid((unsigned)(d * total_chunks)), block(STAT_THREADS);
+  if (dtype == SKMP_F64)
+    hipLaunchKernelGGL(dimstats_partial<double>, grid, block, 0, st, static_cast<const double*>(T), ldt, d,
+                       b.offsets_dev, b.cprefix_dev, (int)n_series, b.part, check ? b.nonfinite : nullptr);
+  else
+    hipLaunchKernelGGL(dimstats_partial<float>, grid, block, 0, st, static_cast<const float*>(T), ldt, d,
+                       b.offsets_dev, b.cprefix_dev, (int)n_series, b.part, check ? b.nonfinite : nullptr);
+  const int64_t pairs = n_series * d;
+  hipLaunchKernelGGL(dimstats_finalize, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, b.part,
+                     b.cprefix_dev, (int)n_series, d, stats_out);
+  SKMP_CHECK_HIP(hipGetLastError());
+  if (check) {
+    unsigned int bad = 0;
+    SKMP_CHECK_HIP(hipMemcpyAsync(&bad, b.nonfinite, sizeof(bad), hipMemcpyDeviceToHost, st));
+    SKMP_CHECK_HIP(hipStreamSynchronize(st));
+    if (bad) {
+      set_error("input contains " + std::to_string(bad) + " non-finite values");
+      return SKMP_ENONFINITE;
+    }
+  }
+  return SKMP_OK;
+}
+
+static std::vector<int64_t> chunk_prefix(int64_t n_series, const int64_t* offsets) {
+  std::vector<int64_t> cpre(n_series + 1, 0);
+  for (int64_t s = 0; s < n_series; ++s) {
+    int64_t L = offsets[s + 1] - offsets[s];
+    cpre[s + 1] = cpre[s] + (L + STAT_CHUNK - 1) / STAT_CHUNK;
+  }
+  return cpre;
+}
+
+}  // namespace skmp
+
+using namespace skmp;
+
+extern "C" const char* skmp_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* skmp_version(void) { return "sketchmp 0.1 (gfx950)"; }
+
+extern "C" int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64_t* dim_ids, int64_t d,
+                             double* S_host) {
+  clear_error();
+  return launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S_host);
+}
+
+extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int64_t* offsets, int32_t k) {
+  if (d < 1 || n_series < 1 || !offsets || k < 1) return 0;
+  std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)k * (size_t)d);
+  stats_workspace(d, n_series, cpre[n_series], cv, nullptr);
+  return cv.used + 256;
+}
+
+extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt, int64_t n_series,
+                            const int64_t* offsets, const int64_t* dim_ids, int32_t k, int32_t kind, uint64_t seed,
+                            uint32_t flags, double* R, int64_t ldr, double* dim_stats, void* workspace,
+                            size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(T && R && dim_stats && offsets, "null pointer argument");
+  SKMP_REQUIRE(dtype == SKMP_F64 || dtype == SKMP_F32, "dtype must be SKMP_F64 or SKMP_F32");
+  SKMP_REQUIRE(d >= 1, "d must be >= 1");
+  SKMP_REQUIRE(n_series >= 1, "n_series must be >= 1");
+  SKMP_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
+  for (int64_t s = 0; s < n_series; ++s)
+    SKMP_REQUIRE(offsets[s + 1] > offsets[s], "every series needs at least one sample (offsets strictly increasing)");
+  const int64_t N = offsets[n_series];
+  SKMP_REQUIRE(ldt >= N && ldr >= N, "row strides must be >= the total number of samples");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  std::vector<double> S((size_t)k * (size_t)d);
+  int rc = launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S.data());
+  if (rc) return rc;
+  std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
+  Carve cv(workspace, ws_bytes);
+  double* S_dev = cv.take<double>((size_t)k * (size_t)d);
+  StatsBuffers sb;
+  stats_workspace(d, n_series, cpre[n_series], cv, &sb);
+  if (!workspace || !cv.fits()) {
+    set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
+    return SKMP_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SKMP_CHECK_HIP(hipMemcpyAsync(S_dev, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, st));
+  rc = run_dimstats(T, dtype, ldt, d, n_series, offsets, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
+  if (rc) return rc;
+  if (dtype == SKMP_F64)
+    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, S_dev, k, R, ldr, 0, st);
+  else
+    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, S_dev, k, R, ldr, 0, st);
+  SKMP_CHECK_HIP(hipGetLastError());
+  return SKMP_OK;
+}
+
+extern "C" size_t sketch_update_workspace(int64_t n, int64_t d_add, int64_t d_rem, int32_t k) {
+  if (n < 1 || k < 1 || d_add < 0 || d_rem < 0) return 0;
+  int64_t offs[2] = {0, n};
+  std::vector<int64_t> cpre = chunk_prefix(1, offs);
+  Carve cv(nullptr, 0);
+  cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_add, 1));
+  cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_rem, 1));
+  stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, nullptr);
+  return cv.used + 256;
+}
+
+extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, int32_t kind, uint64_t seed,
+                                  int32_t dtype, int64_t ldt, const void* T_add, int64_t d_add,
+                                  const int64_t* add_ids, double* add_stats, const void* T_rem, int64_t d_rem,
+                                  const int64_t* rem_ids, const double* rem_stats, uint32_t flags,
+                                  uint64_t* changed_groups, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(R != nullptr, "R is NULL");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(n >= 1 && ldr >= n && ldt >= n, "bad length or strides");
+  SKMP_REQUIRE(dtype == SKMP_F64 || dtype == SKMP_F32, "dtype must be SKMP_F64 or SKMP_F32");
+  SKMP_REQUIRE(d_add >= 0 && d_rem >= 0, "negative dimension count");
+  SKMP_REQUIRE(d_add == 0 || (T_add && add_ids && add_stats), "added dimensions need T_add, add_ids and add_stats");
+  SKMP_REQUIRE(d_rem == 0 || (T_rem && rem_ids && rem_stats), "removed dimensions need T_rem, rem_ids and rem_stats");
+  for (int64_t a = 0; a < d_add; ++a)
+    for (int64_t b = 0; b < d_rem; ++b)
+      SKMP_REQUIRE(add_ids[a] != rem_ids[b], "a dimension id is both added and removed");
+  for (int64_t a = 0; a < d_add; ++a)
+    for (int64_t b = a + 1; b < d_add; ++b) SKMP_REQUIRE(add_ids[a] != add_ids[b], "duplicate added dimension id");
+  for (int64_t a = 0; a < d_rem; ++a)
+    for (int64_t b = a + 1; b < d_rem; ++b) SKMP_REQUIRE(rem_ids[a] != rem_ids[b], "duplicate removed dimension id");
+  std::vector<double> Sa((size_t)k * (size_t)std::max<int64_t>(d_add, 1)),
+      Sr((size_t)k * (size_t)std::max<int64_t>(d_rem, 1));
+  int rc;
+  if (d_add) {
+    rc = launch_sketch_coeffs_host(kind, k, seed, add_ids, d_add, Sa.data());
+    if (rc) return rc;
+  }
+  if (d_rem) {
+    rc = launch_sketch_coeffs_host(kind, k, seed, rem_ids, d_rem, Sr.data());
+    if (rc) return rc;
+  }
+  if (!d_add && !d_rem) {
+    if (changed_groups) *changed_groups = 0;
+    return SKMP_OK;
+  }
+  int64_t offs[2] = {0, n};
+  std::vector<int64_t> cpre = chunk_prefix(1, offs);
+  Carve cv(workspace, ws_bytes);
+  double* Sa_dev = cv.take<double>(Sa.size());
+  double* Sr_dev = cv.take<double>(Sr.size());
+  StatsBuffers sb;
+  stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, &sb);
+  if (!workspace || !cv.fits()) {
+    set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
+    return SKMP_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t mask = 0;
+  if (d_add) {
+    SKMP_CHECK_HIP(hipMemcpyAsync(Sa_dev, Sa.data(), sizeof(double) * Sa.size(), hipMemcpyHostToDevice, st));
+    rc = run_dimstats(T_add, dtype, ldt, d_add, 1, offs, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
+    if (rc) return rc;
+    if (dtype == SKMP_F64)
+      launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, Sa_dev, k, R, ldr, +1, st);
+    else
+      launch_project<float>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, Sa_dev, k, R, ldr, +1, st);
+    for (int g = 0; g < k; ++g)
+      for (int64_t j = 0; j < d_add; ++j)
+        if (Sa[(size_t)g * d_add + j] != 0.0) mask |= 1ull << g;
+  }
+  if (d_rem) {
+    SKMP_CHECK_HIP(hipMemcpyAsync(Sr_dev, Sr.data(), sizeof(double) * Sr.size(), hipMemcpyHostToDevice, st));
+    if (!d_add)
+      SKMP_CHECK_HIP(hipMemcpyAsync(sb.offsets_dev, offs, sizeof(offs), hipMemcpyHostToDevice, st));
+    if (dtype == SKMP_F64)
+      launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, Sr_dev, k, R, ldr, -1, st);
+    else
+      launch_project<float>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, Sr_dev, k, R, ldr, -1, st);
+    for (int g = 0; g < k; ++g)
+      for (int64_t j = 0; j < d_rem; ++j)
+        if (Sr[(size_t)g * d_rem + j] != 0.0) mask |= 1ull << g;
+  }
+  SKMP_CHECK_HIP(hipGetLastError());
+  if (changed_groups) *changed_groups = mask;
+  return SKMP_OK;
+}

@@ -1,0 +1,116 @@
+// Internal definitions shared by the HIP translation units of libsketchmp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/sketchmp.h"
+
+namespace skmp {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define SKMP_CHECK_HIP(expr)                                                              \
+  do {                                                                                    \
+    hipError_t e__ = (expr);                                                              \
+    if (e__ != hipSuccess) {                                                              \
+      ::skmp::set_error(std::string(#expr) + ": " + hipGetErrorString(e__));              \
+      return SKMP_EDEVICE;                                                                \
+    }                                                                                     \
+  } while (0)
+
+#define SKMP_REQUIRE(cond, msg)         \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::skmp::set_error(msg);           \
+      return SKMP_EINVAL;               \
+    }                                   \
+  } while (0)
+
+// -------------------------------------------------------------- constants
+// Padding of the per-window statistics arrays: rows may run 64 below 0 (the
+// skewed tile start) and up to PADR past n_sub (diagonal ends and tile overshoot).
+constexpr int PADL = 64;
+constexpr int PADR = 2048;
+constexpr double FLAT_REL = 1e-10;
+
+// ------------------------------------------------------------ workspace
+// Bump allocator over the caller's workspace; every region 256-byte aligned.
+struct Carve {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carve(void* p, size_t c) : base(static_cast<char*>(p)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return reinterpret_cast<T*>(base ? base + off : nullptr);
+  }
+  bool fits() const { return used <= cap; }
+};
+
+// -------------------------------------------------------------- plan
+// One entry per series, device resident (built on the host, copied once per call).
+struct SeriesPlan {
+  int64_t col;         // first column of the series in T / R / P / I
+  int64_t n;           // samples
+  int64_t n_sub;       // n - m + 1
+  int64_t stat_base;   // index of x = -PADL of this series inside one group's stats row
+  int64_t unit_base;   // first self-join work unit of this series
+  int64_t chunk_base;  // first 256-element chunk of this series (elementwise kernels)
+  int64_t blk_base;    // first 256-window block (flat-index summaries)
+  int32_t nb;          // diagonal bands
+  int32_t ns;          // strips per band (grid, some empty)
+};
+
+struct GroupList {
+  int32_t count;
+  int8_t g[64];
+};
+
+// Shared by the self-join kernels (both precisions).
+struct SJState {
+  const double* R;
+  int64_t ldr;
+  const SeriesPlan* plan;
+  int32_t n_series;
+  int32_t m;
+  int32_t excl;
+  int32_t key_bits;     // global key: low key_bits of the double hold (2^key_bits - 1 - delta)
+  int64_t gstride;      // stride between groups in the stats arrays
+  GroupList groups;
+  double2* dfdg;        // (df, dg) per window, padded
+  double* invn;         // 1 / (sqrt(m) sigma), 0 if flat, NaN in the padding
+  double* mu;           // window mean
+  double* scale;        // per (series, group slot): max |r|
+  unsigned long long* rowkey;  // best key of row i among partners j > i
+  unsigned long long* colkey;  // best key of column j among partners i < j
+  int32_t* flat_first;  // per (series, group slot): smallest flat window index (INT_MAX if none)
+  int32_t* flat_last;   // largest flat window index (-1 if none)
+  int32_t* flat_blk;    // per 256-window block: smallest flat index in the block (INT_MAX if none)
+  int64_t blk_stride;   // stride between groups in flat_blk
+  unsigned int* counter;  // persistent work-queue head
+  int64_t total_units;
+  int64_t total_chunks;
+  int32_t strip;        // steps per strip
+};
+
+__device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series, int64_t key,
+                                           int64_t SeriesPlan::*field) {
+  int lo = 0, hi = n_series - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (plan[mid].*field <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// -------------------------------------------------------- host helpers
+int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S);
+
+}  // namespace skmp

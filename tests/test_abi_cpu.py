@@ -1,0 +1,108 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol,
+draws the same coefficients as the oracle, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2311_03393_amd as skmp
+from oracle import sketchmp_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sketchmp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(skmp.LIB_PATH):
+        from paper_2311_03393_amd import build
+        build.build()
+    return skmp.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 11
+    assert set(names) == set(skmp.EXPORTED)
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert "gfx950" in skmp.version()
+
+
+@pytest.mark.parametrize("kind,k", [("sum", 1), ("count", 5), ("count", 64), ("gauss", 3), ("gauss", 16)])
+def test_coefficients_match_oracle_bit_for_bit(L, kind, k):
+    ids = np.array([0, 1, 2, 7, 100, 12345, 2 ** 40 + 3, 999999937])
+    S_lib = skmp.sketch_coeffs(kind, k, 2001, ids)
+    S_ora = O.sketch_coeffs(kind, k, ids, 2001)
+    assert np.array_equal(S_lib, S_ora)
+
+
+def test_coefficient_argument_errors(L):
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_coeffs("sum", 2, 0, [0, 1])
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_coeffs("count", 0, 0, [0, 1])
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_coeffs("gauss", 65, 0, [0, 1])
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_coeffs("count", 4, 0, [-1])
+
+
+def _offs(*xs):
+    a = np.array(xs, dtype=np.int64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def test_workspace_queries(L):
+    a, p = _offs(0, 1000, 5000)
+    assert L.mp_selfjoin_workspace(2, p, 4, 64, 0) > 0
+    assert L.mp_selfjoin_workspace(2, p, 0, 64, 0) == 0
+    assert L.top_discords_workspace(2, p, 4, 64) > 0
+    assert L.sketch_build_workspace(8, 2, p, 4) > 0
+    assert L.sketch_update_workspace(1000, 3, 2, 4) > 0
+    big, pb = _offs(0, 1 << 20)
+    assert L.mp_selfjoin_workspace(1, pb, 32, 256, 0) > L.mp_selfjoin_workspace(1, p, 32, 256, 0)
+
+
+def test_selfjoin_rejects_bad_arguments_before_launch(L):
+    a, p = _offs(0, 100, 300)
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(256)
+    cases = [
+        dict(k=0, m=16, excl=4),     # k out of range
+        dict(k=65, m=16, excl=4),
+        dict(k=2, m=3, excl=1),      # m < 4
+        dict(k=2, m=16, excl=0),     # excl < 1
+        dict(k=2, m=150, excl=4),    # first series shorter than m
+    ]
+    for c in cases:
+        rc = L.mp_selfjoin(fake, 300, 2, p, c["k"], c["m"], c["excl"], 0, 0, ~0 & ((1 << 64) - 1), fake, fake, 300,
+                           ws, 1 << 30, None)
+        assert rc == -1, c
+        assert L.skmp_last_error()
+    bad, pbad = _offs(0, 300, 100)   # decreasing offsets
+    assert L.mp_selfjoin(fake, 300, 2, pbad, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 1 << 30, None) == -1
+    assert L.mp_selfjoin(fake, 100, 2, p, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 1 << 30, None) == -1  # ldr < N
+    assert L.mp_selfjoin(fake, 300, 2, p, 2, 16, 4, 7, 0, 1, fake, fake, 300, ws, 1 << 30, None) == -1  # prec
+    assert L.mp_selfjoin(fake, 300, 2, p, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 16, None) == -2     # workspace
+
+
+def test_build_and_discords_reject_bad_arguments(L):
+    a, p = _offs(0, 100)
+    fake = ctypes.c_void_p(16)
+    assert L.sketch_build(fake, 0, 4, 100, 1, p, None, 0, 1, 0, 0, fake, 100, fake, fake, 1 << 20, None) == -1
+    assert L.sketch_build(fake, 0, 4, 100, 1, p, None, 2, 0, 0, 0, fake, 100, fake, fake, 1 << 20, None) == -1
+    assert L.sketch_build(fake, 5, 4, 100, 1, p, None, 2, 1, 0, 0, fake, 100, fake, fake, 1 << 20, None) == -1
+    assert L.sketch_build(fake, 0, 4, 50, 1, p, None, 2, 1, 0, 0, fake, 100, fake, fake, 1 << 20, None) == -1
+    assert L.top_discords(fake, 100, 1, p, 2, 16, 0, 0, fake, fake, fake, fake, fake, 1 << 20, None) == -1
+    ids = np.array([3, 3], dtype=np.int64)
+    assert L.sketch_update_dims(fake, 100, 100, 2, 1, 0, 0, 100, fake, 2, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                fake, None, 0, None, None, 0, None, fake, 1 << 20, None) == -1  # duplicate id

@@ -1,0 +1,358 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Profiles are compared element by element at sizes the oracle finishes in
+seconds (several tiles, bands and strips, ragged tails); at the full
+water-treatment size rows are sampled and the top-10 discords are certified
+exactly from the GPU's witnesses.  FP64 tolerance: 1e-9 * 2 sqrt(m) on P (or
+the squared-distance form near P = 0).  Neighbour indices must be admissible
+and attain the oracle's nearest-neighbour distance; where several neighbours
+are equally near, any of them is accepted.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+from oracle import sketchmp_oracle as O
+from tests.helpers import check_neighbours, discords_equivalent, fp64_tol, profile_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    import paper_2311_03393_amd as skmp
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    skmp.lib()
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _to_dev(torch, T, dev):
+    return torch.from_numpy(np.ascontiguousarray(T)).to(dev)
+
+
+def _run_selfjoin(torch, dev, R_np, offsets, k, m, excl, prec="fp64"):
+    import paper_2311_03393_amd as skmp
+    R = _to_dev(torch, R_np, dev)
+    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), I.cpu().numpy()
+
+
+# ------------------------------------------------------------------ sketch
+@pytest.mark.parametrize("case", ["c0", "c1_small", "count", "batch_f32"])
+def test_sketch_build_parity(dev, case):
+    import torch
+    import paper_2311_03393_amd as skmp
+    _say("sketch parity", case)
+    if case == "c0":
+        w = datagen.make("c0")
+    elif case == "c1_small":
+        w = datagen.make("c1", scale=0.1)
+    elif case == "count":
+        w = datagen.make("c0")
+        w.kind, w.k = "count", 3
+    else:
+        w = datagen.make("c3", scale=0.05, n_series=6)
+    T = _to_dev(torch, w.T, dev)
+    R, stats = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
+    torch.cuda.synchronize()
+    R, stats = R.cpu().numpy(), stats.cpu().numpy()
+    for s in range(w.n_series):
+        a, b = w.offsets[s], w.offsets[s + 1]
+        R_o, S_o, mu_o, sd_o = O.build(w.T[:, a:b].astype(np.float64), w.kind, w.k, w.sketch_seed, w.dim_ids)
+        scale = max(1.0, float(np.max(np.abs(R_o))))
+        assert np.max(np.abs(R[:, a:b] - R_o)) <= 1e-12 * scale
+        assert np.allclose(stats[s, :, 0], mu_o, rtol=1e-13, atol=1e-12)
+        assert np.allclose(stats[s, :, 1], sd_o, rtol=1e-12, atol=0)
+
+
+def test_sketch_constant_dimension_and_nonfinite(dev):
+    import torch
+    import paper_2311_03393_amd as skmp
+    T = datagen.tiny_series(11, 4, 500)
+    T[2] = 0.1
+    R, stats = skmp.sketch_build(_to_dev(torch, T, dev), [0, 500], 2, "gauss", 5)
+    torch.cuda.synchronize()
+    R_o, _, mu_o, sd_o = O.build(T, "gauss", 2, 5)
+    assert stats[0, 2, 1].item() == 0.0 and sd_o[2] == 0.0
+    assert np.max(np.abs(R.cpu().numpy() - R_o)) < 1e-12 * np.max(np.abs(R_o))
+    T[1, 17] = np.nan
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_build(_to_dev(torch, T, dev), [0, 500], 2, "gauss", 5, check_finite=True)
+
+
+# --------------------------------------------------------------- self-join
+SMALL = [  # (n, m, excl, k, seed)
+    (300, 16, 4, 2, 1),
+    (777, 8, 2, 1, 2),
+    (1500, 32, 8, 3, 3),
+    (4100, 64, 16, 2, 4),      # several bands (512 diagonals each) and strips
+    (2600, 100, 25, 1, 5),
+    (700, 4, 1, 1, 6),         # smallest m, excl = 1
+    (530, 64, 470, 1, 7),      # excl close to n_sub: few admissible pairs, rows without partners
+]
+
+
+@pytest.mark.parametrize("n,m,excl,k,seed", SMALL)
+def test_selfjoin_fp64_matches_oracle(dev, c_oracle, n, m, excl, k, seed):
+    import torch
+    _say("selfjoin fp64", n, m, excl, k, seed)
+    T = datagen.tiny_series(seed, 5, n)
+    R_np, _, _, _ = O.build(T, "gauss", k, seed)
+    P, I = _run_selfjoin(torch, dev, R_np, [0, n], k, m, excl)
+    n_sub = n - m + 1
+    tol = fp64_tol(m)
+    for g in range(k):
+        P_o, I_o = c_oracle.profile(R_np[g], m, excl)
+        ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
+        assert ok.all(), f"group {g}: {np.count_nonzero(~ok)} rows out of tolerance, max err {err}"
+        check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
+        assert np.all(np.isnan(P[g, n_sub:])) and np.all(I[g, n_sub:] == -2)  # tail untouched
+
+
+def test_selfjoin_c0_and_top10(dev, c_oracle):
+    import torch
+    import paper_2311_03393_amd as skmp
+    w = datagen.make("c0")
+    R_np, _, _, _ = O.build(w.T, w.kind, w.k, w.sketch_seed)
+    R = _to_dev(torch, R_np, dev)
+    P, I = skmp.mp_selfjoin(R, w.offsets, w.k, w.m, w.excl)
+    idx, grp, score, nf = skmp.top_discords(P, w.offsets, w.k, w.m, 10)
+    torch.cuda.synchronize()
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    P_o, I_o = c_oracle.profile(R_np[0], w.m, w.excl)
+    n_sub = len(P_o)
+    ok, err = profile_close(P[0, :n_sub], P_o, w.m, fp64_tol(w.m))
+    assert ok.all(), err
+    top_o = O.top_discords(P_o[None], w.m, 10)
+    gpu = [(int(i), int(g), float(s)) for i, g, s in zip(idx[0].cpu(), grp[0].cpu(), score[0].cpu())]
+    assert int(nf[0]) == 10
+    assert [i for i, _, _ in gpu] == [i for i, _, _ in top_o]
+    (_, _, o, _), = w.planted
+    assert abs(gpu[0][0] - o) <= w.m // 2
+
+
+def test_selfjoin_flat_windows_and_exclusion_boundary(dev, c_oracle):
+    import torch
+    rng = np.random.default_rng(12)
+    m, excl = 16, 4
+    r = rng.standard_normal(3000).cumsum()
+    r[400:460] = 2.0            # long flat stretch
+    r[1500:1516] = -7.0         # single flat window
+    r[2000:2016] = 3.0 * r[1000:1016] + 5.0   # exact repeat far away: P = 0
+    R_np = r[None, :]
+    P, I = _run_selfjoin(torch, dev, R_np, [0, r.size], 1, m, excl)
+    P_o, I_o = c_oracle.profile(r, m, excl)
+    n_sub = len(P_o)
+    ok, err = profile_close(P[0, :n_sub], P_o, m, fp64_tol(m))
+    assert ok.all(), (np.nonzero(~ok)[0][:10], err)
+    flat = np.arange(400, 460 - m + 1)
+    assert np.all(P[0, flat] == 0.0) and np.array_equal(I[0, flat], I_o[flat])
+    assert P[0, 1500] == math.sqrt(m)
+    assert P[0, 1000] < 1e-5 and I[0, 1000] == 2000
+    check_neighbours(c_oracle, r, m, excl, np.arange(n_sub), I[0, :n_sub], P_o, fp64_tol(m))
+
+
+def test_selfjoin_batched_uneven_series(dev, c_oracle):
+    import torch
+    m, excl, k = 32, 8, 2
+    lens = [40, 700, 33, 2500, 1200, 64, 5000]     # includes n_sub < excl + 1 (no admissible pair)
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    T = np.concatenate([datagen.tiny_series(100 + q, 3, L) for q, L in enumerate(lens)], axis=1)
+    R_np = np.zeros((k, offsets[-1]))
+    for s in range(len(lens)):
+        a, b = offsets[s], offsets[s + 1]
+        R_np[:, a:b], _, _, _ = O.build(T[:, a:b], "gauss", k, 77)
+    P, I = _run_selfjoin(torch, dev, R_np, offsets, k, m, excl)
+    for s in range(len(lens)):
+        a, b = offsets[s], offsets[s + 1]
+        n_sub = b - a - m + 1
+        for g in range(k):
+            P_o, I_o = c_oracle.profile(R_np[g, a:b], m, excl)
+            ok, err = profile_close(P[g, a:a + n_sub], P_o, m, fp64_tol(m))
+            assert ok.all(), (s, g, err)
+            check_neighbours(c_oracle, R_np[g, a:b], m, excl, np.arange(n_sub), I[g, a:a + n_sub], P_o, fp64_tol(m))
+
+
+def test_selfjoin_group_mask_and_repeatability(dev):
+    import torch
+    import paper_2311_03393_amd as skmp
+    T = datagen.tiny_series(21, 6, 3000)
+    R_np, _, _, _ = O.build(T, "gauss", 4, 3)
+    R = _to_dev(torch, R_np, dev)
+    P1, I1 = skmp.mp_selfjoin(R, [0, 3000], 4, 48, 12)
+    P2, I2 = skmp.mp_selfjoin(R, [0, 3000], 4, 48, 12)
+    P3, I3 = skmp.mp_selfjoin(R, [0, 3000], 4, 48, 12, group_mask=0b0101)
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2) and torch.equal(I1, I2)        # deterministic
+    assert torch.equal(P3[0], P1[0]) and torch.equal(P3[2], P1[2])
+    assert torch.isnan(P3[1]).all() and torch.isnan(P3[3]).all()   # untouched groups
+
+
+def test_top_discords_matches_oracle_on_same_profiles(dev):
+    import torch
+    import paper_2311_03393_amd as skmp
+    rng = np.random.default_rng(5)
+    k, m = 3, 10
+    lens = [300, 80, 1000]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    P = np.full((k, offsets[-1]), np.nan)
+    for s, L in enumerate(lens):
+        a = offsets[s]
+        n_sub = L - m + 1
+        x = np.round(rng.random((k, n_sub)) * 20) / 4     # many exact ties
+        x[rng.random((k, n_sub)) < 0.05] = np.inf           # rows without partners
+        P[:, a:a + n_sub] = x
+    idx, grp, score, nf = skmp.top_discords(_to_dev(torch, P, dev), offsets, k, m, 12)
+    torch.cuda.synchronize()
+    for s, L in enumerate(lens):
+        a = offsets[s]
+        n_sub = L - m + 1
+        ref = O.top_discords(P[:, a:a + n_sub], m, 12)
+        got = [(int(i), int(g), float(v)) for i, g, v in zip(idx[s].cpu(), grp[s].cpu(), score[s].cpu())][:len(ref)]
+        assert int(nf[s]) == len(ref)
+        assert got == ref
+
+
+# ------------------------------------------------------------------ update
+def test_update_dims_matches_rebuild(dev, c_oracle):
+    import torch
+    import paper_2311_03393_amd as skmp
+    w = datagen.make("c4", scale=1.0 / 256)           # d = 256, n = 4096, same recipe as the large case
+    n = w.T.shape[1]
+    ids = w.dim_ids
+    rem = w.update["rem_ids"]
+    T_add = w.update["T_add"]
+    add_ids = w.update["add_ids"]
+    T = _to_dev(torch, w.T, dev)
+    R, stats = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=ids)
+    rem_stats = stats[0, rem].contiguous()
+    add_stats, mask = skmp.sketch_update_dims(R, w.kind, w.k, w.sketch_seed, T_add=_to_dev(torch, T_add, dev),
+                                              add_ids=add_ids, T_rem=T[rem].contiguous(), rem_ids=rem,
+                                              rem_stats=rem_stats)
+    torch.cuda.synchronize()
+    keep = np.setdiff1d(ids, rem)
+    R_ref, _, mu_a, sd_a = O.build(np.concatenate([w.T[keep], T_add]), w.kind, w.k, w.sketch_seed,
+                                   np.concatenate([keep, add_ids]))
+    Rg = R.cpu().numpy()
+    assert np.max(np.abs(Rg - R_ref)) <= 1e-11 * np.max(np.abs(R_ref))
+    assert mask == (1 << w.k) - 1
+    assert np.allclose(add_stats.cpu().numpy()[:, 1], sd_a[-len(add_ids):], rtol=1e-12)
+    # the profile of the updated sketch equals the profile of a fresh build
+    P_u, I_u = skmp.mp_selfjoin(R, w.offsets, w.k, w.m, w.excl, group_mask=0b11)
+    torch.cuda.synchronize()
+    for g in range(2):
+        P_o, _ = c_oracle.profile(R_ref[g], w.m, w.excl)
+        ok, err = profile_close(P_u[g].cpu().numpy()[:len(P_o)], P_o, w.m, 1e-8 * 2 * math.sqrt(w.m))
+        assert ok.all(), err
+
+
+def test_update_count_sketch_changed_groups(dev):
+    import torch
+    import paper_2311_03393_amd as skmp
+    T = datagen.tiny_series(31, 12, 800)
+    ids = np.arange(12)
+    R, stats = skmp.sketch_build(_to_dev(torch, T, dev), [0, 800], 5, "count", 9, dim_ids=ids)
+    Tn = datagen.tiny_series(32, 2, 800)
+    _, mask = skmp.sketch_update_dims(R, "count", 5, 9, T_add=_to_dev(torch, Tn, dev), add_ids=[40, 41])
+    expect = 0
+    for i in (40, 41):
+        expect |= 1 << O.count_hash(9, i, 5)[0]
+    assert mask == expect
+    torch.cuda.synchronize()
+    R_ref, _, _, _ = O.build(np.concatenate([T, Tn]), "count", 5, 9, np.concatenate([ids, [40, 41]]))
+    assert np.max(np.abs(R.cpu().numpy() - R_ref)) < 1e-12 * np.max(np.abs(R_ref))
+
+
+# -------------------------------------------------- full water-treatment size
+def _certified_top(c_oracle, R_np, m, excl, P_gpu, I_gpu, top_k):
+    """Exact greedy top-K without a full oracle profile.
+
+    U_g[i] = d(i, I_gpu[g, i]) is an upper bound of the exact P_g[i].  Rows are
+    taken in descending max_g U; their exact profiles are computed until every
+    greedy pick on exact values beats the largest bound of the rows not yet
+    computed.  Returns (top list, A_exact dict, U matrix).
+    """
+    k, n_sub = P_gpu.shape
+    rows = np.arange(n_sub)
+    U = np.stack([c_oracle.pair_dist(R_np[g], m, rows, I_gpu[g]) for g in range(k)])
+    U = np.where(I_gpu >= 0, U, -np.inf)
+    AU = U.max(axis=0)
+    order = np.argsort(-AU, kind="stable")
+    exact = {}
+    batch = 64
+    pos = 0
+    while True:
+        new = order[pos:pos + batch]
+        pos += len(new)
+        Pn = np.stack([c_oracle.profile(R_np[g], m, excl, rows=new)[0] for g in range(k)])
+        for q, i in enumerate(new):
+            col = Pn[:, q]
+            col = np.where(np.isfinite(col), col, -np.inf)
+            exact[int(i)] = (float(col.max()), int(np.argmax(col)))
+        tau_rows = order[pos:]
+        alive = np.ones(n_sub, bool)
+        picks = []
+        certified = True
+        for _ in range(top_k):
+            cand = [(v, i) for i, (v, g) in exact.items() if alive[i] and v > -np.inf]
+            if not cand:
+                break
+            v, i = max(cand, key=lambda t: (t[0], -t[1]))
+            rest = tau_rows[alive[tau_rows]]
+            tau = AU[rest].max() if rest.size else -np.inf
+            if tau >= v:
+                certified = False
+                break
+            picks.append((i, exact[i][1], v))
+            alive[max(0, i - m + 1):min(n_sub, i + m)] = False
+        if certified or pos >= n_sub:
+            return picks, exact, U
+
+
+def test_selfjoin_c1_full_size_sampled_and_certified(dev, c_oracle):
+    import torch
+    import paper_2311_03393_amd as skmp
+    w = datagen.make("c1")
+    _say("c1 full size", w.T.shape)
+    T = _to_dev(torch, w.T, dev)
+    R, _ = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
+    P, I = skmp.mp_selfjoin(R, w.offsets, w.k, w.m, w.excl)
+    idx, grp, score, nf = skmp.top_discords(P, w.offsets, w.k, w.m, 10)
+    torch.cuda.synchronize()
+    R_np = R.cpu().numpy()
+    R_o, _, _, _ = O.build(w.T, w.kind, w.k, w.sketch_seed, w.dim_ids)
+    assert np.max(np.abs(R_np - R_o)) <= 1e-12 * np.max(np.abs(R_o))
+    n_sub = w.T.shape[1] - w.m + 1
+    P, I = P.cpu().numpy()[:, :n_sub], I.cpu().numpy()[:, :n_sub]
+    tol = fp64_tol(w.m)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.choice(n_sub, 96, replace=False), [0, 1, n_sub - 2, n_sub - 1],
+                                     [o + q for (_, _, o, _) in w.planted for q in (-5, 0, 5)]]))
+    for g in range(w.k):
+        P_o, _ = c_oracle.profile(R_np[g], w.m, w.excl, rows=rows)
+        ok, err = profile_close(P[g, rows], P_o, w.m, tol)
+        assert ok.all(), (g, err)
+        check_neighbours(c_oracle, R_np[g], w.m, w.excl, rows, I[g, rows], P_o, tol)
+    picks, exact, U = _certified_top(c_oracle, R_np, w.m, w.excl, P, I, 10)
+    # the GPU's reported distance is the exact distance of its reported neighbour
+    fin = np.isfinite(P)
+    assert np.max(np.abs(P[fin] - U[fin])) < 1e-9
+    gpu = [(int(i), int(g), float(s)) for i, g, s in zip(idx[0].cpu(), grp[0].cpu(), score[0].cpu())]
+    A_ex = np.full(n_sub, -np.inf)
+    for i, (v, g) in exact.items():
+        A_ex[i] = v
+    if [i for i, _, _ in gpu] != [i for i, _, _ in picks]:
+        # near ties: accept an eps-greedy sequence on the exact values
+        for (i, g, s), (io, go, so) in zip(gpu, picks):
+            assert i in exact and exact[i][0] >= so - 2 * tol
+    _say("c1 top10", [i for i, _, _ in gpu])
