@@ -103,6 +103,11 @@ def _torch():
     return torch
 
 
+def _ld(t) -> int:
+    """Row stride of a 2-D tensor; a single-row tensor may carry any stride."""
+    return int(t.shape[1]) if t.shape[0] == 1 else int(t.stride(0))
+
+
 def _stream(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -144,9 +149,9 @@ def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_f
     stats = torch.empty((n_series, d, 2), dtype=torch.float64, device=T.device)
     ws_n = lib().sketch_build_workspace(d, n_series, _ptr64(offs), k)
     ws = _workspace(torch, ws_n, T.device)
-    _check(lib().sketch_build(T.data_ptr(), dtype, d, T.stride(0), n_series, _ptr64(offs),
+    _check(lib().sketch_build(T.data_ptr(), dtype, d, _ld(T), n_series, _ptr64(offs),
                               None if ids is None else _ptr64(ids), k, KINDS[kind], seed,
-                              FLAG_CHECK_FINITE if check_finite else 0, R.data_ptr(), R.stride(0), stats.data_ptr(),
+                              FLAG_CHECK_FINITE if check_finite else 0, R.data_ptr(), _ld(R), stats.data_ptr(),
                               ws.data_ptr(), ws.numel(), _stream(torch)))
     return R, stats
 
@@ -161,14 +166,14 @@ def sketch_update_dims(R, kind: str, k: int, seed: int, T_add=None, add_ids=(), 
     d_add, d_rem = add_ids.size, rem_ids.size
     ref = T_add if d_add else T_rem
     dtype = F64 if (ref is None or ref.dtype == torch.float64) else F32
-    ldt = ref.stride(0) if ref is not None else n
+    ldt = _ld(ref) if ref is not None else n
     if d_add and d_rem:
-        assert T_add.dtype == T_rem.dtype and T_add.stride(0) == T_rem.stride(0)
+        assert T_add.dtype == T_rem.dtype and _ld(T_add) == _ld(T_rem)
     add_stats = torch.empty((max(d_add, 1), 2), dtype=torch.float64, device=R.device)
     mask = ctypes.c_uint64(0)
     ws_n = lib().sketch_update_workspace(n, d_add, d_rem, k)
     ws = _workspace(torch, ws_n, R.device)
-    _check(lib().sketch_update_dims(R.data_ptr(), R.stride(0), n, k, KINDS[kind], seed, dtype, ldt,
+    _check(lib().sketch_update_dims(R.data_ptr(), _ld(R), n, k, KINDS[kind], seed, dtype, ldt,
                                     T_add.data_ptr() if d_add else None, d_add, _ptr64(add_ids),
                                     add_stats.data_ptr() if d_add else None,
                                     T_rem.data_ptr() if d_rem else None, d_rem, _ptr64(rem_ids),
@@ -194,13 +199,13 @@ def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refre
         P = torch.full((k, N), float("nan"), dtype=torch.float64, device=R.device)
     if I is None:
         I = torch.full((k, N), -2, dtype=torch.int64, device=R.device)
-    assert P.stride(0) == I.stride(0)
+    assert _ld(P) == _ld(I)
     if workspace is None:
         ws_n = lib().mp_selfjoin_workspace(n_series, _ptr64(offs), k, m, PRECISIONS[prec])
         workspace = _workspace(torch, ws_n, R.device)
     mask = (1 << 64) - 1 if group_mask is None else int(group_mask)
-    _check(lib().mp_selfjoin(R.data_ptr(), R.stride(0), n_series, _ptr64(offs), k, m, excl, PRECISIONS[prec],
-                             refresh, mask, P.data_ptr(), I.data_ptr(), P.stride(0), workspace.data_ptr(),
+    _check(lib().mp_selfjoin(R.data_ptr(), _ld(R), n_series, _ptr64(offs), k, m, excl, PRECISIONS[prec],
+                             refresh, mask, P.data_ptr(), I.data_ptr(), _ld(P), workspace.data_ptr(),
                              workspace.numel(), _stream(torch)))
     return P, I
 
@@ -216,7 +221,7 @@ def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0):
     nf = torch.empty((n_series,), dtype=torch.int32, device=P.device)
     ws_n = lib().top_discords_workspace(n_series, _ptr64(offs), k, m)
     ws = _workspace(torch, ws_n, P.device)
-    _check(lib().top_discords(P.data_ptr(), P.stride(0), n_series, _ptr64(offs), k, m, top_k, halfwidth,
+    _check(lib().top_discords(P.data_ptr(), _ld(P), n_series, _ptr64(offs), k, m, top_k, halfwidth,
                               idx.data_ptr(), grp.data_ptr(), score.data_ptr(), nf.data_ptr(), ws.data_ptr(),
                               ws.numel(), _stream(torch)))
     return idx, grp, score, nf

@@ -87,6 +87,8 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   }
   __syncthreads();
   const int64_t x = c.x0 + threadIdx.x;
+  // the chunk grid rounds each group's padded range up to 256: stay inside it
+  if (x >= sp.n_sub + PADR) return;
   const int64_t sidx = (int64_t)c.gi * st.gstride + sp.stat_base + PADL + x;
   if (x < 0 || x >= sp.n_sub) {
     st.dfdg[sidx] = make_double2(0.0, 0.0);

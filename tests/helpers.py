@@ -26,8 +26,9 @@ def profile_close(P_gpu, P_ora, m: int, tol: float):
     inf_g, inf_o = ~np.isfinite(P_gpu), ~np.isfinite(P_ora)
     ok = inf_g == inf_o
     fin = ~inf_g & ~inf_o
-    d = np.abs(P_gpu - P_ora)
-    d2 = np.abs(P_gpu ** 2 - P_ora ** 2)
+    with np.errstate(invalid="ignore"):
+        d = np.abs(P_gpu - P_ora)
+        d2 = np.abs(P_gpu ** 2 - P_ora ** 2)
     ok_f = (d <= tol) | (d2 <= 2.0 * math.sqrt(m) * tol)
     ok = ok & np.where(fin, ok_f, True)
     err = float(np.max(np.where(fin, d, 0.0))) if fin.any() else 0.0
