@@ -171,6 +171,21 @@ int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* 
                  int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group, double* score, int32_t* n_found,
                  void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Stage timing.  When enabled, each launch of a timed stage is bracketed by HIP
+ * events recorded on the stream the stage runs on; skmp_timing_read waits for
+ * those events and returns the summed device time (ms) and the number of timed
+ * launches since the last reset.  Timers:
+ */
+#define SKMP_TIMER_SKETCH 0     /* dimstats + projection of sketch_build */
+#define SKMP_TIMER_SUBSTATS 1   /* scale + window statistics of mp_selfjoin */
+#define SKMP_TIMER_TILES 2      /* the self-join tile kernel (FP64 or mixed) */
+#define SKMP_TIMER_MERGE 3      /* key merge + FP64 polish */
+#define SKMP_TIMER_DISCORDS 4   /* top_discords */
+#define SKMP_TIMER_COUNT 5
+int skmp_timing_enable(int on);
+int skmp_timing_read(int32_t which, int32_t reset, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

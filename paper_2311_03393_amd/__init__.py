@@ -36,7 +36,8 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 # every symbol include/sketchmp.h declares
 EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
-            "top_discords_workspace", "top_discords")
+            "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
+TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4}
 
 
 class SketchMPError(RuntimeError):
@@ -79,6 +80,8 @@ def lib():
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
                                    _vp]
+        L.skmp_timing_enable.argtypes = [ctypes.c_int]
+        L.skmp_timing_read.argtypes = [_i32, _i32, _dp, _i64p]
         _lib = L
     return _lib
 
@@ -124,6 +127,19 @@ def _workspace(torch, nbytes: int, device):
     return buf
 
 
+def timing_enable(on: bool = True) -> None:
+    """Record HIP events around every timed stage launch (see include/sketchmp.h)."""
+    _check(lib().skmp_timing_enable(1 if on else 0))
+
+
+def timing_read(stage: str, reset: bool = True):
+    """(summed device milliseconds, launches) of a stage since the last reset."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().skmp_timing_read(TIMERS[stage], 1 if reset else 0, ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
+
+
 def version() -> str:
     return lib().skmp_version().decode()
 
@@ -136,7 +152,8 @@ def sketch_coeffs(kind: str, k: int, seed: int, dim_ids: Sequence[int]) -> np.nd
     return S
 
 
-def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_finite: bool = False):
+def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_finite: bool = False, R=None,
+                 stats=None):
     """Normalise every dimension per series and sketch: returns (R k x N, dim_stats n_series x d x 2)."""
     torch = _torch()
     assert T.is_cuda and T.dim() == 2 and T.stride(1) == 1
@@ -145,8 +162,10 @@ def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_f
     offs = _i64arr(offsets)
     n_series = offs.size - 1
     ids = None if dim_ids is None else _i64arr(dim_ids)
-    R = torch.empty((k, N), dtype=torch.float64, device=T.device)
-    stats = torch.empty((n_series, d, 2), dtype=torch.float64, device=T.device)
+    if R is None:
+        R = torch.empty((k, N), dtype=torch.float64, device=T.device)
+    if stats is None:
+        stats = torch.empty((n_series, d, 2), dtype=torch.float64, device=T.device)
     ws_n = lib().sketch_build_workspace(d, n_series, _ptr64(offs), k)
     ws = _workspace(torch, ws_n, T.device)
     _check(lib().sketch_build(T.data_ptr(), dtype, d, _ld(T), n_series, _ptr64(offs),
@@ -210,15 +229,18 @@ def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refre
     return P, I
 
 
-def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0):
+def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0, out=None):
     """Ordered non-overlapping discords per series: (idx, group, score, n_found) device tensors."""
     torch = _torch()
     offs = _i64arr(offsets)
     n_series = offs.size - 1
-    idx = torch.empty((n_series, top_k), dtype=torch.int64, device=P.device)
-    grp = torch.empty((n_series, top_k), dtype=torch.int32, device=P.device)
-    score = torch.empty((n_series, top_k), dtype=torch.float64, device=P.device)
-    nf = torch.empty((n_series,), dtype=torch.int32, device=P.device)
+    if out is None:
+        idx = torch.empty((n_series, top_k), dtype=torch.int64, device=P.device)
+        grp = torch.empty((n_series, top_k), dtype=torch.int32, device=P.device)
+        score = torch.empty((n_series, top_k), dtype=torch.float64, device=P.device)
+        nf = torch.empty((n_series,), dtype=torch.int32, device=P.device)
+    else:
+        idx, grp, score, nf = out
     ws_n = lib().top_discords_workspace(n_series, _ptr64(offs), k, m)
     ws = _workspace(torch, ws_n, P.device)
     _check(lib().top_discords(P.data_ptr(), _ld(P), n_series, _ptr64(offs), k, m, top_k, halfwidth,

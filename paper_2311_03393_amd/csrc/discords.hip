@@ -4,10 +4,9 @@
 //   combine:  A[i] = max over groups of P[g][i] with the first group kept on
 //             ties (Algorithm 2 replaces its best only on a strictly larger
 //             score); non-finite scores (no admissible neighbour) are dropped.
-//   pick x K: each series is split into 64K-window chunks; one block per chunk
-//             finds the first maximum of A among windows not masked by earlier
-//             picks, then one block per series reduces the chunk winners and
-//             appends the pick.  A pick masks |i - i*| < halfwidth.
+//   select:   one 1024-thread block per series runs all K greedy passes: each
+//             pass takes the first maximum of A among windows not masked by
+//             earlier picks (kept in LDS); a pick masks |i - i*| < halfwidth.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -73,100 +72,70 @@ __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__
   G[t] = bg;
 }
 
-__device__ __forceinline__ void block_argmax(double& v, int64_t& i) {
-  __shared__ double sv[DISC_THREADS / 64];
-  __shared__ int64_t si[DISC_THREADS / 64];
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_down(v, off);
-    const int64_t oi = __shfl_down(i, off);
-    if (better(ov, oi, v, i)) {
-      v = ov;
-      i = oi;
-    }
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    sv[w] = v;
-    si[w] = i;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < DISC_THREADS / 64; ++q)
-      if (better(sv[q], si[q], v, i)) {
-        v = sv[q];
-        i = si[q];
-      }
-  }
-}
+constexpr int SEL_THREADS = 1024;
+constexpr int MAX_TOPK = 256;
 
-__global__ __launch_bounds__(DISC_THREADS) void chunk_pick_kernel(DiscState st, int pass) {
-  const int64_t chunk = blockIdx.x;
-  int lo = 0, hi = st.n_series - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (st.ser[mid].chunk_base <= chunk) lo = mid; else hi = mid - 1;
-  }
-  const DiscSeries sr = st.ser[lo];
-  const int64_t a = (chunk - sr.chunk_base) * DISC_CHUNK;
-  const int64_t b = min(a + (int64_t)DISC_CHUNK, sr.n_sub);
-  const int64_t* picks = st.idx + (int64_t)lo * st.top_k;
-  double v = -INFINITY;
-  int64_t bi = INT64_MAX;
-  for (int64_t i = a + threadIdx.x; i < b; i += DISC_THREADS) {
-    const double x = st.A[sr.col + i];
-    if (!(x > -INFINITY)) continue;
-    bool masked = false;
-    for (int q = 0; q < pass; ++q) {
-      const int64_t p = picks[q];
-      if (p >= 0 && (i - p < st.halfwidth) && (p - i < st.halfwidth)) masked = true;
-    }
-    if (!masked && better(x, i, v, bi)) {
-      v = x;
-      bi = i;
-    }
-  }
-  block_argmax(v, bi);
-  if (threadIdx.x == 0) {
-    st.cand_val[chunk] = v;
-    st.cand_idx[chunk] = bi;
-  }
-}
-
-__global__ __launch_bounds__(64) void series_pick_kernel(DiscState st, int pass) {
+__global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
+  __shared__ int64_t picks[MAX_TOPK];
+  __shared__ double wv[SEL_THREADS / 64];
+  __shared__ int64_t wi[SEL_THREADS / 64];
   const int s = blockIdx.x;
   const DiscSeries sr = st.ser[s];
-  const int64_t nch = (sr.n_sub + DISC_CHUNK - 1) / DISC_CHUNK;
-  double v = -INFINITY;
-  int64_t bi = INT64_MAX;
-  for (int64_t c = threadIdx.x; c < nch; c += 64) {
-    const double x = st.cand_val[sr.chunk_base + c];
-    const int64_t i = st.cand_idx[sr.chunk_base + c];
-    if (x > -INFINITY && better(x, i, v, bi)) {
-      v = x;
-      bi = i;
+  const double* A = st.A + sr.col;
+  const int64_t h = st.halfwidth;
+  int found = 0;
+  for (int pass = 0; pass < st.top_k; ++pass) {
+    double v = -INFINITY;
+    int64_t bi = INT64_MAX;
+    for (int64_t i = threadIdx.x; i < sr.n_sub; i += SEL_THREADS) {
+      const double x = A[i];
+      if (!(x > -INFINITY) || !better(x, i, v, bi)) continue;
+      bool masked = false;
+      for (int q = 0; q < pass; ++q) {
+        const int64_t p = picks[q];
+        masked |= (i - p < h) && (p - i < h);
+      }
+      if (!masked) {
+        v = x;
+        bi = i;
+      }
     }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_down(v, off);
-    const int64_t oi = __shfl_down(bi, off);
-    if (better(ov, oi, v, bi)) {
-      v = ov;
-      bi = oi;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(v, off);
+      const int64_t oi = __shfl_down(bi, off);
+      if (better(ov, oi, v, bi)) {
+        v = ov;
+        bi = oi;
+      }
     }
-  }
-  if (threadIdx.x == 0) {
-    const int64_t o = (int64_t)s * st.top_k + pass;
-    if (v > -INFINITY) {
-      st.idx[o] = bi;
-      st.group[o] = st.G[sr.col + bi];
-      st.score[o] = v;
-      st.n_found[s] = pass + 1;
-    } else {
-      st.idx[o] = -1;
-      st.group[o] = -1;
-      st.score[o] = __longlong_as_double(0x7FF8000000000000ll);
+    if ((threadIdx.x & 63) == 0) {
+      wv[threadIdx.x >> 6] = v;
+      wi[threadIdx.x >> 6] = bi;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < SEL_THREADS / 64; ++q)
+        if (better(wv[q], wi[q], v, bi)) {
+          v = wv[q];
+          bi = wi[q];
+        }
+      const int64_t o = (int64_t)s * st.top_k + pass;
+      if (v > -INFINITY) {
+        st.idx[o] = bi;
+        st.group[o] = st.G[sr.col + bi];
+        st.score[o] = v;
+        picks[pass] = bi;
+      } else {
+        picks[pass] = INT64_MIN / 2;  // nothing left: masks nothing
+      }
+      wv[0] = v;
+    }
+    __syncthreads();
+    if (!(wv[0] > -INFINITY)) break;
+    found = pass + 1;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) st.n_found[s] = found;
 }
 
 __global__ void init_outputs(DiscState st) {
@@ -220,7 +189,7 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
   SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
   SKMP_REQUIRE(m >= 1, "m must be >= 1");
-  SKMP_REQUIRE(top_k >= 1 && top_k <= 4096, "top_k must lie in [1, 4096]");
+  SKMP_REQUIRE(top_k >= 1 && top_k <= MAX_TOPK, "top_k must lie in [1, 256]");
   SKMP_REQUIRE(halfwidth >= 0, "halfwidth must be >= 0");
   SKMP_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
   for (int64_t s = 0; s < n_series; ++s) SKMP_REQUIRE(offsets[s + 1] >= offsets[s], "offsets must be non-decreasing");
@@ -250,15 +219,13 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   }
   hipStream_t stream_ = static_cast<hipStream_t>(stream);
   SKMP_CHECK_HIP(hipMemcpyAsync(ser, ds.data(), sizeof(DiscSeries) * n_series, hipMemcpyHostToDevice, stream_));
+  StageTimer tm(SKMP_TIMER_DISCORDS, stream_);
   const int64_t outs = std::max<int64_t>(n_series * top_k, n_series);
   hipLaunchKernelGGL(init_outputs, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream_, st);
   if (N > 0)
     hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream_, P, ldp, k, ser,
                        (int)n_series, N, st.A, st.G);
-  for (int pass = 0; pass < top_k; ++pass) {
-    hipLaunchKernelGGL(chunk_pick_kernel, dim3((unsigned)chunks), dim3(DISC_THREADS), 0, stream_, st, pass);
-    hipLaunchKernelGGL(series_pick_kernel, dim3((unsigned)n_series), dim3(64), 0, stream_, st, pass);
-  }
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), 0, stream_, st);
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }

@@ -55,7 +55,7 @@ __device__ __forceinline__ ChunkPos decode_chunk(const SJState& st, int64_t chun
   ChunkPos c;
   c.s = find_series(st.plan, st.n_series, chunk, &SeriesPlan::chunk_base);
   const SeriesPlan& sp = st.plan[c.s];
-  const int64_t per_group = (sp.n_sub + PADL + PADR + 255) / 256;
+  const int64_t per_group = (sp.lpad + 255) / 256;
   const int64_t local = chunk - sp.chunk_base;
   c.gi = (int)(local / per_group);
   c.x0 = (local - (int64_t)c.gi * per_group) * 256 - PADL;
@@ -88,12 +88,18 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   __syncthreads();
   const int64_t x = c.x0 + threadIdx.x;
   // the chunk grid rounds each group's padded range up to 256: stay inside it
-  if (x >= sp.n_sub + PADR) return;
-  const int64_t sidx = (int64_t)c.gi * st.gstride + sp.stat_base + PADL + x;
+  if (x >= sp.lpad - PADL) return;
+  const int64_t gbase = (int64_t)c.gi * st.gstride + sp.stat_base;
+  const int64_t sidx = gbase + PADL + x;
+  const int64_t xp = x + PADL;
+  const int64_t tidx = gbase + (xp % CSTRIDE) * (sp.lpad / CSTRIDE) + xp / CSTRIDE;
   if (x < 0 || x >= sp.n_sub) {
+    const double qnan = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
     st.dfdg[sidx] = make_double2(0.0, 0.0);
-    st.invn[sidx] = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
+    st.invn[sidx] = qnan;
     st.mu[sidx] = 0.0;
+    st.cdfdg[tidx] = make_double2(0.0, 0.0);
+    st.cinvn[tidx] = qnan;
     return;
   }
   const double* w = sh_r + threadIdx.x;
@@ -117,9 +123,12 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     df = 0.5 * (w[m] - w[0]);
     dg = (w[m] - mu1) + (w[0] - mu);
   }
+  const double iv = flat ? 0.0 : 1.0 / (sd * sqrt((double)m));
   st.dfdg[sidx] = make_double2(df, dg);
-  st.invn[sidx] = flat ? 0.0 : 1.0 / (sd * sqrt((double)m));
+  st.invn[sidx] = iv;
   st.mu[sidx] = mu;
+  st.cdfdg[tidx] = make_double2(df, dg);
+  st.cinvn[tidx] = iv;
   if (flat) {
     const int64_t sg = (int64_t)c.s * st.groups.count + c.gi;
     atomicMin(st.flat_first + sg, (int32_t)x);
@@ -152,24 +161,56 @@ struct LaneState {
   double colacc[C];
 };
 
+// Statistics of the row and of the newly entering column, fetched one step ahead.
+struct StepLoad {
+  double2 rs;    // (df, dg) of row i
+  double rinv;   // invn of row i
+  double2 cs;    // (df, dg) of the column entering the window
+  double cinv;
+};
+
+// Column jn = U + CSTRIDE * t lives at plane (U + PADL) mod CSTRIDE, slot
+// (U + PADL) div CSTRIDE + t of the de-interleaved arrays (U uniform).
+struct ColAddr {
+  const double2* cdfdg;  // de-interleaved arrays of this (series, group)
+  const double* cinvn;
+  int plane;             // lpad / CSTRIDE
+};
+
+__device__ __forceinline__ StepLoad load_step(const double2* __restrict__ dfdg, const double* __restrict__ invn,
+                                              const ColAddr& ca, int i, int U, int t) {
+  StepLoad l;
+  l.rs = dfdg[i];
+  l.rinv = invn[i];
+  const int up = U + PADL;
+  const int off = (up % CSTRIDE) * ca.plane + up / CSTRIDE + t;
+  l.cs = ca.cdfdg[off];
+  l.cinv = ca.cinvn[off];
+  return l;
+}
+
+// Runs ngroups * C steps.  On entry ``cur`` holds the loads of the first step;
+// on exit it holds the loads of the step after the last one.
 template <int C, bool EDGE>
-__device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, const uint32_t (&code)[C], uint32_t keep, int ngroups,
-                                              int row0, int jbase, const double2* __restrict__ dfdg,
-                                              const double* __restrict__ invn, unsigned long long* rowk,
+__device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad& cur, const uint32_t (&code)[C],
+                                              uint32_t keep, int ngroups, int row0, int ubase,
+                                              const double2* __restrict__ dfdg, const double* __restrict__ invn,
+                                              const ColAddr& ca, unsigned long long* rowk,
                                               unsigned long long* colk, int t) {
+  static_assert(C - 1 == CSTRIDE, "lanes' columns must be CSTRIDE apart");
   for (int gidx = 0; gidx < ngroups; ++gidx) {
 #pragma unroll
     for (int p = 0; p < C; ++p) {
       const int us = gidx * C + p;
-      const int i = row0 + us;
-      const double2 rs = dfdg[i];
-      const double rinv = invn[i];
-      const int jn = jbase + us + C - 1;
+      // prefetch the next step while this one computes; its entering column is
+      // ubase + us + C + (C - 1) t, ubase = u0 + db uniform
+      const StepLoad nxt = load_step(dfdg, invn, ca, row0 + us + 1, ubase + us + C, t);
       const int sn = (p + C - 1) % C;
-      const double2 cs = dfdg[jn];
-      ls.cdf[sn] = cs.x;
-      ls.cdg[sn] = cs.y;
-      ls.cinv[sn] = invn[jn];
+      ls.cdf[sn] = cur.cs.x;
+      ls.cdg[sn] = cur.cs.y;
+      ls.cinv[sn] = cur.cinv;
+      const double2 rs = cur.rs;
+      const double rinv = cur.rinv;
       double rowp = 0.0;
 #pragma unroll
       for (int q = 0; q < C; ++q) {
@@ -186,6 +227,7 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, const uint32_t (
       }
       atomicMax(&rowk[us + 63 - t], kbits(rowp));
       atomicMax(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
+      cur = nxt;
     }
   }
 }
@@ -213,7 +255,7 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
   for (;;) {
     unsigned int unit = 0;
     if (t == 0) unit = atomicAdd(st.counter, 1u);
-    unit = __shfl(unit, 0);
+    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
     if ((int64_t)unit >= st.total_units) break;
     const int s = find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base);
     const SeriesPlan sp = st.plan[s];
@@ -239,23 +281,29 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
     unsigned long long* gco = st.colkey + sbase;
 
     LaneState<C> ls;
-    // exact FP64 seeds at the strip start: lane t's first row is u_begin - t
+    // exact FP64 seeds at the strip start: lane t's first row is u_begin - t.
+    // Diagonals that end before that row are computed on clamped (valid)
+    // addresses and zeroed: their cells are all masked.
     {
       const int rr = max(u_begin - t, 0);
       const int j0 = rr + db + t * C;
+      const int nlast = (int)sp.n - 1;
       const double mr = mu[rr];
-#pragma unroll
-      for (int q = 0; q < C; ++q) ls.Cq[q] = 0.0;
       double mj[C];
 #pragma unroll
-      for (int q = 0; q < C; ++q) mj[q] = (j0 + q < n_sub) ? mu[j0 + q] : 0.0;
-      const int nvalid = min(C, max(0, n_sub - j0));
+      for (int q = 0; q < C; ++q) {
+        ls.Cq[q] = 0.0;
+        mj[q] = mu[min(j0 + q, n_sub - 1)];
+      }
+#pragma unroll 4
       for (int x = 0; x < m; ++x) {
         const double a = r[rr + x] - mr;
 #pragma unroll
-        for (int q = 0; q < C; ++q)
-          if (q < nvalid) ls.Cq[q] = fma(a, r[j0 + q + x] - mj[q], ls.Cq[q]);
+        for (int q = 0; q < C; ++q) ls.Cq[q] = fma(a, r[min(j0 + q + x, nlast)] - mj[q], ls.Cq[q]);
       }
+#pragma unroll
+      for (int q = 0; q < C; ++q)
+        if (j0 + q >= n_sub) ls.Cq[q] = 0.0;
     }
     // column window: columns J + q (q < C-1) in slots q, J = u_begin + db + t (C-1)
     {
@@ -270,15 +318,17 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
       }
     }
 
+    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;
+    const ColAddr ca{st.cdfdg + gbase, st.cinvn + gbase, (int)(sp.lpad / CSTRIDE)};
+    StepLoad cur = load_step(dfdg, invn, ca, u_begin - t, u_begin + db + C - 1, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
       const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
       const int row0 = u0 - t;
-      const int jbase = u0 + db + t * (C - 1);
       if (edge)
-        sj_run_groups<C, true>(ls, code, keep, ngroups, row0, jbase, dfdg, invn, rowk, colk, t);
+        sj_run_groups<C, true>(ls, cur, code, keep, ngroups, row0, u0 + db, dfdg, invn, ca, rowk, colk, t);
       else
-        sj_run_groups<C, false>(ls, code, keep, ngroups, row0, jbase, dfdg, invn, rowk, colk, t);
+        sj_run_groups<C, false>(ls, cur, code, keep, ngroups, row0, u0 + db, dfdg, invn, ca, rowk, colk, t);
       const bool last = (u0 + TL >= u_end);
       if (last) {
         // retire the columns still open in the window (phase 0 after full groups)
@@ -287,29 +337,34 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
           atomicMax(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
       }
       __syncthreads();
-      // flush rows [u0 - 63, u0 + TL) and columns [u0 + db, u0 + db + NCOL)
-      for (int xr = t; xr < NROW; xr += 64) {
-        const unsigned long long key = rowk[xr];
-        if (key) {
-          rowk[xr] = 0ull;
-          const int x = u0 - 63 + xr;
-          if (x >= 0 && x < n_sub) {
-            const int delta = db + (int)(LMAX - (uint32_t)(key & LMAX));
-            const unsigned long long gk = (key & ~GMAX) | (GMAX - (unsigned long long)delta);
-            atomicMax(gro + x, gk);
-          }
+      // flush rows [u0 - 63, u0 + TL) and columns [u0 + db, u0 + db + NCOL):
+      // read every partial first, clear LDS, then issue the global atomics
+      constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
+      unsigned long long kr[RPL], kc[CPL];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) kr[q] = (t + 64 * q < NROW) ? rowk[t + 64 * q] : 0ull;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) kc[q] = (t + 64 * q < NCOL) ? colk[t + 64 * q] : 0ull;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (t + 64 * q < NROW) rowk[t + 64 * q] = 0ull;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+        if (t + 64 * q < NCOL) colk[t + 64 * q] = 0ull;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int x = u0 - 63 + t + 64 * q;
+        if (kr[q] && x >= 0 && x < n_sub) {
+          const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
+          atomicMax(gro + x, (kr[q] & ~GMAX) | (GMAX - (unsigned long long)delta));
         }
       }
-      for (int xr = t; xr < NCOL; xr += 64) {
-        const unsigned long long key = colk[xr];
-        if (key) {
-          colk[xr] = 0ull;
-          const int j = u0 + db + xr;
-          if (j < n_sub) {
-            const int delta = db + (int)(LMAX - (uint32_t)(key & LMAX));
-            const unsigned long long gk = (key & ~GMAX) | (GMAX - (unsigned long long)delta);
-            atomicMax(gco + j, gk);
-          }
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int j = u0 + db + t + 64 * q;
+        if (kc[q] && j < n_sub) {
+          const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
+          atomicMax(gco + j, (kc[q] & ~GMAX) | (GMAX - (unsigned long long)delta));
         }
       }
       __syncthreads();
@@ -426,7 +481,8 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.n_sub = std::max<int64_t>(p.n - m + 1, 1);
     max_nsub = std::max(max_nsub, p.n_sub);
     p.stat_base = stat;
-    stat += p.n_sub + PADL + PADR;
+    p.lpad = ((p.n_sub + PADL + PADR + CSTRIDE - 1) / CSTRIDE) * CSTRIDE;
+    stat += p.lpad;
     const int64_t nd = p.n_sub - excl;  // diagonals with admissible pairs
     const int64_t D = 64 * (int64_t)C;
     p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
@@ -434,7 +490,7 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.unit_base = unit;
     unit += (int64_t)p.nb * p.ns * kact;
     p.chunk_base = chunk;
-    chunk += ((p.n_sub + PADL + PADR + 255) / 256) * kact;
+    chunk += ((p.lpad + 255) / 256) * kact;
     p.blk_base = blk;
     blk += (p.n_sub + 255) / 256;
   }
@@ -452,6 +508,8 @@ struct SJBuffers {
   SeriesPlan* plan;
   double2* dfdg;
   double* invn;
+  double2* cdfdg;
+  double* cinvn;
   double* mu;
   unsigned long long* rowkey;
   unsigned long long* colkey;
@@ -467,6 +525,8 @@ static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, 
   b.plan = cv.take<SeriesPlan>(n_series);
   b.dfdg = cv.take<double2>(cells);
   b.invn = cv.take<double>(cells);
+  b.cdfdg = cv.take<double2>(cells);
+  b.cinvn = cv.take<double>(cells);
   b.mu = cv.take<double>(cells);
   b.rowkey = cv.take<unsigned long long>(cells);
   b.colkey = cv.take<unsigned long long>(cells);
@@ -563,6 +623,8 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   s.groups = gl;
   s.dfdg = b.dfdg;
   s.invn = b.invn;
+  s.cdfdg = b.cdfdg;
+  s.cinvn = b.cinvn;
   s.mu = b.mu;
   s.scale = b.scale;
   s.rowkey = b.rowkey;
@@ -589,17 +651,24 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   SKMP_CHECK_HIP(hipGetLastError());
 
   const dim3 cg((unsigned)pl.total_chunks);
-  hipLaunchKernelGGL(scale_kernel, cg, fb, 0, st, s);
-  hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1), st, s);
+  {
+    StageTimer tm(SKMP_TIMER_SUBSTATS, st);
+    hipLaunchKernelGGL(scale_kernel, cg, fb, 0, st, s);
+    hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1), st, s);
+  }
   SKMP_CHECK_HIP(hipGetLastError());
 
   if (pl.total_units > 0) {
     const void* kfn = reinterpret_cast<const void*>(&sj_fp64_kernel<FP64_C, FP64_TL>);
     const int grid = (int)std::min<int64_t>(grid_for(kfn, 64, 0), pl.total_units);
+    StageTimer tm(SKMP_TIMER_TILES, st);
     hipLaunchKernelGGL((sj_fp64_kernel<FP64_C, FP64_TL>), dim3(grid), dim3(64), 0, st, s);
-    SKMP_CHECK_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
+  SKMP_CHECK_HIP(hipGetLastError());
+  {
+    StageTimer tm(SKMP_TIMER_MERGE, st);
+    hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
+  }
   SKMP_CHECK_HIP(hipGetLastError());
   (void)refresh;
   return SKMP_OK;

@@ -357,6 +357,7 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   SKMP_CHECK_HIP(hipMemcpyAsync(S_dev, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, st));
+  StageTimer tm(SKMP_TIMER_SKETCH, st);
   rc = run_dimstats(T, dtype, ldt, d, n_series, offsets, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
   if (dtype == SKMP_F64)

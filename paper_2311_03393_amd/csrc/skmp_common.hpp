@@ -37,6 +37,10 @@ void clear_error();
 constexpr int PADL = 64;
 constexpr int PADR = 2048;
 constexpr double FLAT_REL = 1e-10;
+// The column statistics are also stored de-interleaved by CSTRIDE (plane
+// x mod CSTRIDE, slot x div CSTRIDE, for the padded index x + PADL) so that
+// 64 lanes whose columns are CSTRIDE apart read 64 adjacent elements.
+constexpr int CSTRIDE = 7;
 
 // ------------------------------------------------------------ workspace
 // Bump allocator over the caller's workspace; every region 256-byte aligned.
@@ -64,6 +68,7 @@ struct SeriesPlan {
   int64_t unit_base;   // first self-join work unit of this series
   int64_t chunk_base;  // first 256-element chunk of this series (elementwise kernels)
   int64_t blk_base;    // first 256-window block (flat-index summaries)
+  int64_t lpad;        // padded windows per group: round_up(n_sub + PADL + PADR, CSTRIDE)
   int32_t nb;          // diagonal bands
   int32_t ns;          // strips per band (grid, some empty)
 };
@@ -86,6 +91,8 @@ struct SJState {
   GroupList groups;
   double2* dfdg;        // (df, dg) per window, padded
   double* invn;         // 1 / (sqrt(m) sigma), 0 if flat, NaN in the padding
+  double2* cdfdg;       // dfdg de-interleaved by CSTRIDE
+  double* cinvn;        // invn de-interleaved by CSTRIDE
   double* mu;           // window mean
   double* scale;        // per (series, group slot): max |r|
   unsigned long long* rowkey;  // best key of row i among partners j > i
@@ -109,6 +116,23 @@ __device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series,
   }
   return lo;
 }
+
+// ---------------------------------------------------------------- timing
+// Brackets the launches issued during its lifetime with HIP events on ``st``
+// when timing is enabled (skmp_timing_enable); a no-op otherwise.
+class StageTimer {
+ public:
+  StageTimer(int which, hipStream_t st);
+  ~StageTimer();
+  StageTimer(const StageTimer&) = delete;
+  StageTimer& operator=(const StageTimer&) = delete;
+
+ private:
+  int which_;
+  hipStream_t st_;
+  hipEvent_t a_{}, b_{};
+  bool live_ = false;
+};
 
 // -------------------------------------------------------- host helpers
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S);
