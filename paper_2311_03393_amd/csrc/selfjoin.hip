@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   const int64_t gbase = (int64_t)c.gi * st.gstride + sp.stat_base;
   const int64_t sidx = gbase + PADL + x;
   const int64_t xp = x + PADL;
-  const int64_t tidx = gbase + (xp % CSTRIDE) * (sp.lpad / CSTRIDE) + xp / CSTRIDE;
+  const int64_t tidx = gbase + (xp % st.cstride) * (sp.lpad / st.cstride) + xp / st.cstride;
   if (x < 0 || x >= sp.n_sub) {
     const double qnan = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
     st.dfdg[sidx] = make_double2(0.0, 0.0);
@@ -154,6 +155,15 @@ __device__ __forceinline__ double embed(double x, uint32_t keep, uint32_t code) 
 
 __device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned long long)__double_as_longlong(k); }
 
+// Values that are the same in every lane but come out of vector loads: make
+// the compiler keep them (and what derives from them) in scalar registers.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int C>
 struct LaneState {
   double Cq[C];
@@ -169,42 +179,68 @@ struct StepLoad {
   double cinv;
 };
 
-// Column jn = U + CSTRIDE * t lives at plane (U + PADL) mod CSTRIDE, slot
-// (U + PADL) div CSTRIDE + t of the de-interleaved arrays (U uniform).
-struct ColAddr {
-  const double2* cdfdg;  // de-interleaved arrays of this (series, group)
-  const double* cinvn;
-  int plane;             // lpad / CSTRIDE
+// Buffer resources over one (series, group)'s padded statistics (element 0 is
+// window -PADL).  Offsets split into a per-lane constant (voffset), a uniform
+// part (soffset, scalar unit) and the step's immediate, so the per-step
+// address arithmetic costs no vector instructions.
+struct StatRsrc {
+  __amdgpu_buffer_rsrc_t rd, ri;  // natural layout: dfdg, invn
+  __amdgpu_buffer_rsrc_t cd, ci;  // de-interleaved by C - 1: cdfdg, cinvn
+  int plane;                      // lpad / (C - 1)
 };
 
-__device__ __forceinline__ StepLoad load_step(const double2* __restrict__ dfdg, const double* __restrict__ invn,
-                                              const ColAddr& ca, int i, int U, int t) {
+constexpr int kBufWord3 = 0x00020000;
+
+template <int C>
+__device__ __forceinline__ StatRsrc make_rsrc(const SJState& st, int64_t gbase, int64_t lpad) {
+  StatRsrc r;
+  r.rd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.dfdg + gbase), 0, (int)(lpad * 16), kBufWord3);
+  r.ri = __builtin_amdgcn_make_buffer_rsrc((void*)(st.invn + gbase), 0, (int)(lpad * 8), kBufWord3);
+  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cdfdg + gbase), 0, (int)(lpad * 16), kBufWord3);
+  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cinvn + gbase), 0, (int)(lpad * 8), kBufWord3);
+  r.plane = (int)(lpad / (C - 1));
+  return r;
+}
+
+// Loads for the step whose rows are u - t and whose entering column is
+// U + (C - 1) t (U = u + db + C - 1, uniform): rows from the natural layout at
+// element u - t + PADL = (u + PADL - 63) + (63 - t); the column from plane
+// (U + PADL) mod (C - 1), slot (U + PADL) div (C - 1) + t.
+template <int C>
+__device__ __forceinline__ StepLoad load_step(const StatRsrc& R, int u, int U, int t) {
   StepLoad l;
-  l.rs = dfdg[i];
-  l.rinv = invn[i];
+  const int rs_el = u + PADL - 63;        // >= 1: u >= 0
+  const int vrow = 63 - t;
+  l.rs = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(R.rd, vrow * 16, rs_el * 16, 0));
+  l.rinv = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(R.ri, vrow * 8, rs_el * 8, 0));
   const int up = U + PADL;
-  const int off = (up % CSTRIDE) * ca.plane + up / CSTRIDE + t;
-  l.cs = ca.cdfdg[off];
-  l.cinv = ca.cinvn[off];
+  const int el = (up % (C - 1)) * R.plane + up / (C - 1);
+  l.cs = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(R.cd, t * 16, el * 16, 0));
+  l.cinv = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(R.ci, t * 8, el * 8, 0));
   return l;
 }
 
-// Runs ngroups * C steps.  On entry ``cur`` holds the loads of the first step;
-// on exit it holds the loads of the step after the last one.
-template <int C, bool EDGE>
-__device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad& cur, const uint32_t (&code)[C],
-                                              uint32_t keep, int ngroups, int row0, int ubase,
-                                              const double2* __restrict__ dfdg, const double* __restrict__ invn,
-                                              const ColAddr& ca, unsigned long long* rowk,
-                                              unsigned long long* colk, int t) {
-  static_assert(C - 1 == CSTRIDE, "lanes' columns must be CSTRIDE apart");
+// Runs ngroups * C steps.  On entry ring[k] holds the loads of step k of this
+// call (k < PD); on exit it holds those of the PD steps after the last one.
+// CL = false: each lane keeps a running maximum per open column and retires
+// one column per step into LDS; CL = true: every cell's key goes straight to
+// LDS with ds_max_u64 (fewer VALU max instructions, more LDS atomics).
+template <int C, bool EDGE, int PD, bool CL>
+__device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)[PD], const uint32_t (&code)[C],
+                                              uint32_t keep, int ngroups, int u0, int db, const StatRsrc& R,
+                                              unsigned long long* rowk, unsigned long long* colk, int t) {
+  static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
   for (int gidx = 0; gidx < ngroups; ++gidx) {
 #pragma unroll
     for (int p = 0; p < C; ++p) {
       const int us = gidx * C + p;
-      // prefetch the next step while this one computes; its entering column is
-      // ubase + us + C + (C - 1) t, ubase = u0 + db uniform
-      const StepLoad nxt = load_step(dfdg, invn, ca, row0 + us + 1, ubase + us + C, t);
+      // prefetch PD steps ahead
+      const int ua = u0 + us + PD;
+      const StepLoad ahead = load_step<C>(R, ua, ua + db + C - 1, t);
+      const StepLoad cur = ring[0];
+#pragma unroll
+      for (int k = 0; k + 1 < PD; ++k) ring[k] = ring[k + 1];
+      ring[PD - 1] = ahead;
       const int sn = (p + C - 1) % C;
       ls.cdf[sn] = cur.cs.x;
       ls.cdg[sn] = cur.cs.y;
@@ -220,20 +256,23 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad& cur, c
         key = embed(key, keep, code[q]);
         if (q == 0) rowp = EDGE ? vmax(0.0, key) : key;
         else rowp = vmax(rowp, key);
-        if (q == C - 1) ls.colacc[sl] = EDGE ? vmax(0.0, key) : key;
-        else ls.colacc[sl] = vmax(ls.colacc[sl], key);
+        if (CL) {
+          atomicMax(&colk[us + t * (C - 1) + q], kbits(EDGE ? vmax(0.0, key) : key));
+        } else {
+          if (q == C - 1) ls.colacc[sl] = EDGE ? vmax(0.0, key) : key;
+          else ls.colacc[sl] = vmax(ls.colacc[sl], key);
+        }
         ls.Cq[q] = fma(rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = fma(ls.cdf[sl], rs.y, ls.Cq[q]);
       }
       atomicMax(&rowk[us + 63 - t], kbits(rowp));
-      atomicMax(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
-      cur = nxt;
+      if (!CL) atomicMax(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
     }
   }
 }
 
-template <int C, int TL>
-__global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
+template <int C, int TL, int PD, int WPE, bool CL>
+__global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   constexpr int NROW = TL + 64;
   constexpr int NCOL = TL + 64 * C;
   constexpr int LBITS = (64 * C <= 512) ? 9 : ((64 * C <= 1024) ? 10 : 11);
@@ -257,8 +296,16 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
     if (t == 0) unit = atomicAdd(st.counter, 1u);
     unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
     if ((int64_t)unit >= st.total_units) break;
-    const int s = find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base);
-    const SeriesPlan sp = st.plan[s];
+    const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
+    SeriesPlan sp = st.plan[s];
+    sp.unit_base = uni(sp.unit_base);
+    sp.nb = uni(sp.nb);
+    sp.ns = uni(sp.ns);
+    sp.n_sub = uni(sp.n_sub);
+    sp.stat_base = uni(sp.stat_base);
+    sp.lpad = uni(sp.lpad);
+    sp.col = uni(sp.col);
+    sp.n = uni(sp.n);
     const int64_t local = (int64_t)unit - sp.unit_base;
     const int64_t per_group = (int64_t)sp.nb * sp.ns;
     const int gi = (int)(local / per_group);
@@ -319,18 +366,19 @@ __global__ __launch_bounds__(64) void sj_fp64_kernel(SJState st) {
     }
 
     const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;
-    const ColAddr ca{st.cdfdg + gbase, st.cinvn + gbase, (int)(sp.lpad / CSTRIDE)};
-    StepLoad cur = load_step(dfdg, invn, ca, u_begin - t, u_begin + db + C - 1, t);
+    const StatRsrc R = make_rsrc<C>(st, gbase, sp.lpad);
+    StepLoad ring[PD];
+#pragma unroll
+    for (int k = 0; k < PD; ++k) ring[k] = load_step<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
       const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
-      const int row0 = u0 - t;
       if (edge)
-        sj_run_groups<C, true>(ls, cur, code, keep, ngroups, row0, u0 + db, dfdg, invn, ca, rowk, colk, t);
+        sj_run_groups<C, true, PD, CL>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
       else
-        sj_run_groups<C, false>(ls, cur, code, keep, ngroups, row0, u0 + db, dfdg, invn, ca, rowk, colk, t);
+        sj_run_groups<C, false, PD, CL>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
       const bool last = (u0 + TL >= u_end);
-      if (last) {
+      if (last && !CL) {
         // retire the columns still open in the window (phase 0 after full groups)
 #pragma unroll
         for (int q = 0; q < C - 1; ++q)
@@ -481,7 +529,7 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.n_sub = std::max<int64_t>(p.n - m + 1, 1);
     max_nsub = std::max(max_nsub, p.n_sub);
     p.stat_base = stat;
-    p.lpad = ((p.n_sub + PADL + PADR + CSTRIDE - 1) / CSTRIDE) * CSTRIDE;
+    p.lpad = ((p.n_sub + PADL + PADR + C - 2) / (C - 1)) * (C - 1);
     stat += p.lpad;
     const int64_t nd = p.n_sub - excl;  // diagonals with admissible pairs
     const int64_t D = 64 * (int64_t)C;
@@ -538,9 +586,46 @@ static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, 
 }
 
 // tile configuration of the FP64 kernel
-constexpr int FP64_C = 8;
-constexpr int FP64_TL = 256;
 constexpr int DEFAULT_STRIP = 2048;
+
+// Compiled variants of the FP64 tile kernel: diagonals per lane C, prefetch
+// depth PD and the waves-per-SIMD occupancy the register allocation is held to.
+struct Fp64Variant {
+  const char* name;
+  int C;
+  const void* fn;
+  void (*launch)(dim3 grid, hipStream_t st, const SJState& s);
+};
+
+// tile length: the largest multiple of C not above 256
+constexpr int tl_for(int C) { return 256 - 256 % C; }
+
+template <int C, int PD, int WPE, bool CL>
+static void launch_fp64(dim3 grid, hipStream_t st, const SJState& s) {
+  hipLaunchKernelGGL((sj_fp64_kernel<C, tl_for(C), PD, WPE, CL>), grid, dim3(64), 0, st, s);
+}
+
+#define SKMP_FP64_V(C, PD, WPE, CL)                                                                 \
+  {                                                                                                 \
+    "c" #C "_pd" #PD "_w" #WPE "_cl" #CL, C,                                                        \
+        reinterpret_cast<const void*>(&sj_fp64_kernel<C, tl_for(C), PD, WPE, CL>), &launch_fp64<C, PD, WPE, CL> \
+  }
+static const Fp64Variant kFp64Variants[] = {
+    SKMP_FP64_V(8, 1, 2, false), SKMP_FP64_V(8, 1, 2, true),  SKMP_FP64_V(8, 2, 2, true),
+    SKMP_FP64_V(10, 1, 2, true), SKMP_FP64_V(12, 1, 2, true), SKMP_FP64_V(6, 1, 3, true),
+    SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true),
+};
+#undef SKMP_FP64_V
+constexpr int kNumFp64Variants = sizeof(kFp64Variants) / sizeof(kFp64Variants[0]);
+
+static const Fp64Variant& fp64_variant() {
+  static int idx = [] {
+    const char* e = getenv("SKMP_FP64_VARIANT");
+    int v = e ? atoi(e) : 0;
+    return (v >= 0 && v < kNumFp64Variants) ? v : 0;
+  }();
+  return kFp64Variants[idx];
+}
 
 static int grid_for(const void* kernel, int block, size_t lds) {
   int dev = 0, ncu = 0, per_cu = 0;
@@ -566,7 +651,8 @@ extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets
   (void)prec;
   if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
   PlanInfo pl;
-  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, FP64_C, DEFAULT_STRIP, pl, false) != SKMP_OK) return 0;
+  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, fp64_variant().C, DEFAULT_STRIP, pl, false) != SKMP_OK)
+    return 0;
   Carve cv(nullptr, 0);
   SJBuffers b;
   carve_sj(cv, pl, n_series, k, b);
@@ -599,7 +685,8 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   }
   const int kact = gl.count;
   PlanInfo pl;
-  int rc = make_plan(n_series, offsets, m, excl, kact, FP64_C, DEFAULT_STRIP, pl, true);
+  const Fp64Variant& var = fp64_variant();
+  int rc = make_plan(n_series, offsets, m, excl, kact, var.C, DEFAULT_STRIP, pl, true);
   if (rc) return rc;
   Carve cv(workspace, ws_bytes);
   SJBuffers b;
@@ -625,6 +712,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   s.invn = b.invn;
   s.cdfdg = b.cdfdg;
   s.cinvn = b.cinvn;
+  s.cstride = var.C - 1;
   s.mu = b.mu;
   s.scale = b.scale;
   s.rowkey = b.rowkey;
@@ -659,10 +747,9 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   SKMP_CHECK_HIP(hipGetLastError());
 
   if (pl.total_units > 0) {
-    const void* kfn = reinterpret_cast<const void*>(&sj_fp64_kernel<FP64_C, FP64_TL>);
-    const int grid = (int)std::min<int64_t>(grid_for(kfn, 64, 0), pl.total_units);
+    const int grid = (int)std::min<int64_t>(grid_for(var.fn, 64, 0), pl.total_units);
     StageTimer tm(SKMP_TIMER_TILES, st);
-    hipLaunchKernelGGL((sj_fp64_kernel<FP64_C, FP64_TL>), dim3(grid), dim3(64), 0, st, s);
+    var.launch(dim3(grid), st, s);
   }
   SKMP_CHECK_HIP(hipGetLastError());
   {

@@ -37,10 +37,10 @@ void clear_error();
 constexpr int PADL = 64;
 constexpr int PADR = 2048;
 constexpr double FLAT_REL = 1e-10;
-// The column statistics are also stored de-interleaved by CSTRIDE (plane
-// x mod CSTRIDE, slot x div CSTRIDE, for the padded index x + PADL) so that
-// 64 lanes whose columns are CSTRIDE apart read 64 adjacent elements.
-constexpr int CSTRIDE = 7;
+// The column statistics are also stored de-interleaved by a stride cs (plane
+// x mod cs, slot x div cs, for the padded index x + PADL) so that 64 lanes
+// whose columns are cs apart read 64 adjacent elements; cs = C - 1 for a tile
+// kernel whose lanes own C diagonals each.
 
 // ------------------------------------------------------------ workspace
 // Bump allocator over the caller's workspace; every region 256-byte aligned.
@@ -68,7 +68,7 @@ struct SeriesPlan {
   int64_t unit_base;   // first self-join work unit of this series
   int64_t chunk_base;  // first 256-element chunk of this series (elementwise kernels)
   int64_t blk_base;    // first 256-window block (flat-index summaries)
-  int64_t lpad;        // padded windows per group: round_up(n_sub + PADL + PADR, CSTRIDE)
+  int64_t lpad;        // padded windows per group: round_up(n_sub + PADL + PADR, cstride)
   int32_t nb;          // diagonal bands
   int32_t ns;          // strips per band (grid, some empty)
 };
@@ -91,8 +91,9 @@ struct SJState {
   GroupList groups;
   double2* dfdg;        // (df, dg) per window, padded
   double* invn;         // 1 / (sqrt(m) sigma), 0 if flat, NaN in the padding
-  double2* cdfdg;       // dfdg de-interleaved by CSTRIDE
-  double* cinvn;        // invn de-interleaved by CSTRIDE
+  double2* cdfdg;       // dfdg de-interleaved by cstride
+  double* cinvn;        // invn de-interleaved by cstride
+  int32_t cstride;      // de-interleave stride of cdfdg / cinvn
   double* mu;           // window mean
   double* scale;        // per (series, group slot): max |r|
   unsigned long long* rowkey;  // best key of row i among partners j > i
