@@ -39,6 +39,8 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--refresh", type=int, default=0,
+                    help="mixed paths: rows between exact FP64 recomputations (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -111,7 +113,7 @@ def main() -> int:
 
     def step():
         skmp.sketch_build(T, w.offsets, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R, stats=stats)
-        skmp.mp_selfjoin(R, w.offsets, k, w.m, w.excl, prec=args.prec, P=P, I=I, workspace=ws)
+        skmp.mp_selfjoin(R, w.offsets, k, w.m, w.excl, prec=args.prec, refresh=args.refresh, P=P, I=I, workspace=ws)
         skmp.top_discords(P, w.offsets, k, w.m, 10, out=out)
 
     for _ in range(args.warmup):
@@ -164,7 +166,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"water-treatment-shaped d={d} n={n} gaussian k={k} m={w.m} excl={w.excl}"
                                if args.workload == "c1" else f"{args.workload} d={d} n={n} k={k} m={w.m}",
-                   "precision": args.prec, "cells_per_step": cells, "valid_half_pairs": valid,
+                   "precision": args.prec, "refresh": args.refresh, "cells_per_step": cells, "valid_half_pairs": valid,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "stages_ms_per_step": {st: v[0] / max(args.steps, 1) for st, v in stage.items()},

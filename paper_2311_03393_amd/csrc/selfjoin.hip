@@ -101,6 +101,13 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     st.mu[sidx] = 0.0;
     st.cdfdg[tidx] = make_double2(0.0, 0.0);
     st.cinvn[tidx] = qnan;
+    if (st.fdfdg) {
+      const float fnan = __int_as_float(0x7FC00000);
+      st.fdfdg[sidx] = make_float2(0.f, 0.f);
+      st.finvn[sidx] = fnan;
+      st.fcdfdg[tidx] = make_float2(0.f, 0.f);
+      st.fcinvn[tidx] = fnan;
+    }
     return;
   }
   const double* w = sh_r + threadIdx.x;
@@ -130,6 +137,12 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   st.mu[sidx] = mu;
   st.cdfdg[tidx] = make_double2(df, dg);
   st.cinvn[tidx] = iv;
+  if (st.fdfdg) {
+    st.fdfdg[sidx] = make_float2((float)df, (float)dg);
+    st.finvn[sidx] = (float)iv;
+    st.fcdfdg[tidx] = make_float2((float)df, (float)dg);
+    st.fcinvn[tidx] = (float)iv;
+  }
   if (flat) {
     const int64_t sg = (int64_t)c.s * st.groups.count + c.gi;
     atomicMin(st.flat_first + sg, (int32_t)x);
@@ -162,6 +175,36 @@ __device__ __forceinline__ int64_t uni(int64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+
+// Exact FP64 seeds C(rr, j0 + q) = sum_x (r[rr+x] - mu[rr]) (r[j0+q+x] - mu[j0+q])
+// for the C consecutive diagonals of a lane.  Written as
+// sum_x a_x r[j0+q+x] - mu[j0+q] sum_x a_x with a_x = r[rr+x] - mu[rr], so the
+// r values of the C diagonals stream through one sliding window (about 3 m
+// loads instead of (C + 1) m).  Diagonals that end before row rr (j0 + q >=
+// n_sub) read clamped addresses and are zeroed.
+template <int C>
+__device__ __forceinline__ void exact_seeds(const double* __restrict__ r, const double* __restrict__ mu, int rr, int j0,
+                                            int n_sub, int nlast, int m, double (&acc)[C]) {
+  const double mr = mu[rr];
+  double sa = 0.0;
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] = 0.0;
+  for (int x0 = 0; x0 < m; x0 += C) {
+    double w[2 * C - 1];
+#pragma unroll
+    for (int k = 0; k < 2 * C - 1; ++k) w[k] = r[min(j0 + x0 + k, nlast)];
+#pragma unroll
+    for (int dx = 0; dx < C; ++dx) {
+      const double a = (x0 + dx < m) ? r[rr + x0 + dx] - mr : 0.0;
+      sa += a;
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[q] = fma(a, w[dx + q], acc[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] = (j0 + q < n_sub) ? fma(-mu[min(j0 + q, n_sub - 1)], sa, acc[q]) : 0.0;
 }
 
 template <int C>
@@ -328,30 +371,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
     unsigned long long* gco = st.colkey + sbase;
 
     LaneState<C> ls;
-    // exact FP64 seeds at the strip start: lane t's first row is u_begin - t.
-    // Diagonals that end before that row are computed on clamped (valid)
-    // addresses and zeroed: their cells are all masked.
-    {
-      const int rr = max(u_begin - t, 0);
-      const int j0 = rr + db + t * C;
-      const int nlast = (int)sp.n - 1;
-      const double mr = mu[rr];
-      double mj[C];
-#pragma unroll
-      for (int q = 0; q < C; ++q) {
-        ls.Cq[q] = 0.0;
-        mj[q] = mu[min(j0 + q, n_sub - 1)];
-      }
-#pragma unroll 4
-      for (int x = 0; x < m; ++x) {
-        const double a = r[rr + x] - mr;
-#pragma unroll
-        for (int q = 0; q < C; ++q) ls.Cq[q] = fma(a, r[min(j0 + q + x, nlast)] - mj[q], ls.Cq[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < C; ++q)
-        if (j0 + q >= n_sub) ls.Cq[q] = 0.0;
-    }
+    // exact FP64 seeds at the strip start: lane t's first row is u_begin - t
+    exact_seeds<C>(r, mu, max(u_begin - t, 0), max(u_begin - t, 0) + db + t * C, n_sub, (int)sp.n - 1, m, ls.Cq);
     // column window: columns J + q (q < C-1) in slots q, J = u_begin + db + t (C-1)
     {
       const int J = u_begin + db + t * (C - 1);
@@ -413,6 +434,224 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
         if (kc[q] && j < n_sub) {
           const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
           atomicMax(gco + j, (kc[q] & ~GMAX) | (GMAX - (unsigned long long)delta));
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+
+// ------------------------------------------------------- FP32 tile kernel
+// Same walk as the FP64 kernel with the running covariance, the window
+// statistics and the keys in FP32: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
+// in FP32 from an exact FP64 seed recomputed at the start of every strip
+// (the strip length is the refresh period).  Keys are the bits of the FP32
+// value rho + 2 in [1, 3] with the local diagonal in the low LBITS bits;
+// as positive floats they order like unsigned integers, so the maxima use
+// 32-bit integer max (v_max3_u32 for the row).
+struct StepLoadF {
+  float2 rs;
+  float rinv;
+  float2 cs;
+  float cinv;
+};
+
+struct StatRsrcF {
+  __amdgpu_buffer_rsrc_t rd, ri, cd, ci;
+  int plane;
+};
+
+template <int C>
+__device__ __forceinline__ StatRsrcF make_rsrc_f(const SJState& st, int64_t gbase, int64_t lpad) {
+  StatRsrcF r;
+  r.rd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fdfdg + gbase), 0, (int)(lpad * 8), kBufWord3);
+  r.ri = __builtin_amdgcn_make_buffer_rsrc((void*)(st.finvn + gbase), 0, (int)(lpad * 4), kBufWord3);
+  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcdfdg + gbase), 0, (int)(lpad * 8), kBufWord3);
+  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcinvn + gbase), 0, (int)(lpad * 4), kBufWord3);
+  r.plane = (int)(lpad / (C - 1));
+  return r;
+}
+
+template <int C>
+__device__ __forceinline__ StepLoadF load_step_f(const StatRsrcF& R, int u, int U, int t) {
+  StepLoadF l;
+  const int rs_el = u + PADL - 63;
+  const int vrow = 63 - t;
+  l.rs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.rd, vrow * 8, rs_el * 8, 0));
+  l.rinv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ri, vrow * 4, rs_el * 4, 0));
+  const int up = U + PADL;
+  const int el = (up % (C - 1)) * R.plane + up / (C - 1);
+  l.cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
+  l.cinv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
+  return l;
+}
+
+__device__ __forceinline__ float vmaxf(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+template <int C>
+struct LaneStateF {
+  float Cq[C];
+  float cdf[C], cdg[C], cinv[C];
+  uint32_t colacc[C];
+};
+
+template <int C, bool EDGE, int PD>
+__device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], const uint32_t (&code)[C],
+                                               uint32_t keep, int ngroups, int u0, int db, const StatRsrcF& R,
+                                               uint32_t* rowk, uint32_t* colk, int t) {
+  for (int gidx = 0; gidx < ngroups; ++gidx) {
+#pragma unroll
+    for (int p = 0; p < C; ++p) {
+      const int us = gidx * C + p;
+      const int ua = u0 + us + PD;
+      const StepLoadF ahead = load_step_f<C>(R, ua, ua + db + C - 1, t);
+      const StepLoadF cur = ring[0];
+#pragma unroll
+      for (int k = 0; k + 1 < PD; ++k) ring[k] = ring[k + 1];
+      ring[PD - 1] = ahead;
+      const int sn = (p + C - 1) % C;
+      ls.cdf[sn] = cur.cs.x;
+      ls.cdg[sn] = cur.cs.y;
+      ls.cinv[sn] = cur.cinv;
+      uint32_t rowp = 0u;
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const int sl = (p + q) % C;
+        const float a = ls.Cq[q] * ls.cinv[sl];
+        float kf = __builtin_fmaf(a, cur.rinv, 2.0f);
+        uint32_t key = (__float_as_uint(kf) & keep) | code[q];
+        if (EDGE) key = __float_as_uint(vmaxf(0.0f, __uint_as_float(key)));  // padded cells (NaN) -> 0
+        rowp = (q == 0) ? key : max(rowp, key);
+        if (q == C - 1) ls.colacc[sl] = key;
+        else ls.colacc[sl] = max(ls.colacc[sl], key);
+        ls.Cq[q] = __builtin_fmaf(cur.rs.x, ls.cdg[sl], ls.Cq[q]);
+        ls.Cq[q] = __builtin_fmaf(ls.cdf[sl], cur.rs.y, ls.Cq[q]);
+      }
+      atomicMax(&rowk[us + 63 - t], rowp);
+      atomicMax(&colk[us + t * (C - 1)], ls.colacc[p]);
+    }
+  }
+}
+
+template <int C, int TL, int PD, int WPE>
+__global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
+  constexpr int NROW = TL + 64;
+  constexpr int NCOL = TL + 64 * C;
+  constexpr int LBITS = (64 * C <= 512) ? 9 : ((64 * C <= 1024) ? 10 : 11);
+  constexpr uint32_t LMAX = (1u << LBITS) - 1;
+  static_assert(TL % C == 0, "tile length must be a multiple of C");
+  static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
+  __shared__ uint32_t rowk[NROW];
+  __shared__ uint32_t colk[NCOL];
+  const int t = threadIdx.x;
+  for (int x = t; x < NROW; x += 64) rowk[x] = 0u;
+  for (int x = t; x < NCOL; x += 64) colk[x] = 0u;
+  __syncthreads();
+  const uint32_t keep = ~LMAX;
+  uint32_t code[C];
+#pragma unroll
+  for (int q = 0; q < C; ++q) code[q] = LMAX - (uint32_t)(t * C + q);
+  const unsigned long long GMAX = (1ull << st.key_bits) - 1;
+  const int m = st.m;
+
+  for (;;) {
+    unsigned int unit = 0;
+    if (t == 0) unit = atomicAdd(st.counter, 1u);
+    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
+    if ((int64_t)unit >= st.total_units) break;
+    const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
+    SeriesPlan sp = st.plan[s];
+    sp.unit_base = uni(sp.unit_base);
+    sp.nb = uni(sp.nb);
+    sp.ns = uni(sp.ns);
+    sp.n_sub = uni(sp.n_sub);
+    sp.stat_base = uni(sp.stat_base);
+    sp.lpad = uni(sp.lpad);
+    sp.col = uni(sp.col);
+    sp.n = uni(sp.n);
+    const int64_t local = (int64_t)unit - sp.unit_base;
+    const int64_t per_group = (int64_t)sp.nb * sp.ns;
+    const int gi = (int)(local / per_group);
+    const int64_t rem = local - (int64_t)gi * per_group;
+    const int sigma = (int)(rem / sp.nb);
+    const int b = (int)(rem - (int64_t)sigma * sp.nb);
+    const int n_sub = (int)sp.n_sub;
+    const int db = st.excl + b * 64 * C;
+    const int Ub = n_sub - db;
+    const int u_begin = sigma * st.strip;
+    if (u_begin >= Ub) continue;
+    const int u_end = min(u_begin + st.strip, Ub);
+    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;
+    const int64_t sbase = gbase + PADL;
+    const double* __restrict__ mu = st.mu + sbase;
+    const double* __restrict__ r = st.R + (int64_t)st.groups.g[gi] * st.ldr + sp.col;
+    unsigned long long* gro = st.rowkey + sbase;
+    unsigned long long* gco = st.colkey + sbase;
+
+    LaneStateF<C> ls;
+    {  // exact FP64 seeds, rounded once to FP32
+      double acc[C];
+      exact_seeds<C>(r, mu, max(u_begin - t, 0), max(u_begin - t, 0) + db + t * C, n_sub, (int)sp.n - 1, m, acc);
+#pragma unroll
+      for (int q = 0; q < C; ++q) ls.Cq[q] = (float)acc[q];
+    }
+    const StatRsrcF R = make_rsrc_f<C>(st, gbase, sp.lpad);
+    {
+      const int up = u_begin + db + PADL;
+#pragma unroll
+      for (int q = 0; q < C - 1; ++q) {
+        const int el = ((up + q) % (C - 1)) * R.plane + (up + q) / (C - 1);
+        const float2 cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
+        ls.cdf[q] = cs.x;
+        ls.cdg[q] = cs.y;
+        ls.cinv[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
+        ls.colacc[q] = 0u;
+      }
+    }
+    StepLoadF ring[PD];
+#pragma unroll
+    for (int k = 0; k < PD; ++k) ring[k] = load_step_f<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
+    for (int u0 = u_begin; u0 < u_end; u0 += TL) {
+      const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
+      const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
+      if (edge)
+        sjf_run_groups<C, true, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
+      else
+        sjf_run_groups<C, false, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
+      if (u0 + TL >= u_end) {
+#pragma unroll
+        for (int q = 0; q < C - 1; ++q) atomicMax(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
+      }
+      __syncthreads();
+      for (int xr = t; xr < NROW; xr += 64) {
+        const uint32_t key = rowk[xr];
+        if (key) {
+          rowk[xr] = 0u;
+          const int x = u0 - 63 + xr;
+          if (x >= 0 && x < n_sub) {
+            const int delta = db + (int)(LMAX - (key & LMAX));
+            const double v = (double)__uint_as_float(key & ~LMAX);
+            const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+            atomicMax(gro + x, (kb & ~GMAX) | (GMAX - (unsigned long long)delta));
+          }
+        }
+      }
+      for (int xr = t; xr < NCOL; xr += 64) {
+        const uint32_t key = colk[xr];
+        if (key) {
+          colk[xr] = 0u;
+          const int j = u0 + db + xr;
+          if (j < n_sub) {
+            const int delta = db + (int)(LMAX - (key & LMAX));
+            const double v = (double)__uint_as_float(key & ~LMAX);
+            const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+            atomicMax(gco + j, (kb & ~GMAX) | (GMAX - (unsigned long long)delta));
+          }
         }
       }
       __syncthreads();
@@ -558,6 +797,10 @@ struct SJBuffers {
   double* invn;
   double2* cdfdg;
   double* cinvn;
+  float2* fdfdg = nullptr;
+  float* finvn = nullptr;
+  float2* fcdfdg = nullptr;
+  float* fcinvn = nullptr;
   double* mu;
   unsigned long long* rowkey;
   unsigned long long* colkey;
@@ -568,8 +811,14 @@ struct SJBuffers {
   unsigned int* counter;
 };
 
-static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, SJBuffers& b) {
+static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, int prec, SJBuffers& b) {
   const size_t cells = (size_t)kact * (size_t)pl.gstride;
+  if (prec == SKMP_FP32) {
+    b.fdfdg = cv.take<float2>(cells);
+    b.finvn = cv.take<float>(cells);
+    b.fcdfdg = cv.take<float2>(cells);
+    b.fcinvn = cv.take<float>(cells);
+  }
   b.plan = cv.take<SeriesPlan>(n_series);
   b.dfdg = cv.take<double2>(cells);
   b.invn = cv.take<double>(cells);
@@ -587,6 +836,7 @@ static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, 
 
 // tile configuration of the FP64 kernel
 constexpr int DEFAULT_STRIP = 2048;
+constexpr int DEFAULT_REFRESH_FP32 = 256;
 
 // Compiled variants of the FP64 tile kernel: diagonals per lane C, prefetch
 // depth PD and the waves-per-SIMD occupancy the register allocation is held to.
@@ -618,6 +868,32 @@ static const Fp64Variant kFp64Variants[] = {
 #undef SKMP_FP64_V
 constexpr int kNumFp64Variants = sizeof(kFp64Variants) / sizeof(kFp64Variants[0]);
 
+template <int C, int PD, int WPE>
+static void launch_fp32(dim3 grid, hipStream_t st, const SJState& s) {
+  hipLaunchKernelGGL((sj_fp32_kernel<C, tl_for(C), PD, WPE>), grid, dim3(64), 0, st, s);
+}
+
+#define SKMP_FP32_V(C, PD, WPE)                                                                              \
+  {                                                                                                          \
+    "f32_c" #C "_pd" #PD "_w" #WPE, C, reinterpret_cast<const void*>(&sj_fp32_kernel<C, tl_for(C), PD, WPE>), \
+        &launch_fp32<C, PD, WPE>                                                                             \
+  }
+static const Fp64Variant kFp32Variants[] = {
+    SKMP_FP32_V(8, 1, 2), SKMP_FP32_V(16, 1, 2), SKMP_FP32_V(8, 1, 3), SKMP_FP32_V(12, 1, 2), SKMP_FP32_V(8, 2, 3),
+    SKMP_FP32_V(16, 2, 2),
+};
+#undef SKMP_FP32_V
+constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
+
+static const Fp64Variant& fp32_variant() {
+  static int idx = [] {
+    const char* e = getenv("SKMP_FP32_VARIANT");
+    int v = e ? atoi(e) : 1;
+    return (v >= 0 && v < kNumFp32Variants) ? v : 1;
+  }();
+  return kFp32Variants[idx];
+}
+
 static const Fp64Variant& fp64_variant() {
   static int idx = [] {
     const char* e = getenv("SKMP_FP64_VARIANT");
@@ -648,14 +924,14 @@ static int active_groups(int32_t k, uint64_t group_mask, GroupList& gl) {
 
 extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
                                         int32_t prec) {
-  (void)prec;
   if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
   PlanInfo pl;
-  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, fp64_variant().C, DEFAULT_STRIP, pl, false) != SKMP_OK)
-    return 0;
+  const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
+  const int strip = (prec == SKMP_FP32) ? DEFAULT_REFRESH_FP32 : DEFAULT_STRIP;
+  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, var.C, strip, pl, false) != SKMP_OK) return 0;
   Carve cv(nullptr, 0);
   SJBuffers b;
-  carve_sj(cv, pl, n_series, k, b);
+  carve_sj(cv, pl, n_series, k, prec, b);
   return cv.used + 256;
 }
 
@@ -669,7 +945,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   SKMP_REQUIRE(m >= 4 && m <= 2048, "m must lie in [4, 2048]");
   SKMP_REQUIRE(excl >= 1, "excl must be >= 1 (a subsequence is its own trivial match)");
   SKMP_REQUIRE(prec >= SKMP_FP64 && prec <= SKMP_FP16X3, "unknown precision");
-  SKMP_REQUIRE(refresh >= 0, "refresh must be >= 0");
+  SKMP_REQUIRE(refresh == 0 || (refresh >= 64 && refresh <= (1 << 20)), "refresh must be 0 or in [64, 2^20]");
   SKMP_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
   for (int64_t s = 0; s < n_series; ++s) SKMP_REQUIRE(offsets[s + 1] >= offsets[s], "offsets must be non-decreasing");
   const int64_t N = offsets[n_series];
@@ -679,18 +955,20 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   if (k < 64) group_mask &= (1ull << k) - 1;
   GroupList gl;
   if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
-  if (prec != SKMP_FP64) {
-    set_error("mixed-precision self-join is not available in this build");
+  if (prec != SKMP_FP64 && prec != SKMP_FP32) {
+    set_error("the BF16x3 / FP16x3 self-join is not available in this build");
     return SKMP_EINVAL;
   }
   const int kact = gl.count;
   PlanInfo pl;
-  const Fp64Variant& var = fp64_variant();
-  int rc = make_plan(n_series, offsets, m, excl, kact, var.C, DEFAULT_STRIP, pl, true);
+  const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
+  // FP32: strips restart from an exact FP64 seed, so the strip is the refresh period
+  const int strip = (prec == SKMP_FP32) ? (refresh > 0 ? refresh : DEFAULT_REFRESH_FP32) : DEFAULT_STRIP;
+  int rc = make_plan(n_series, offsets, m, excl, kact, var.C, strip, pl, true);
   if (rc) return rc;
   Carve cv(workspace, ws_bytes);
   SJBuffers b;
-  carve_sj(cv, pl, n_series, kact, b);
+  carve_sj(cv, pl, n_series, kact, prec, b);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
     return SKMP_ENOMEM;
@@ -713,6 +991,10 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   s.cdfdg = b.cdfdg;
   s.cinvn = b.cinvn;
   s.cstride = var.C - 1;
+  s.fdfdg = b.fdfdg;
+  s.finvn = b.finvn;
+  s.fcdfdg = b.fcdfdg;
+  s.fcinvn = b.fcinvn;
   s.mu = b.mu;
   s.scale = b.scale;
   s.rowkey = b.rowkey;
@@ -724,7 +1006,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   s.counter = b.counter;
   s.total_units = pl.total_units;
   s.total_chunks = pl.total_chunks;
-  s.strip = DEFAULT_STRIP;
+  s.strip = strip;
 
   const size_t cells = (size_t)kact * (size_t)pl.gstride;
   const dim3 fb(256), fg(2048);
@@ -757,6 +1039,5 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
     hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
   }
   SKMP_CHECK_HIP(hipGetLastError());
-  (void)refresh;
   return SKMP_OK;
 }

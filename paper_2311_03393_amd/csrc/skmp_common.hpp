@@ -94,6 +94,10 @@ struct SJState {
   double2* cdfdg;       // dfdg de-interleaved by cstride
   double* cinvn;        // invn de-interleaved by cstride
   int32_t cstride;      // de-interleave stride of cdfdg / cinvn
+  float2* fdfdg;        // FP32 copies for the FP32 tile kernel (NULL when unused)
+  float* finvn;
+  float2* fcdfdg;
+  float* fcinvn;
   double* mu;           // window mean
   double* scale;        // per (series, group slot): max |r|
   unsigned long long* rowkey;  // best key of row i among partners j > i

@@ -357,3 +357,68 @@ def test_selfjoin_c1_full_size_sampled_and_certified(dev, c_oracle):
         for (i, g, s), (io, go, so) in zip(gpu, picks):
             assert i in exact and exact[i][0] >= so - 2 * tol
     _say("c1 top10", [i for i, _, _ in gpu])
+
+
+# ------------------------------------------------------- mixed precisions
+MIXED = ["fp32"]
+
+
+@pytest.mark.parametrize("prec", MIXED)
+@pytest.mark.parametrize("n,m,excl,k,seed", SMALL)
+def test_selfjoin_mixed_matches_oracle(dev, c_oracle, prec, n, m, excl, k, seed):
+    import torch
+    from tests.helpers import mixed_tol
+    _say("selfjoin", prec, n, m, excl, k, seed)
+    T = datagen.tiny_series(seed, 5, n)
+    R_np, _, _, _ = O.build(T, "gauss", k, seed)
+    P, I = _run_selfjoin(torch, dev, R_np, [0, n], k, m, excl, prec=prec)
+    n_sub = n - m + 1
+    tol = mixed_tol(m)
+    for g in range(k):
+        P_o, _ = c_oracle.profile(R_np[g], m, excl)
+        ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
+        assert ok.all(), f"{prec} group {g}: {np.count_nonzero(~ok)} rows out of tolerance, max err {err}"
+        check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
+        # the reported distance is the exact FP64 distance of the reported neighbour
+        fin = I[g, :n_sub] >= 0
+        if fin.any():
+            dd = c_oracle.pair_dist(R_np[g], m, np.arange(n_sub)[fin], I[g, :n_sub][fin])
+            assert np.max(np.abs(dd - P[g, :n_sub][fin])) < 1e-9
+
+
+@pytest.mark.parametrize("prec", MIXED)
+def test_selfjoin_mixed_batched_flat_and_top10(dev, c_oracle, prec):
+    import torch
+    import paper_2311_03393_amd as skmp
+    from tests.helpers import mixed_tol
+    m, excl, k = 32, 8, 2
+    lens = [40, 700, 2500, 64, 3000]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    T = np.concatenate([datagen.tiny_series(200 + q, 3, L) for q, L in enumerate(lens)], axis=1)
+    T[:, offsets[4] + 500:offsets[4] + 560] = 1.0         # constant stretch: flat windows in every group
+    R_np = np.zeros((k, offsets[-1]))
+    for s in range(len(lens)):
+        a, b = offsets[s], offsets[s + 1]
+        R_np[:, a:b], _, _, _ = O.build(T[:, a:b], "gauss", k, 77)
+    R = _to_dev(torch, R_np, dev)
+    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec)
+    idx, grp, score, nf = skmp.top_discords(P, offsets, k, m, 10)
+    torch.cuda.synchronize()
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    tol = mixed_tol(m)
+    for s in range(len(lens)):
+        a, b = offsets[s], offsets[s + 1]
+        n_sub = b - a - m + 1
+        Ps = []
+        for g in range(k):
+            P_o, _ = c_oracle.profile(R_np[g, a:b], m, excl)
+            ok, err = profile_close(P[g, a:a + n_sub], P_o, m, tol)
+            assert ok.all(), (s, g, err)
+            check_neighbours(c_oracle, R_np[g, a:b], m, excl, np.arange(n_sub), I[g, a:a + n_sub], P_o, tol)
+            Ps.append(P_o)
+        if n_sub > 0:
+            ref = O.top_discords(np.stack(Ps), m, 10)
+            A_o = np.max(np.where(np.isfinite(np.stack(Ps)), np.stack(Ps), -np.inf), axis=0)
+            got = [(int(i), int(g), float(v)) for i, g, v in zip(idx[s].cpu(), grp[s].cpu(), score[s].cpu())][:len(ref)]
+            assert int(nf[s]) == len(ref)
+            discords_equivalent(got, ref, A_o, m, tol)
