@@ -168,14 +168,7 @@ __device__ __forceinline__ double embed(double x, uint32_t keep, uint32_t code) 
 
 __device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned long long)__double_as_longlong(k); }
 
-// Values that are the same in every lane but come out of vector loads: make
-// the compiler keep them (and what derives from them) in scalar registers.
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ int64_t uni(int64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
+
 
 
 // Exact FP64 seeds C(rr, j0 + q) = sum_x (r[rr+x] - mu[rr]) (r[j0+q+x] - mu[j0+q])
@@ -753,8 +746,11 @@ struct PlanInfo {
   int key_bits = 0;
 };
 
+// C > 0: diagonal kernels (bands of 64 C diagonals x strips of `strip` rows);
+// C = 0: MFMA tiles (row panels of MFMA_TILE rows x segments of MFMA_SEG column tiles).
 static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_t excl, int kact, int C, int strip,
                      PlanInfo& pl, bool validate) {
+  const int cs = C > 0 ? C - 1 : 7;  // de-interleave stride of the column statistics
   pl.sp.resize(n_series);
   int64_t stat = 0, unit = 0, chunk = 0, blk = 0, max_nsub = 1;
   for (int64_t s = 0; s < n_series; ++s) {
@@ -768,12 +764,19 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.n_sub = std::max<int64_t>(p.n - m + 1, 1);
     max_nsub = std::max(max_nsub, p.n_sub);
     p.stat_base = stat;
-    p.lpad = ((p.n_sub + PADL + PADR + C - 2) / (C - 1)) * (C - 1);
+    p.lpad = ((p.n_sub + PADL + PADR + cs - 1) / cs) * cs;
     stat += p.lpad;
     const int64_t nd = p.n_sub - excl;  // diagonals with admissible pairs
-    const int64_t D = 64 * (int64_t)C;
-    p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
-    p.ns = nd > 0 ? (int32_t)(((p.n_sub - excl) + strip - 1) / strip) : 0;
+    if (C > 0) {
+      const int64_t D = 64 * (int64_t)C;
+      p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
+      p.ns = nd > 0 ? (int32_t)((nd + strip - 1) / strip) : 0;
+    } else {
+      const int64_t jt_last = (p.n_sub - 1) / MFMA_TILE;
+      const int64_t nt0 = jt_last - (int64_t)excl / MFMA_TILE + 1;  // tiles of row panel 0
+      p.nb = nd > 0 ? (int32_t)((p.n_sub + MFMA_TILE - 1) / MFMA_TILE) : 0;
+      p.ns = nd > 0 ? (int32_t)((nt0 + MFMA_SEG - 1) / MFMA_SEG) : 0;
+    }
     p.unit_base = unit;
     unit += (int64_t)p.nb * p.ns * kact;
     p.chunk_base = chunk;
@@ -926,9 +929,10 @@ extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets
                                         int32_t prec) {
   if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
   PlanInfo pl;
+  const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
   const int strip = (prec == SKMP_FP32) ? DEFAULT_REFRESH_FP32 : DEFAULT_STRIP;
-  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, var.C, strip, pl, false) != SKMP_OK) return 0;
+  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, mfma ? 0 : var.C, strip, pl, false) != SKMP_OK) return 0;
   Carve cv(nullptr, 0);
   SJBuffers b;
   carve_sj(cv, pl, n_series, k, prec, b);
@@ -955,16 +959,14 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   if (k < 64) group_mask &= (1ull << k) - 1;
   GroupList gl;
   if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
-  if (prec != SKMP_FP64 && prec != SKMP_FP32) {
-    set_error("the BF16x3 / FP16x3 self-join is not available in this build");
-    return SKMP_EINVAL;
-  }
+  const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
+  SKMP_REQUIRE(!mfma || m <= 1024, "the BF16x3 / FP16x3 self-join supports m <= 1024");
   const int kact = gl.count;
   PlanInfo pl;
   const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
   // FP32: strips restart from an exact FP64 seed, so the strip is the refresh period
   const int strip = (prec == SKMP_FP32) ? (refresh > 0 ? refresh : DEFAULT_REFRESH_FP32) : DEFAULT_STRIP;
-  int rc = make_plan(n_series, offsets, m, excl, kact, var.C, strip, pl, true);
+  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true);
   if (rc) return rc;
   Carve cv(workspace, ws_bytes);
   SJBuffers b;
@@ -990,7 +992,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   s.invn = b.invn;
   s.cdfdg = b.cdfdg;
   s.cinvn = b.cinvn;
-  s.cstride = var.C - 1;
+  s.cstride = mfma ? 7 : var.C - 1;
   s.fdfdg = b.fdfdg;
   s.finvn = b.finvn;
   s.fcdfdg = b.fcdfdg;
@@ -1029,9 +1031,14 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   SKMP_CHECK_HIP(hipGetLastError());
 
   if (pl.total_units > 0) {
-    const int grid = (int)std::min<int64_t>(grid_for(var.fn, 64, 0), pl.total_units);
     StageTimer tm(SKMP_TIMER_TILES, st);
-    var.launch(dim3(grid), st, s);
+    if (mfma) {
+      rc = launch_sj_mfma(prec, s, pl.total_units, st);
+      if (rc) return rc;
+    } else {
+      const int grid = (int)std::min<int64_t>(grid_for(var.fn, 64, 0), pl.total_units);
+      var.launch(dim3(grid), st, s);
+    }
   }
   SKMP_CHECK_HIP(hipGetLastError());
   {

@@ -122,6 +122,44 @@ __device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series,
   return lo;
 }
 
+// Values that are the same in every lane but come out of vector loads: make
+// the compiler keep them (and what derives from them) in scalar registers.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Decoded self-join work unit: series s, group slot gi and the two unit
+// coordinates (diagonal kernels: strip sigma, band b; MFMA kernel: segment,
+// row panel), with the series fields forced uniform.
+struct UnitPos {
+  SeriesPlan sp;
+  int s, gi, outer, inner;
+};
+
+__device__ __forceinline__ UnitPos decode_unit(const SJState& st, unsigned int unit) {
+  UnitPos u;
+  u.s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
+  u.sp = st.plan[u.s];
+  u.sp.unit_base = uni(u.sp.unit_base);
+  u.sp.nb = uni(u.sp.nb);
+  u.sp.ns = uni(u.sp.ns);
+  u.sp.n_sub = uni(u.sp.n_sub);
+  u.sp.stat_base = uni(u.sp.stat_base);
+  u.sp.lpad = uni(u.sp.lpad);
+  u.sp.col = uni(u.sp.col);
+  u.sp.n = uni(u.sp.n);
+  const int64_t local = (int64_t)unit - u.sp.unit_base;
+  const int64_t per_group = (int64_t)u.sp.nb * u.sp.ns;
+  u.gi = (int)(local / per_group);
+  const int64_t rem = local - (int64_t)u.gi * per_group;
+  u.outer = (int)(rem / u.sp.nb);
+  u.inner = (int)(rem - (int64_t)u.outer * u.sp.nb);
+  return u;
+}
+
 // ---------------------------------------------------------------- timing
 // Brackets the launches issued during its lifetime with HIP events on ``st``
 // when timing is enabled (skmp_timing_enable); a no-op otherwise.
@@ -141,5 +179,11 @@ class StageTimer {
 
 // -------------------------------------------------------- host helpers
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S);
+
+// MFMA self-join (selfjoin_mixed.hip): tile edge, units per row panel, LDS bytes
+constexpr int MFMA_TILE = 128;
+constexpr int MFMA_SEG = 4;
+size_t mfma_lds_bytes(int m);
+int launch_sj_mfma(int prec, const SJState& s, int64_t total_units, hipStream_t st);
 
 }  // namespace skmp

@@ -360,7 +360,7 @@ def test_selfjoin_c1_full_size_sampled_and_certified(dev, c_oracle):
 
 
 # ------------------------------------------------------- mixed precisions
-MIXED = ["fp32"]
+MIXED = ["fp32", "bf16x3", "fp16x3"]
 
 
 @pytest.mark.parametrize("prec", MIXED)
