@@ -45,7 +45,14 @@ def _parse():
                     help="headline precision (default: the one the workload names)")
     ap.add_argument("--refresh", type=int, default=None,
                     help="mixed paths: rows between exact FP64 recomputations (default: the workload's)")
-    ap.add_argument("--also", default="fp64", help="comma-separated extra precisions measured into 'paths'")
+    ap.add_argument("--also", default=None,
+                    help="comma-separated extra precisions measured into 'paths' (default: fp64 plus, where a "
+                         "step takes well under a second, the other mixed forms)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step into a HIP graph and time graph replays (stage timings then come from "
+                         "an extra eager pass)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
+                    help="run one plain device copy of MB MiB before the steps (reference for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -128,13 +135,27 @@ def main() -> int:
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        graph = None
+        if args.graph:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                step()
+            torch.cuda.synchronize()
         skmp.timing_enable(True)
         for st in skmp.TIMERS:
             skmp.timing_read(st, reset=True)
+        if graph is not None:  # stage timings from eager steps; the timed loop replays the graph
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            skmp.timing_enable(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            step()
+            if graph is not None:
+                graph.replay()
+            else:
+                step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         skmp.timing_enable(False)
@@ -142,6 +163,7 @@ def main() -> int:
         ms = (t1 - t0) * 1e3 / steps
         tiles_ms, tiles_n = stage["tiles"]
         tile_avg_s = tiles_ms / max(tiles_n, 1) * 1e-3
+        profiles[pr] = P[:, :n_sub].clone()
         return {
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
@@ -150,10 +172,37 @@ def main() -> int:
             "top10": [int(x) for x in out[0][0].cpu()],
         }
 
+    if args.copy_calib > 0:
+        src = torch.empty(args.copy_calib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    profiles = {}
+    also = args.also
+    if also is None:
+        also = "fp64" if args.workload in ("c4",) else "fp64,fp32,bf16x3,fp16x3"
     head = measure(prec, refresh, args.steps, args.warmup)
     paths = {f"{prec}" + (f"_refresh{refresh}" if refresh else ""): head}
-    for extra in [x for x in args.also.split(",") if x and x != prec]:
+    for extra in [x for x in also.split(",") if x and x != prec]:
         paths[extra] = measure(extra, 0, max(3, args.steps // 2), 1)
+    if "fp64" in profiles:
+        # error of every path against the FP64 path (itself held to the oracle at 1e-9 * 2 sqrt(m))
+        ref = profiles["fp64"]
+        tol = 1e-3 * 2 * w.m ** 0.5
+        for key, v in paths.items():
+            got = profiles[v["precision"]]
+            both = torch.isfinite(ref) & torch.isfinite(got)
+            err = (got - ref).abs()[both]
+            sq = (got * got - ref * ref).abs()[both]
+            v["vs_fp64"] = {
+                "max_abs_dP": float(err.max()) if err.numel() else 0.0,
+                "max_abs_dP2": float(sq.max()) if sq.numel() else 0.0,
+                "finite_pattern_equal": bool(torch.equal(torch.isfinite(ref), torch.isfinite(got))),
+                "tolerance_dP": tol,
+                "top10_equal": v["top10"] == paths[[x for x in paths if paths[x]["precision"] == "fp64"][0]]["top10"],
+            }
 
     tile_avg_s = head["tile_kernel_ms"] * 1e-3
     achieved = OPS_PER_CELL * valid / tile_avg_s
@@ -184,6 +233,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec),
         "data": "synthetic",
+        "graph": bool(args.graph),
         "config": {"workload": (f"water-treatment-shaped d={d} n={n} gaussian k={k} m={w.m} excl={w.excl}"
                                 if args.workload == "c1" else f"{args.workload} d={d} n={n} k={k} m={w.m}"),
                    "precision": prec, "refresh": refresh, "cells_per_step": cells, "valid_half_pairs": valid,

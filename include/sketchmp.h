@@ -29,6 +29,16 @@
  *   - Return value: SKMP_OK (0) or a negative SKMP_E* code; a message for the
  *     last failure on the calling thread is available from skmp_last_error().
  *     On error nothing has been launched.
+ *   - HIP graph capture: every call except a sketch call with
+ *     SKMP_FLAG_CHECK_FINITE (which reads a flag back on the host, rejected with
+ *     SKMP_EINVAL under capture) only enqueues kernels and host-to-device
+ *     copies of small host tables (series plans, sketch coefficients), so it
+ *     may be captured.  The copies read library-owned pinned copies of those
+ *     tables (kept for the life of the process, 64 MiB in total), created by an
+ *     uncaptured call: make one call with the same arguments before capturing,
+ *     otherwise the captured call fails with SKMP_EINVAL.  A graph replays the
+ *     same pointers: keep the captured buffers (including the workspace) alive
+ *     and unchanged in size.
  */
 #ifndef SKETCHMP_H
 #define SKETCHMP_H
@@ -147,6 +157,8 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  *            series s to its nearest admissible neighbour; +inf if none.
  *   I        device out, k x N int64, row stride ldp: that neighbour's index
  *            within the series (0-based), -1 if none.
+ *            The last m - 1 columns of every series (no subsequence starts
+ *            there) are not written in P or I.
  * Subsequence statistics use the population sigma; a subsequence whose sigma
  * is <= 1e-10 * max|R^(g)| over its series is flat and normalises to the zero
  * vector (dist(flat, flat) = 0, dist(flat, other) = sqrt(m)).  Reported P values

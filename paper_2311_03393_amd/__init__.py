@@ -119,7 +119,9 @@ _ws_cache = {}
 
 
 def _workspace(torch, nbytes: int, device):
-    key = (str(device),)
+    # one cached scratch buffer per (device, stream): calls on one stream run in
+    # order, calls on different streams may overlap and must not share scratch
+    key = (str(device), torch.cuda.current_stream().cuda_stream)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)

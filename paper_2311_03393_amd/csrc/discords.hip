@@ -218,7 +218,7 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
     return SKMP_ENOMEM;
   }
   hipStream_t stream_ = static_cast<hipStream_t>(stream);
-  SKMP_CHECK_HIP(hipMemcpyAsync(ser, ds.data(), sizeof(DiscSeries) * n_series, hipMemcpyHostToDevice, stream_));
+  if (int rc = upload_async(ser, ds.data(), sizeof(DiscSeries) * n_series, stream_)) return rc;
   StageTimer tm(SKMP_TIMER_DISCORDS, stream_);
   const int64_t outs = std::max<int64_t>(n_series * top_k, n_series);
   hipLaunchKernelGGL(init_outputs, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream_, st);

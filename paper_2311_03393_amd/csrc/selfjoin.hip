@@ -172,28 +172,54 @@ __device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned
 
 
 // Exact FP64 seeds C(rr, j0 + q) = sum_x (r[rr+x] - mu[rr]) (r[j0+q+x] - mu[j0+q])
-// for the C consecutive diagonals of a lane.  Written as
-// sum_x a_x r[j0+q+x] - mu[j0+q] sum_x a_x with a_x = r[rr+x] - mu[rr], so the
-// r values of the C diagonals stream through one sliding window (about 3 m
-// loads instead of (C + 1) m).  Diagonals that end before row rr (j0 + q >=
-// n_sub) read clamped addresses and are zeroed.
+// for the C consecutive diagonals of every lane of the wave at step u: lane t
+// is on row rr = max(u - t, 0) and its first diagonal starts at column
+// j0 = rr + db + t C.  Written as sum_x a_x r[j0+q+x] - mu[j0+q] sum_x a_x with
+// a_x = r[rr+x] - mu[rr], so the r values of the C diagonals stream through
+// one sliding window.  The 64 rows span at most 64 + m samples and the 64 C
+// diagonals at most 64 C + m, so chunks of MCH samples of both ranges are
+// first staged in LDS with coalesced loads (stage: 64 + MCH + 64 C + MCH
+// doubles); every lane then reads its windows from LDS.  Diagonals that end
+// before row rr (j0 + q >= n_sub) read clamped samples and are zeroed.  Must be
+// called by all 64 lanes with the same u.
 template <int C>
-__device__ __forceinline__ void exact_seeds(const double* __restrict__ r, const double* __restrict__ mu, int rr, int j0,
-                                            int n_sub, int nlast, int m, double (&acc)[C]) {
+constexpr int seed_chunk() { return (128 / C) * C; }
+template <int C>
+constexpr int seed_stage_len() { return 64 + seed_chunk<C>() + 64 * C + seed_chunk<C>(); }
+
+template <int C>
+__device__ __forceinline__ void exact_seeds(double* stage, const double* __restrict__ r, const double* __restrict__ mu,
+                                            int u, int db, int t, int n_sub, int nlast, int m, double (&acc)[C]) {
+  constexpr int MCH = seed_chunk<C>();
+  double* srow = stage;
+  double* scol = stage + 64 + MCH;
+  const int rr = max(u - t, 0);
+  const int j0 = rr + db + t * C;
+  const int rbase = max(u - 63, 0);
+  const int cbase = u + db;
+  const int ro = rr - rbase;   // [0, 64)
+  const int co = j0 - cbase;   // [0, 63 C]
   const double mr = mu[rr];
   double sa = 0.0;
 #pragma unroll
   for (int q = 0; q < C; ++q) acc[q] = 0.0;
-  for (int x0 = 0; x0 < m; x0 += C) {
-    double w[2 * C - 1];
+  for (int x0 = 0; x0 < m; x0 += MCH) {
+    __syncthreads();  // the previous chunk (or the caller's use of the stage) is done
+    for (int i = t; i < 64 + MCH; i += 64) srow[i] = r[min(rbase + x0 + i, nlast)];
+    for (int i = t; i < 64 * C + MCH; i += 64) scol[i] = r[min(cbase + x0 + i, nlast)];
+    __syncthreads();
+    const int xe = min(MCH, m - x0);
+    for (int xx = 0; xx < xe; xx += C) {
+      double w[2 * C - 1];
 #pragma unroll
-    for (int k = 0; k < 2 * C - 1; ++k) w[k] = r[min(j0 + x0 + k, nlast)];
+      for (int k = 0; k < 2 * C - 1; ++k) w[k] = scol[co + xx + k];
 #pragma unroll
-    for (int dx = 0; dx < C; ++dx) {
-      const double a = (x0 + dx < m) ? r[rr + x0 + dx] - mr : 0.0;
-      sa += a;
+      for (int dx = 0; dx < C; ++dx) {
+        const double a = (xx + dx < xe) ? srow[ro + xx + dx] - mr : 0.0;
+        sa += a;
 #pragma unroll
-      for (int q = 0; q < C; ++q) acc[q] = fma(a, w[dx + q], acc[q]);
+        for (int q = 0; q < C; ++q) acc[q] = fma(a, w[dx + q], acc[q]);
+      }
     }
   }
 #pragma unroll
@@ -307,6 +333,65 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
   }
 }
 
+// Flush of the LDS partials after the block of TL steps that starts at step
+// u0.  rowk[x] holds row u0 - 63 + x (x < TL + 64), colk[x] column u0 + db + x
+// (x < TL + 64 C).  After the block, rows x < TL and columns x < TL have all
+// their cells of this unit (the one-lane skew and the band width bound the
+// rows and columns a later step can touch), so they go to the global key
+// arrays; unless this was the unit's last block, the other 64 rows and 64 C
+// columns move down by TL and keep accumulating in the next block.  Every row
+// and column of a unit is thereby flushed once.  to_global(key, delta) forms
+// the global 64-bit key of a local key whose partner lies delta diagonals up.
+template <int C, int TL, typename K, typename G>
+__device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_sub, int t,
+                                            unsigned long long* gro, unsigned long long* gco, G to_global) {
+  constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
+  constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
+  constexpr uint32_t LMAX = (64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u);
+  __syncthreads();
+  K kr[RPL], kc[CPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) kr[q] = (t + 64 * q < NROW) ? rowk[t + 64 * q] : K(0);
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) kc[q] = (t + 64 * q < NCOL) ? colk[t + 64 * q] : K(0);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int x = t + 64 * q;
+    if (x < NROW) {
+      if (x >= NROW - TL) rowk[x] = K(0);                   // [64, NROW): cleared
+      if (x >= TL) rowk[x - TL] = last ? K(0) : kr[q];     // [TL, NROW) -> [0, 64)
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int x = t + 64 * q;
+    if (x < NCOL) {
+      if (x >= NCOL - TL) colk[x] = K(0);                   // [64 C, NCOL): cleared
+      if (x >= TL) colk[x - TL] = last ? K(0) : kc[q];     // [TL, NCOL) -> [0, 64 C)
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int xl = t + 64 * q;
+    const int x = u0 - 63 + xl;
+    if (kr[q] && (last || xl < TL) && xl < NROW && x >= 0 && x < n_sub) {
+      const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
+      atomicMax(gro + x, to_global(kr[q], delta));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int xl = t + 64 * q;
+    const int j = u0 + db + xl;
+    if (kc[q] && (last || xl < TL) && xl < NCOL && j < n_sub) {
+      const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
+      atomicMax(gco + j, to_global(kc[q], delta));
+    }
+  }
+  __syncthreads();
+}
+
 template <int C, int TL, int PD, int WPE, bool CL>
 __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   constexpr int NROW = TL + 64;
@@ -316,6 +401,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   static_assert(TL % C == 0, "tile length must be a multiple of C");
   __shared__ unsigned long long rowk[NROW];
   __shared__ unsigned long long colk[NCOL];
+  __shared__ double sseed[seed_stage_len<C>()];
   const int t = threadIdx.x;
   for (int x = t; x < NROW; x += 64) rowk[x] = 0ull;
   for (int x = t; x < NCOL; x += 64) colk[x] = 0ull;
@@ -365,7 +451,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
 
     LaneState<C> ls;
     // exact FP64 seeds at the strip start: lane t's first row is u_begin - t
-    exact_seeds<C>(r, mu, max(u_begin - t, 0), max(u_begin - t, 0) + db + t * C, n_sub, (int)sp.n - 1, m, ls.Cq);
+    exact_seeds<C>(sseed, r, mu, u_begin, db, t, n_sub, (int)sp.n - 1, m, ls.Cq);
     // column window: columns J + q (q < C-1) in slots q, J = u_begin + db + t (C-1)
     {
       const int J = u_begin + db + t * (C - 1);
@@ -398,38 +484,10 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
         for (int q = 0; q < C - 1; ++q)
           atomicMax(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
       }
-      __syncthreads();
-      // flush rows [u0 - 63, u0 + TL) and columns [u0 + db, u0 + db + NCOL):
-      // read every partial first, clear LDS, then issue the global atomics
-      constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
-      unsigned long long kr[RPL], kc[CPL];
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) kr[q] = (t + 64 * q < NROW) ? rowk[t + 64 * q] : 0ull;
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) kc[q] = (t + 64 * q < NCOL) ? colk[t + 64 * q] : 0ull;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q)
-        if (t + 64 * q < NROW) rowk[t + 64 * q] = 0ull;
-#pragma unroll
-      for (int q = 0; q < CPL; ++q)
-        if (t + 64 * q < NCOL) colk[t + 64 * q] = 0ull;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int x = u0 - 63 + t + 64 * q;
-        if (kr[q] && x >= 0 && x < n_sub) {
-          const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
-          atomicMax(gro + x, (kr[q] & ~GMAX) | (GMAX - (unsigned long long)delta));
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int j = u0 + db + t + 64 * q;
-        if (kc[q] && j < n_sub) {
-          const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
-          atomicMax(gco + j, (kc[q] & ~GMAX) | (GMAX - (unsigned long long)delta));
-        }
-      }
-      __syncthreads();
+      flush_block<C, TL>(rowk, colk, last, u0, db, n_sub, t, gro, gco,
+                         [GMAX](unsigned long long key, int delta) {
+                           return (key & ~GMAX) | (GMAX - (unsigned long long)delta);
+                         });
     }
   }
 }
@@ -541,6 +599,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
   __shared__ uint32_t rowk[NROW];
   __shared__ uint32_t colk[NCOL];
+  __shared__ double sseed[seed_stage_len<C>()];
   const int t = threadIdx.x;
   for (int x = t; x < NROW; x += 64) rowk[x] = 0u;
   for (int x = t; x < NCOL; x += 64) colk[x] = 0u;
@@ -589,7 +648,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     LaneStateF<C> ls;
     {  // exact FP64 seeds, rounded once to FP32
       double acc[C];
-      exact_seeds<C>(r, mu, max(u_begin - t, 0), max(u_begin - t, 0) + db + t * C, n_sub, (int)sp.n - 1, m, acc);
+      exact_seeds<C>(sseed, r, mu, u_begin, db, t, n_sub, (int)sp.n - 1, m, acc);
 #pragma unroll
       for (int q = 0; q < C; ++q) ls.Cq[q] = (float)acc[q];
     }
@@ -616,38 +675,16 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
         sjf_run_groups<C, true, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
       else
         sjf_run_groups<C, false, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
-      if (u0 + TL >= u_end) {
+      const bool last = (u0 + TL >= u_end);
+      if (last) {
 #pragma unroll
         for (int q = 0; q < C - 1; ++q) atomicMax(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
       }
-      __syncthreads();
-      for (int xr = t; xr < NROW; xr += 64) {
-        const uint32_t key = rowk[xr];
-        if (key) {
-          rowk[xr] = 0u;
-          const int x = u0 - 63 + xr;
-          if (x >= 0 && x < n_sub) {
-            const int delta = db + (int)(LMAX - (key & LMAX));
-            const double v = (double)__uint_as_float(key & ~LMAX);
-            const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-            atomicMax(gro + x, (kb & ~GMAX) | (GMAX - (unsigned long long)delta));
-          }
-        }
-      }
-      for (int xr = t; xr < NCOL; xr += 64) {
-        const uint32_t key = colk[xr];
-        if (key) {
-          colk[xr] = 0u;
-          const int j = u0 + db + xr;
-          if (j < n_sub) {
-            const int delta = db + (int)(LMAX - (key & LMAX));
-            const double v = (double)__uint_as_float(key & ~LMAX);
-            const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-            atomicMax(gco + j, (kb & ~GMAX) | (GMAX - (unsigned long long)delta));
-          }
-        }
-      }
-      __syncthreads();
+      flush_block<C, TL>(rowk, colk, last, u0, db, n_sub, t, gro, gco, [GMAX](uint32_t key, int delta) {
+        const double v = (double)__uint_as_float(key & ~LMAX);
+        const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+        return (kb & ~GMAX) | (GMAX - (unsigned long long)delta);
+      });
     }
   }
 }
@@ -906,6 +943,19 @@ static const Fp64Variant& fp64_variant() {
   return kFp64Variants[idx];
 }
 
+// Work-unit strip.  FP64 needs no refresh (SKMP_STRIP overrides its strip
+// for tuning).  FP32 restarts from an exact FP64 seed at every unit start, so
+// its strip is the refresh period.
+static int strip_for(int prec, int refresh) {
+  static const int target = [] {
+    const char* e = getenv("SKMP_STRIP");
+    const int v = e ? atoi(e) : 0;
+    return (v >= 256 && v <= (1 << 20)) ? v : 0;
+  }();
+  if (prec != SKMP_FP32) return target ? target : DEFAULT_STRIP;
+  return refresh > 0 ? refresh : DEFAULT_REFRESH_FP32;
+}
+
 static int grid_for(const void* kernel, int block, size_t lds) {
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -931,7 +981,7 @@ extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets
   PlanInfo pl;
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
-  const int strip = (prec == SKMP_FP32) ? DEFAULT_REFRESH_FP32 : DEFAULT_STRIP;
+  const int strip = strip_for(prec, 0);
   if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, mfma ? 0 : var.C, strip, pl, false) != SKMP_OK) return 0;
   Carve cv(nullptr, 0);
   SJBuffers b;
@@ -964,8 +1014,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   const int kact = gl.count;
   PlanInfo pl;
   const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
-  // FP32: strips restart from an exact FP64 seed, so the strip is the refresh period
-  const int strip = (prec == SKMP_FP32) ? (refresh > 0 ? refresh : DEFAULT_REFRESH_FP32) : DEFAULT_STRIP;
+  const int strip = strip_for(prec, refresh);
   int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true);
   if (rc) return rc;
   Carve cv(workspace, ws_bytes);
@@ -976,7 +1025,7 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
     return SKMP_ENOMEM;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SKMP_CHECK_HIP(hipMemcpyAsync(b.plan, pl.sp.data(), sizeof(SeriesPlan) * n_series, hipMemcpyHostToDevice, st));
+  if (int rc = upload_async(b.plan, pl.sp.data(), sizeof(SeriesPlan) * n_series, st)) return rc;
 
   SJState s;
   s.R = R;

@@ -270,8 +270,12 @@ static size_t stats_workspace(int64_t d, int64_t n_series, int64_t total_chunks,
 static int run_dimstats(const void* T, int32_t dtype, int64_t ldt, int64_t d, int64_t n_series,
                         const int64_t* offsets_host, const std::vector<int64_t>& cpre, const StatsBuffers& b,
                         double* stats_out, bool check, hipStream_t st) {
-  SKMP_CHECK_HIP(hipMemcpyAsync(b.offsets_dev, offsets_host, sizeof(int64_t) * (n_series + 1), hipMemcpyHostToDevice, st));
-  SKMP_CHECK_HIP(hipMemcpyAsync(b.cprefix_dev, cpre.data(), sizeof(int64_t) * (n_series + 1), hipMemcpyHostToDevice, st));
+  if (check && stream_capturing(st)) {
+    set_error("the non-finite input check reads its result back on the host and cannot run under graph capture");
+    return SKMP_EINVAL;
+  }
+  if (int rc = upload_async(b.offsets_dev, offsets_host, sizeof(int64_t) * (n_series + 1), st)) return rc;
+  if (int rc = upload_async(b.cprefix_dev, cpre.data(), sizeof(int64_t) * (n_series + 1), st)) return rc;
   if (check) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, st, b.nonfinite, 0u, (int64_t)1);
   const int64_t total_chunks = cpre[n_series];
   dim3 grid((unsigned)(d * total_chunks)), block(STAT_THREADS);
@@ -356,7 +360,7 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
     return SKMP_ENOMEM;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SKMP_CHECK_HIP(hipMemcpyAsync(S_dev, S.data(), sizeof(double) * S.size(), hipMemcpyHostToDevice, st));
+  if (int rc2 = upload_async(S_dev, S.data(), sizeof(double) * S.size(), st)) return rc2;
   StageTimer tm(SKMP_TIMER_SKETCH, st);
   rc = run_dimstats(T, dtype, ldt, d, n_series, offsets, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
@@ -428,7 +432,7 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint64_t mask = 0;
   if (d_add) {
-    SKMP_CHECK_HIP(hipMemcpyAsync(Sa_dev, Sa.data(), sizeof(double) * Sa.size(), hipMemcpyHostToDevice, st));
+    if (int rc2 = upload_async(Sa_dev, Sa.data(), sizeof(double) * Sa.size(), st)) return rc2;
     rc = run_dimstats(T_add, dtype, ldt, d_add, 1, offs, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
     if (rc) return rc;
     if (dtype == SKMP_F64)
@@ -440,9 +444,9 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
         if (Sa[(size_t)g * d_add + j] != 0.0) mask |= 1ull << g;
   }
   if (d_rem) {
-    SKMP_CHECK_HIP(hipMemcpyAsync(Sr_dev, Sr.data(), sizeof(double) * Sr.size(), hipMemcpyHostToDevice, st));
+    if (int rc2 = upload_async(Sr_dev, Sr.data(), sizeof(double) * Sr.size(), st)) return rc2;
     if (!d_add)
-      SKMP_CHECK_HIP(hipMemcpyAsync(sb.offsets_dev, offs, sizeof(offs), hipMemcpyHostToDevice, st));
+      if (int rc2 = upload_async(sb.offsets_dev, offs, sizeof(offs), st)) return rc2;
     if (dtype == SKMP_F64)
       launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, Sr_dev, k, R, ldr, -1, st);
     else

@@ -178,6 +178,11 @@ class StageTimer {
 };
 
 // -------------------------------------------------------- host helpers
+// True while ``st`` is being captured into a HIP graph.
+bool stream_capturing(hipStream_t st);
+// Host-to-device copy of a small immutable host table, safe under graph
+// capture (the source is served from a library-owned pinned copy).
+int upload_async(void* dst, const void* src, size_t bytes, hipStream_t st);
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S);
 
 // MFMA self-join (selfjoin_mixed.hip): tile edge, units per row panel, LDS bytes

@@ -1,7 +1,8 @@
 // Per-stage HIP-event timing (off unless enabled).  When enabled, every launch
 // of a timed stage is bracketed by two events recorded on the stream the
 // stage runs on; skmp_timing_read waits for the events and sums the elapsed
-// times, so the figures are the stages' own device durations.
+// times, so the figures are the stages' own device durations.  Launches made
+// while the stream is being captured into a graph are not timed.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -25,12 +26,17 @@ int64_t g_n[SKMP_TIMER_COUNT];
 StageTimer::StageTimer(int which, hipStream_t st) : which_(which), st_(st) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on || which < 0 || which >= SKMP_TIMER_COUNT) return;
+  if (stream_capturing(st)) return;  // events inside a graph would time the capture, not a run
   if (hipEventCreate(&a_) != hipSuccess) return;
   if (hipEventCreate(&b_) != hipSuccess) {
     (void)hipEventDestroy(a_);
     return;
   }
-  if (hipEventRecord(a_, st_) != hipSuccess) return;
+  if (hipEventRecord(a_, st_) != hipSuccess) {
+    (void)hipEventDestroy(a_);
+    (void)hipEventDestroy(b_);
+    return;
+  }
   live_ = true;
 }
 

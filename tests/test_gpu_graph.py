@@ -1,0 +1,104 @@
+"""HIP graph capture of the whole hot path (sketch, self-join, top discords).
+
+One eager call per argument set comes first (it creates the library's pinned
+copies of the host tables); the same sequence is then captured into a graph
+and replayed several times, with eager work and an in-place change of the
+input between replays.  Every replay must reproduce the eager results bit for
+bit (the kernels are deterministic: maxima of packed keys, FP64 polish).
+The eager results themselves are held to the oracle by the parity tests.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_graph_replays_match_eager(prec):
+    import torch
+    import paper_2311_03393_amd as skmp
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda:0")
+    m, excl, k, top_k = 32, 8, 4, 5
+    lens = [900, 2600, 1500]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    N = int(offsets[-1])
+    _say("graph", prec, lens, m, k)
+    T_a = np.concatenate([datagen.tiny_series(300 + q, 6, L) for q, L in enumerate(lens)], axis=1)
+    T_b = np.concatenate([datagen.tiny_series(400 + q, 6, L) for q, L in enumerate(lens)], axis=1)
+    d = T_a.shape[0]
+
+    T = torch.from_numpy(np.ascontiguousarray(T_a)).to(dev)
+    R = torch.empty((k, N), dtype=torch.float64, device=dev)
+    stats = torch.empty((len(lens), d, 2), dtype=torch.float64, device=dev)
+    P = torch.empty((k, N), dtype=torch.float64, device=dev)
+    I = torch.empty((k, N), dtype=torch.int64, device=dev)
+    ws = torch.empty(skmp.mp_selfjoin_workspace(offsets, k, m, prec), dtype=torch.uint8, device=dev)
+    out = (torch.empty((len(lens), top_k), dtype=torch.int64, device=dev),
+           torch.empty((len(lens), top_k), dtype=torch.int32, device=dev),
+           torch.empty((len(lens), top_k), dtype=torch.float64, device=dev),
+           torch.empty((len(lens),), dtype=torch.int32, device=dev))
+
+    def step():
+        skmp.sketch_build(T, offsets, k, "gauss", 11, R=R, stats=stats)
+        skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec, P=P, I=I, workspace=ws)
+        skmp.top_discords(P, offsets, k, m, top_k, out=out)
+
+    # P and I are defined on the n - m + 1 window columns of every series only
+    win = torch.from_numpy(np.concatenate([np.arange(offsets[s], offsets[s + 1] - m + 1)
+                                           for s in range(len(lens))]))
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return [x.cpu().clone() for x in (R, P[:, win.to(dev)], I[:, win.to(dev)]) + out]
+
+    def same(a, b):
+        for x, y in zip(a, b):
+            if x.dtype.is_floating_point:
+                assert torch.equal(torch.nan_to_num(x, nan=-7.0), torch.nan_to_num(y, nan=-7.0))
+            else:
+                assert torch.equal(x, y)
+
+    # eager references for both inputs
+    step()
+    ref_a = snapshot()
+    T.copy_(torch.from_numpy(T_b).to(dev))
+    step()
+    ref_b = snapshot()
+    T.copy_(torch.from_numpy(T_a).to(dev))
+    torch.cuda.synchronize()
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()  # eager call on the capture stream before capturing
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    torch.cuda.synchronize()
+
+    for rep, (src, ref) in enumerate([(T_a, ref_a), (T_a, ref_a), (T_b, ref_b), (T_a, ref_a)]):
+        # eager work between replays: overwrite every output, then restore the input
+        P.fill_(123.0)
+        I.fill_(-9)
+        R.fill_(0.5)
+        for x in out:
+            x.fill_(3)
+        T.copy_(torch.from_numpy(src).to(dev))
+        torch.cuda.synchronize()
+        g.replay()
+        got = snapshot()
+        _say("replay", rep, "top", got[3][0].tolist())
+        same(got, ref)
+    del g

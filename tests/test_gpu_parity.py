@@ -39,10 +39,10 @@ def _to_dev(torch, T, dev):
     return torch.from_numpy(np.ascontiguousarray(T)).to(dev)
 
 
-def _run_selfjoin(torch, dev, R_np, offsets, k, m, excl, prec="fp64"):
+def _run_selfjoin(torch, dev, R_np, offsets, k, m, excl, prec="fp64", refresh=0):
     import paper_2311_03393_amd as skmp
     R = _to_dev(torch, R_np, dev)
-    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec)
+    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec, refresh=refresh)
     torch.cuda.synchronize()
     return P.cpu().numpy(), I.cpu().numpy()
 
@@ -422,3 +422,24 @@ def test_selfjoin_mixed_batched_flat_and_top10(dev, c_oracle, prec):
             got = [(int(i), int(g), float(v)) for i, g, v in zip(idx[s].cpu(), grp[s].cpu(), score[s].cpu())][:len(ref)]
             assert int(nf[s]) == len(ref)
             discords_equivalent(got, ref, A_o, m, tol)
+
+
+@pytest.mark.parametrize("refresh", [100, 512, 4096])
+def test_selfjoin_fp32_refresh_periods(dev, c_oracle, refresh):
+    """FP32 with a refresh period that is not a multiple of the tile length (a
+    unit is one period), one that re-seeds inside a unit, and one longer than
+    the series (no re-seed at all)."""
+    import torch
+    from tests.helpers import mixed_tol
+    n, m, excl, k, seed = 5200, 48, 12, 2, 21
+    _say("fp32 refresh", refresh, n, m)
+    T = datagen.tiny_series(seed, 4, n)
+    R_np, _, _, _ = O.build(T, "gauss", k, seed)
+    P, I = _run_selfjoin(torch, dev, R_np, [0, n], k, m, excl, prec="fp32", refresh=refresh)
+    n_sub = n - m + 1
+    tol = mixed_tol(m)
+    for g in range(k):
+        P_o, _ = c_oracle.profile(R_np[g], m, excl)
+        ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
+        assert ok.all(), f"refresh {refresh} group {g}: {np.count_nonzero(~ok)} rows out of tolerance, max err {err}"
+        check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
