@@ -6,7 +6,9 @@
 //             score); non-finite scores (no admissible neighbour) are dropped.
 //   select:   one 1024-thread block per series runs all K greedy passes: each
 //             pass takes the first maximum of A among windows not masked by
-//             earlier picks (kept in LDS); a pick masks |i - i*| < halfwidth.
+//             earlier picks; a pick masks |i - i*| < halfwidth.  Maxima per
+//             block of windows (computed with A) make a pass a reduction over
+//             the blocks plus a re-scan of the few blocks the new mask touches.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -18,13 +20,21 @@
 
 namespace skmp {
 
-constexpr int DISC_CHUNK = 1 << 16;
-constexpr int DISC_THREADS = 256;
+// Windows per block maximum: a power of two >= 256, chosen per call so that
+// every series has at most SEL_LDS_BLOCKS blocks (they live in LDS during
+// the selection).
+constexpr int DISC_BLK_MIN_SHIFT = 8;
+constexpr int SEL_THREADS = 1024;
+constexpr int SEL_WAVES = SEL_THREADS / 64;
+constexpr int MAX_TOPK = 256;
+constexpr int SEL_LDS_BLOCKS = 4096;
 
 struct DiscSeries {
   int64_t col;
-  int64_t n_sub;       // 0 if the series is shorter than m
-  int64_t chunk_base;  // first chunk of this series
+  int64_t n_sub;     // 0 if the series is shorter than m
+  int64_t blk_base;  // first block maximum of this series
+  int32_t nblk;
+  int32_t pad_;
 };
 
 struct DiscState {
@@ -32,11 +42,13 @@ struct DiscState {
   int n_series;
   int top_k;
   int halfwidth;
+  int shift;  // log2 of the windows per block
+  int64_t total_blocks;
   double* A;
   int32_t* G;
-  double* cand_val;     // per chunk
-  int64_t* cand_idx;
-  int64_t* idx;         // outputs
+  double* bval;   // per block: max of A over the block (-inf if none)
+  int32_t* bidx;  // its first window (index within the series), -1 if none
+  int64_t* idx;   // outputs
   int32_t* group;
   double* score;
   int32_t* n_found;
@@ -46,20 +58,44 @@ __device__ __forceinline__ bool better(double v, int64_t i, double bv, int64_t b
   return v > bv || (v == bv && i < bi);
 }
 
-__global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__ P, int64_t ldp, int k,
-                                                      const DiscSeries* __restrict__ ser, int n_series, int64_t N,
-                                                      double* __restrict__ A, int32_t* __restrict__ G) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N) return;
-  int lo = 0, hi = n_series - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (ser[mid].col <= t) lo = mid; else hi = mid - 1;
+__device__ __forceinline__ void wave_best(double& v, int& i) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(v, off);
+    const int oi = __shfl_down(i, off);
+    if (better(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+    }
   }
-  const int64_t i = t - ser[lo].col;
-  double best = -INFINITY;
-  int32_t bg = -1;
-  if (i < ser[lo].n_sub) {
+}
+
+__device__ __forceinline__ int find_block_series(const DiscSeries* ser, int n, int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ser[mid].blk_base <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A[i] = max over groups of P[g][i], first group on ties, non-finite scores
+// dropped; one 256-thread block per block of 2^shift windows, which also
+// writes that block's maximum (first window on ties).
+__global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__ P, int64_t ldp, int k, DiscState st) {
+  __shared__ double wv[4];
+  __shared__ int wi[4];
+  const int64_t b = blockIdx.x;
+  const int s = find_block_series(st.ser, st.n_series, b);
+  const DiscSeries sr = st.ser[s];
+  const int64_t first = (b - sr.blk_base) << st.shift;
+  const int64_t last = min(first + ((int64_t)1 << st.shift), sr.n_sub);
+  double bv = -INFINITY;
+  int bi = INT_MAX;
+  for (int64_t i = first + threadIdx.x; i < last; i += 256) {
+    const int64_t t = sr.col + i;
+    double best = -INFINITY;
+    int32_t bg = -1;
     for (int g = 0; g < k; ++g) {
       const double v = P[(int64_t)g * ldp + t];
       if (isfinite(v) && v > best) {
@@ -67,75 +103,126 @@ __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__
         bg = g;
       }
     }
+    st.A[t] = best;
+    st.G[t] = bg;
+    if (best > -INFINITY && better(best, i, bv, bi)) {
+      bv = best;
+      bi = (int)i;
+    }
   }
-  A[t] = best;
-  G[t] = bg;
+  wave_best(bv, bi);
+  if ((threadIdx.x & 63) == 0) {
+    wv[threadIdx.x >> 6] = bv;
+    wi[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < 4; ++q)
+      if (better(wv[q], wi[q], bv, bi)) {
+        bv = wv[q];
+        bi = wi[q];
+      }
+    st.bval[b] = bv;
+    st.bidx[b] = bv > -INFINITY ? bi : -1;
+  }
 }
 
-constexpr int SEL_THREADS = 1024;
-constexpr int MAX_TOPK = 256;
-
+// One 1024-thread block per series runs the K greedy passes.  The block maxima
+// sit in LDS; a pass takes the best block (its maximum is the best unmasked
+// window: ties resolve to the smallest window, as blocks are in window order),
+// records it, and re-scans only the blocks that the new mask |i - i*| < h
+// touches, skipping windows masked by any pick so far.
 __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char sel_lds[];
+  double* sv = reinterpret_cast<double*>(sel_lds);
+  int* si = reinterpret_cast<int*>(sv + SEL_LDS_BLOCKS);
   __shared__ int64_t picks[MAX_TOPK];
-  __shared__ double wv[SEL_THREADS / 64];
-  __shared__ int64_t wi[SEL_THREADS / 64];
+  __shared__ double wv[SEL_WAVES];
+  __shared__ int wi[SEL_WAVES];
+  __shared__ double pv;
+  __shared__ int pi;
   const int s = blockIdx.x;
   const DiscSeries sr = st.ser[s];
-  const double* A = st.A + sr.col;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = sr.nblk;
   const int64_t h = st.halfwidth;
+  const int B = 1 << st.shift;
+  for (int b = tid; b < nb; b += SEL_THREADS) {
+    sv[b] = st.bval[sr.blk_base + b];
+    si[b] = st.bidx[sr.blk_base + b];
+  }
+  __syncthreads();
   int found = 0;
   for (int pass = 0; pass < st.top_k; ++pass) {
+    // best block
     double v = -INFINITY;
-    int64_t bi = INT64_MAX;
-    for (int64_t i = threadIdx.x; i < sr.n_sub; i += SEL_THREADS) {
-      const double x = A[i];
-      if (!(x > -INFINITY) || !better(x, i, v, bi)) continue;
-      bool masked = false;
-      for (int q = 0; q < pass; ++q) {
-        const int64_t p = picks[q];
-        masked |= (i - p < h) && (p - i < h);
+    int bi = INT_MAX;
+    for (int b = tid; b < nb; b += SEL_THREADS)
+      if (sv[b] > -INFINITY && better(sv[b], si[b], v, bi)) {
+        v = sv[b];
+        bi = si[b];
       }
-      if (!masked) {
-        v = x;
-        bi = i;
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_down(v, off);
-      const int64_t oi = __shfl_down(bi, off);
-      if (better(ov, oi, v, bi)) {
-        v = ov;
-        bi = oi;
-      }
-    }
-    if ((threadIdx.x & 63) == 0) {
-      wv[threadIdx.x >> 6] = v;
-      wi[threadIdx.x >> 6] = bi;
+    wave_best(v, bi);
+    if (lane == 0) {
+      wv[wave] = v;
+      wi[wave] = bi;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int q = 1; q < SEL_THREADS / 64; ++q)
+    if (tid == 0) {
+      for (int q = 1; q < SEL_WAVES; ++q)
         if (better(wv[q], wi[q], v, bi)) {
           v = wv[q];
           bi = wi[q];
         }
+      pv = v;
+      pi = bi;
       const int64_t o = (int64_t)s * st.top_k + pass;
       if (v > -INFINITY) {
         st.idx[o] = bi;
         st.group[o] = st.G[sr.col + bi];
         st.score[o] = v;
         picks[pass] = bi;
-      } else {
-        picks[pass] = INT64_MIN / 2;  // nothing left: masks nothing
       }
-      wv[0] = v;
     }
     __syncthreads();
-    if (!(wv[0] > -INFINITY)) break;
+    const double best = pv;
+    const int64_t ip = pi;
+    if (!(best > -INFINITY)) break;
     found = pass + 1;
+    if (pass + 1 == st.top_k) break;
+    // re-scan the blocks the new mask touches: wave w takes block r0 + w
+    const int b_lo = (int)(max<int64_t>(0, ip - h + 1) >> st.shift);
+    const int b_hi = (int)(min<int64_t>(sr.n_sub - 1, ip + h - 1) >> st.shift);
+    for (int r0 = b_lo; r0 <= b_hi; r0 += SEL_WAVES) {
+      const int b = r0 + wave;
+      if (b <= b_hi) {
+        const int64_t w0 = (int64_t)b << st.shift;
+        const int64_t w1 = min(w0 + B, sr.n_sub);
+        double x = -INFINITY;
+        int xi = INT_MAX;
+        for (int64_t i = w0 + lane; i < w1; i += 64) {
+          const double a = st.A[sr.col + i];
+          if (!(a > -INFINITY) || !better(a, i, x, xi)) continue;
+          bool masked = false;
+          for (int q = 0; q <= pass; ++q) {
+            const int64_t p = picks[q];
+            masked |= (i - p < h) && (p - i < h);
+          }
+          if (!masked) {
+            x = a;
+            xi = (int)i;
+          }
+        }
+        wave_best(x, xi);
+        if (lane == 0) {
+          sv[b] = x;
+          si[b] = x > -INFINITY ? xi : -1;
+        }
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) st.n_found[s] = found;
+  if (tid == 0) st.n_found[s] = found;
 }
 
 __global__ void init_outputs(DiscState st) {
@@ -149,17 +236,28 @@ __global__ void init_outputs(DiscState st) {
   if (t < st.n_series) st.n_found[t] = 0;
 }
 
-static void disc_plan(int64_t n_series, const int64_t* offsets, int32_t m, std::vector<DiscSeries>& ds,
-                      int64_t& chunks) {
+// Block size (log2) and per-series block ranges.
+static int disc_plan(int64_t n_series, const int64_t* offsets, int32_t m, std::vector<DiscSeries>& ds,
+                     int64_t& blocks) {
+  int64_t max_nsub = 0;
+  for (int64_t s = 0; s < n_series; ++s) {
+    const int64_t n = offsets[s + 1] - offsets[s];
+    max_nsub = std::max<int64_t>(max_nsub, n >= m ? n - m + 1 : 0);
+  }
+  int shift = DISC_BLK_MIN_SHIFT;
+  while ((max_nsub + (1ll << shift) - 1) >> shift > SEL_LDS_BLOCKS) ++shift;
   ds.resize(n_series);
-  chunks = 0;
+  blocks = 0;
   for (int64_t s = 0; s < n_series; ++s) {
     const int64_t n = offsets[s + 1] - offsets[s];
     ds[s].col = offsets[s];
     ds[s].n_sub = n >= m ? n - m + 1 : 0;
-    ds[s].chunk_base = chunks;
-    chunks += std::max<int64_t>(1, (ds[s].n_sub + DISC_CHUNK - 1) / DISC_CHUNK);
+    ds[s].blk_base = blocks;
+    ds[s].nblk = (int32_t)((ds[s].n_sub + (1ll << shift) - 1) >> shift);
+    ds[s].pad_ = 0;
+    blocks += ds[s].nblk;
   }
+  return shift;
 }
 
 }  // namespace skmp
@@ -170,14 +268,14 @@ extern "C" size_t top_discords_workspace(int64_t n_series, const int64_t* offset
   (void)k;
   if (n_series < 1 || !offsets || m < 1) return 0;
   std::vector<DiscSeries> ds;
-  int64_t chunks;
-  disc_plan(n_series, offsets, m, ds, chunks);
+  int64_t blocks;
+  disc_plan(n_series, offsets, m, ds, blocks);
   Carve cv(nullptr, 0);
   cv.take<DiscSeries>(n_series);
   cv.take<double>(offsets[n_series]);
   cv.take<int32_t>(offsets[n_series]);
-  cv.take<double>(chunks);
-  cv.take<int64_t>(chunks);
+  cv.take<double>(blocks);
+  cv.take<int32_t>(blocks);
   return cv.used + 256;
 }
 
@@ -193,11 +291,13 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   SKMP_REQUIRE(halfwidth >= 0, "halfwidth must be >= 0");
   SKMP_REQUIRE(offsets[0] == 0, "offsets[0] must be 0");
   for (int64_t s = 0; s < n_series; ++s) SKMP_REQUIRE(offsets[s + 1] >= offsets[s], "offsets must be non-decreasing");
+  for (int64_t s = 0; s < n_series; ++s)
+    SKMP_REQUIRE(offsets[s + 1] - offsets[s] < (int64_t)INT_MAX, "series too long");
   const int64_t N = offsets[n_series];
   SKMP_REQUIRE(ldp >= N, "ldp must be >= the total number of samples");
   std::vector<DiscSeries> ds;
-  int64_t chunks;
-  disc_plan(n_series, offsets, m, ds, chunks);
+  int64_t blocks;
+  const int shift = disc_plan(n_series, offsets, m, ds, blocks);
   Carve cv(workspace, ws_bytes);
   DiscSeries* ser = cv.take<DiscSeries>(n_series);
   DiscState st;
@@ -205,10 +305,12 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   st.n_series = (int)n_series;
   st.top_k = top_k;
   st.halfwidth = halfwidth > 0 ? halfwidth : m;
+  st.shift = shift;
+  st.total_blocks = blocks;
   st.A = cv.take<double>(N);
   st.G = cv.take<int32_t>(N);
-  st.cand_val = cv.take<double>(chunks);
-  st.cand_idx = cv.take<int64_t>(chunks);
+  st.bval = cv.take<double>(blocks);
+  st.bidx = cv.take<int32_t>(blocks);
   st.idx = idx;
   st.group = group;
   st.score = score;
@@ -222,10 +324,11 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   StageTimer tm(SKMP_TIMER_DISCORDS, stream_);
   const int64_t outs = std::max<int64_t>(n_series * top_k, n_series);
   hipLaunchKernelGGL(init_outputs, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream_, st);
-  if (N > 0)
-    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream_, P, ldp, k, ser,
-                       (int)n_series, N, st.A, st.G);
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), 0, stream_, st);
+  if (blocks > 0) {
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, stream_, P, ldp, k, st);
+    const size_t lds = (size_t)SEL_LDS_BLOCKS * (sizeof(double) + sizeof(int));
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), lds, stream_, st);
+  }
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }

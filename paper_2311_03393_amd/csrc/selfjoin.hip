@@ -63,16 +63,44 @@ __device__ __forceinline__ ChunkPos decode_chunk(const SJState& st, int64_t chun
   return c;
 }
 
-__global__ __launch_bounds__(256) void scale_kernel(SJState st) {
-  const ChunkPos c = decode_chunk(st, blockIdx.x);
-  const SeriesPlan& sp = st.plan[c.s];
-  const int64_t t = c.x0 + threadIdx.x;
-  const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
-  double v = (t >= 0 && t < sp.n) ? fabs(r[t]) : 0.0;
+// max |r| per (series, group) for the flat-window threshold.  A block walks
+// SCALE_CHUNKS consecutive chunks of 256 windows and keeps a running maximum
+// per thread; whenever the (series, group) changes (and at the end) the block
+// reduces it and issues one 64-bit atomic max, so an address receives a few
+// atomics instead of one per wave.
+constexpr int SCALE_CHUNKS = 32;
+
+__device__ __forceinline__ void scale_flush(double v, unsigned long long* dst, double* red) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
-  if ((threadIdx.x & 63) == 0 && v > 0.0)
-    atomicMax(reinterpret_cast<unsigned long long*>(st.scale) + (int64_t)c.s * st.groups.count + c.gi,
-              (unsigned long long)__double_as_longlong(v));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (b > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(b));
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void scale_kernel(SJState st) {
+  __shared__ double red[4];
+  const int64_t c0 = (int64_t)blockIdx.x * SCALE_CHUNKS;
+  const int64_t c1 = min(c0 + SCALE_CHUNKS, st.total_chunks);
+  double run = 0.0;
+  int64_t cur = -1;
+  for (int64_t chunk = c0; chunk < c1; ++chunk) {
+    const ChunkPos c = decode_chunk(st, chunk);
+    const int64_t key = (int64_t)c.s * st.groups.count + c.gi;
+    if (key != cur) {
+      if (cur >= 0) scale_flush(run, reinterpret_cast<unsigned long long*>(st.scale) + cur, red);
+      cur = key;
+      run = 0.0;
+    }
+    const SeriesPlan& sp = st.plan[c.s];
+    const int64_t t = c.x0 + threadIdx.x;
+    const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
+    if (t >= 0 && t < sp.n) run = fmax(run, fabs(r[t]));
+  }
+  if (cur >= 0) scale_flush(run, reinterpret_cast<unsigned long long*>(st.scale) + cur, red);
 }
 
 __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
@@ -1074,7 +1102,8 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   const dim3 cg((unsigned)pl.total_chunks);
   {
     StageTimer tm(SKMP_TIMER_SUBSTATS, st);
-    hipLaunchKernelGGL(scale_kernel, cg, fb, 0, st, s);
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((pl.total_chunks + SCALE_CHUNKS - 1) / SCALE_CHUNKS)), fb, 0, st,
+                       s);
     hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1), st, s);
   }
   SKMP_CHECK_HIP(hipGetLastError());

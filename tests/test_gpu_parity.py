@@ -224,6 +224,44 @@ def test_top_discords_matches_oracle_on_same_profiles(dev):
         assert got == ref
 
 
+@pytest.mark.parametrize("case", ["wide_mask", "exhaust", "long_series"])
+def test_top_discords_block_maxima_edge_cases(dev, case):
+    """The selection keeps maxima per block of windows (256 windows, more for
+    series above 2^20 windows): masks wider than a block, ties across block
+    boundaries, more picks than the series can hold, series without windows,
+    and a series long enough to need larger blocks."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    rng = np.random.default_rng({"wide_mask": 6, "exhaust": 7, "long_series": 8}[case])
+    if case == "wide_mask":
+        k, m, top_k, hw = 2, 700, 25, 0
+        lens = [30000, 500, 9000]
+    elif case == "exhaust":
+        k, m, top_k, hw = 3, 64, 200, 1000
+        lens = [5000, 2048, 63]
+    else:
+        k, m, top_k, hw = 2, 300, 20, 0
+        lens = [1_200_299]
+    _say("top discords", case, lens, m, top_k, hw)
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    P = np.full((k, offsets[-1]), np.nan)
+    for s, L in enumerate(lens):
+        a = offsets[s]
+        n_sub = max(L - m + 1, 0)
+        x = np.round(rng.random((k, n_sub)) * 8) / 2      # many exact ties, also across blocks
+        x[rng.random((k, n_sub)) < 0.02] = np.inf
+        P[:, a:a + n_sub] = x
+    idx, grp, score, nf = skmp.top_discords(_to_dev(torch, P, dev), offsets, k, m, top_k, halfwidth=hw)
+    torch.cuda.synchronize()
+    for s, L in enumerate(lens):
+        a = offsets[s]
+        n_sub = max(L - m + 1, 0)
+        ref = O.top_discords(P[:, a:a + n_sub], m, top_k, halfwidth=hw) if n_sub else []
+        got = [(int(i), int(g), float(v)) for i, g, v in zip(idx[s].cpu(), grp[s].cpu(), score[s].cpu())][:len(ref)]
+        assert int(nf[s]) == len(ref), (case, s, int(nf[s]), len(ref))
+        assert got == ref, (case, s)
+
+
 # ------------------------------------------------------------------ update
 def test_update_dims_matches_rebuild(dev, c_oracle):
     import torch
