@@ -4,17 +4,22 @@
 One step = the whole hot path over one batch of synthetic input already
 resident in HBM: sketch_build (per-dimension statistics + projection),
 mp_selfjoin (window statistics, self-join tiles, merge + FP64 polish) and
-top_discords (top 10).  Default workload: the water-treatment-shaped series,
-d = 51 (25 AR(1) sensors, 26 on/off actuators), n = 50,000, Gaussian sketch
-k = 8, m = 100, exclusion zone 25, three planted discords; its named
-precision is the FP32 path with an exact FP64 refresh every 256 rows.
+top_discords (top 10 per series).  Default workload: the water-treatment-shaped
+series, d = 51 (25 AR(1) sensors, 26 on/off actuators), n = 50,000, Gaussian
+sketch k = 8, m = 100, exclusion zone 25, three planted discords; its named
+precision is the FP32 path with an exact FP64 refresh every 256 rows.  Other
+workloads: c0 (small FP64 case), c2 (transportation-shaped, d = 1024,
+n = 131,072, m = 288), c3 (4096 merchant-shaped series, d = 32, lengths
+U[2048, 65536], FP32 input, k = 4, m = 64, generated on the GPU), c4 (d = 256,
+n = 2^20, k = 32, m = 256).
 
-Metric: matrix-profile cells per second, cells = k * n^2 / 2 per step.
-Prints ONE JSON line.  ``value`` is the named precision's throughput over the
-K timed steps; ``paths`` repeats the measurement for the FP64 path (and any
-other precision asked for) on the same input.  ``roofline`` covers the named
-path's tile kernel, timed with HIP events on the library's stream;
-``cpu_baseline`` times the CPU oracle on a bounded sample of rows.
+Metric: matrix-profile cells per second, cells = k * n^2 / 2 per series per
+step.  Prints ONE JSON line.  ``value`` is the named precision's throughput
+over the K timed steps; ``paths`` repeats the measurement for the FP64 path
+(and any other precision asked for) on the same input, with each path's error
+against the FP64 path.  ``roofline`` covers the named path's tile kernel,
+timed with HIP events on the library's stream; ``cpu_baseline`` times the CPU
+oracle on a bounded sample of rows.
 """
 from __future__ import annotations
 
@@ -31,8 +36,17 @@ if ROOT not in sys.path:
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-ops/s
 # (FP64 FMA is full rate; FP32 without packed math issues at the same rate)
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
-OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalisation) + 2 MAX (row, column)
-NAMED = {"c0": ("fp64", 0), "c1": ("fp32", 256), "c2": ("bf16x3", 0), "c4": ("fp16x3", 0)}
+OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MAX (row, column)
+NAMED = {"c0": ("fp64", 0), "c1": ("fp32", 256), "c2": ("bf16x3", 0), "c3": ("fp32", 256), "c4": ("fp16x3", 0)}
+DESCR = {
+    "c0": "random-walk+sine d=8 n=4096 sum sketch k=1 m=64 excl=16",
+    "c1": "water-treatment-shaped d=51 n=50000 gaussian k=8 m=100 excl=25",
+    "c2": "transportation-shaped d=1024 n=131072 gaussian k=16 m=288 excl=72",
+    "c3": "merchant-shaped batch 4096 series d=32 L~U[2048,65536] fp32 input gaussian k=4 m=64 excl=16",
+    "c4": "random-walk+sine d=256 n=1048576 gaussian k=32 m=256 excl=64",
+}
+KERNELS = {"fp64": "sj_fp64_kernel<8,256,1,2,false>", "fp32": "sj_fp32_kernel<16,256,1,2>",
+           "bf16x3": "sj_mfma_kernel<BF16X3>", "fp16x3": "sj_mfma_kernel<FP16X3>"}
 
 
 def _parse():
@@ -40,7 +54,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16x3", "fp16x3"],
                     help="headline precision (default: the one the workload names)")
     ap.add_argument("--refresh", type=int, default=None,
@@ -63,33 +77,41 @@ def _valid_half_pairs(n_sub: int, excl: int) -> int:
     return L * (L + 1) // 2
 
 
-def _cpu_baseline(R_np, w, target_s: float):
-    """The plain-C FP64 brute-force oracle, timed on a bounded sample of rows."""
+def _cpu_baseline(R_host_series, w, target_s: float):
+    """The plain-C FP64 brute-force oracle, timed on a bounded sample of rows.
+
+    R_host_series: list of (series index, k x L host array).  Rows are drawn in
+    batches of 64 from random (series, group) pairs; the time per row of a
+    series is taken as proportional to its number of windows, and the full
+    profile's time is extrapolated from that rate."""
     import numpy as np
     from oracle import c_oracle
     c = c_oracle()
-    k, n = R_np.shape
-    n_sub = n - w.m + 1
     rng = np.random.default_rng(0)
-    c.profile(R_np[0], w.m, w.excl, rows=rng.choice(n_sub, 8, replace=False))   # warm-up
-    total_rows = 0
-    t0 = time.perf_counter()
-    g = 0
-    while time.perf_counter() - t0 < target_s and total_rows < k * n_sub:
-        rows = rng.choice(n_sub, 256, replace=False)
-        c.profile(R_np[g % k], w.m, w.excl, rows=rows)
-        total_rows += rows.size
-        g += 1
-    t = time.perf_counter() - t0
-    t_full = t * (k * n_sub) / total_rows
+    lens = w.lengths()
+    first = R_host_series[0][1]
+    c.profile(first[0], w.m, w.excl, rows=rng.choice(first.shape[1] - w.m + 1, 8, replace=False))  # warm-up
+    rows_done, win_rows, t = 0, 0.0, 0.0
+    while t < target_s:
+        s, Rs = R_host_series[int(rng.integers(len(R_host_series)))]
+        n_sub = Rs.shape[1] - w.m + 1
+        rows = rng.choice(n_sub, min(64, n_sub), replace=False)
+        t0 = time.perf_counter()
+        c.profile(Rs[int(rng.integers(w.k))], w.m, w.excl, rows=rows)
+        t += time.perf_counter() - t0
+        rows_done += rows.size
+        win_rows += rows.size * n_sub
+    sec_per_window_row = t / win_rows
+    n_sub_all = np.maximum(lens - w.m + 1, 0).astype(np.float64)
+    t_full = sec_per_window_row * w.k * float(np.sum(n_sub_all * n_sub_all))
     return {
         "value": w.cells() / t_full,
         "unit": "cells/s",
         "cores": c.threads(),
         "kind": "oracle",
-        "sample": f"{total_rows} of the {k * n_sub} profile rows (batches of 256 random rows over the {k} "
-                  f"groups), each a full O(n m) brute-force row; {t:.1f} s measured, full profile "
-                  f"extrapolated to {t_full:.0f} s",
+        "sample": f"{rows_done} profile rows (batches of 64 random rows of a random group of "
+                  f"{len(R_host_series)} series), each a full O(n m) brute-force row; {t:.1f} s measured, full "
+                  f"profile extrapolated to {t_full:.0f} s",
     }
 
 
@@ -100,6 +122,7 @@ def main() -> int:
         print("bench.py runs on one GPU only: the sketched self-join of one workload is measured on a single "
               "MI355X (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         return 2
+    import numpy as np
     import torch
 
     import datagen
@@ -110,27 +133,41 @@ def main() -> int:
     refresh = args.refresh if args.refresh is not None else (named_refresh if prec == named_prec else 0)
 
     dev = torch.device("cuda:0")
-    w = datagen.make(args.workload)
-    d, n = w.T.shape
-    n_sub = n - w.m + 1
-    T = torch.from_numpy(w.T).to(dev)
-    k = w.k
-    R = torch.empty((k, n), dtype=torch.float64, device=dev)
-    stats = torch.empty((1, d, 2), dtype=torch.float64, device=dev)
-    P = torch.empty((k, n), dtype=torch.float64, device=dev)
-    I = torch.empty((k, n), dtype=torch.int64, device=dev)
-    out = (torch.empty((1, 10), dtype=torch.int64, device=dev), torch.empty((1, 10), dtype=torch.int32, device=dev),
-           torch.empty((1, 10), dtype=torch.float64, device=dev), torch.empty((1,), dtype=torch.int32, device=dev))
+    if args.workload == "c3":
+        w, T = datagen.make_c3_device(torch, dev)
+    else:
+        w = datagen.make(args.workload)
+        T = torch.from_numpy(w.T).to(dev)
+    d, N = T.shape
+    k, m = w.k, w.m
+    offsets = w.offsets
+    n_series = len(offsets) - 1
+    lens = np.diff(offsets)
+    n_subs = lens - m + 1
+    R = torch.empty((k, N), dtype=torch.float64, device=dev)
+    stats = torch.empty((n_series, d, 2), dtype=torch.float64, device=dev)
+    P = torch.empty((k, N), dtype=torch.float64, device=dev)
+    I = torch.empty((k, N), dtype=torch.int64, device=dev)
+    out = (torch.empty((n_series, 10), dtype=torch.int64, device=dev),
+           torch.empty((n_series, 10), dtype=torch.int32, device=dev),
+           torch.empty((n_series, 10), dtype=torch.float64, device=dev),
+           torch.empty((n_series,), dtype=torch.int32, device=dev))
     cells = w.cells()
-    valid = k * _valid_half_pairs(n_sub, w.excl)
+    valid = k * sum(_valid_half_pairs(int(x), w.excl) for x in n_subs)
+    # window columns (P and I are defined there only)
+    wmask_h = np.zeros(N, dtype=bool)
+    for a, ns in zip(offsets[:-1], n_subs):
+        wmask_h[int(a):int(a) + int(ns)] = True
+    wmask = torch.from_numpy(wmask_h).to(dev)
+    profiles, picks = {}, {}
 
     def measure(pr: str, rf: int, steps: int, warmup: int):
-        ws = torch.empty(skmp.mp_selfjoin_workspace(w.offsets, k, w.m, pr), dtype=torch.uint8, device=dev)
+        ws = torch.empty(skmp.mp_selfjoin_workspace(offsets, k, m, pr), dtype=torch.uint8, device=dev)
 
         def step():
-            skmp.sketch_build(T, w.offsets, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R, stats=stats)
-            skmp.mp_selfjoin(R, w.offsets, k, w.m, w.excl, prec=pr, refresh=rf, P=P, I=I, workspace=ws)
-            skmp.top_discords(P, w.offsets, k, w.m, 10, out=out)
+            skmp.sketch_build(T, offsets, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R, stats=stats)
+            skmp.mp_selfjoin(R, offsets, k, m, w.excl, prec=pr, refresh=rf, P=P, I=I, workspace=ws)
+            skmp.top_discords(P, offsets, k, m, 10, out=out)
 
         for _ in range(warmup):
             step()
@@ -160,10 +197,12 @@ def main() -> int:
         t1 = time.perf_counter()
         skmp.timing_enable(False)
         stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
+        del ws, graph
         ms = (t1 - t0) * 1e3 / steps
         tiles_ms, tiles_n = stage["tiles"]
         tile_avg_s = tiles_ms / max(tiles_n, 1) * 1e-3
-        profiles[pr] = P[:, :n_sub].clone()
+        profiles[pr] = P[:, wmask].clone()
+        picks[pr] = out[0].cpu().clone()
         return {
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
@@ -179,10 +218,9 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    profiles = {}
     also = args.also
     if also is None:
-        also = "fp64" if args.workload in ("c4",) else "fp64,fp32,bf16x3,fp16x3"
+        also = "fp64" if args.workload in ("c3", "c4") else "fp64,fp32,bf16x3,fp16x3"
     head = measure(prec, refresh, args.steps, args.warmup)
     paths = {f"{prec}" + (f"_refresh{refresh}" if refresh else ""): head}
     for extra in [x for x in also.split(",") if x and x != prec]:
@@ -190,7 +228,7 @@ def main() -> int:
     if "fp64" in profiles:
         # error of every path against the FP64 path (itself held to the oracle at 1e-9 * 2 sqrt(m))
         ref = profiles["fp64"]
-        tol = 1e-3 * 2 * w.m ** 0.5
+        tol = 1e-3 * 2 * m ** 0.5
         for key, v in paths.items():
             got = profiles[v["precision"]]
             both = torch.isfinite(ref) & torch.isfinite(got)
@@ -201,8 +239,11 @@ def main() -> int:
                 "max_abs_dP2": float(sq.max()) if sq.numel() else 0.0,
                 "finite_pattern_equal": bool(torch.equal(torch.isfinite(ref), torch.isfinite(got))),
                 "tolerance_dP": tol,
-                "top10_equal": v["top10"] == paths[[x for x in paths if paths[x]["precision"] == "fp64"][0]]["top10"],
+                "top10_equal_all_series": bool(torch.equal(picks[v["precision"]], picks["fp64"])),
             }
+            del got, both, err, sq
+        del ref
+    profiles.clear()
 
     tile_avg_s = head["tile_kernel_ms"] * 1e-3
     achieved = OPS_PER_CELL * valid / tile_avg_s
@@ -213,8 +254,7 @@ def main() -> int:
         "unit": "Tops/s",
         "frac": achieved / VALU_LANE_OPS_PEAK,
         "traffic": None,
-        "kernel": {"fp64": "sj_fp64_kernel<8,256,1,2,false>", "fp32": "sj_fp32_kernel<16,256,1,2>"}.get(
-            prec, f"selfjoin tiles ({prec})"),
+        "kernel": KERNELS[prec],
         "per_launch": {"cells": valid, "ops_per_cell": OPS_PER_CELL, "avg_ms": head["tile_kernel_ms"],
                        "launches": head["tile_launches"]},
         "basis": "VALU issue: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 6 lane-ops (2 FMA, 2 MUL, 2 MAX) "
@@ -234,15 +274,17 @@ def main() -> int:
         "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec),
         "data": "synthetic",
         "graph": bool(args.graph),
-        "config": {"workload": (f"water-treatment-shaped d={d} n={n} gaussian k={k} m={w.m} excl={w.excl}"
-                                if args.workload == "c1" else f"{args.workload} d={d} n={n} k={k} m={w.m}"),
-                   "precision": prec, "refresh": refresh, "cells_per_step": cells, "valid_half_pairs": valid,
+        "config": {"workload": DESCR[args.workload], "precision": prec, "refresh": refresh,
+                   "n_series": n_series, "cells_per_step": cells, "valid_half_pairs": valid,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "paths": paths,
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = _cpu_baseline(R.cpu().numpy(), w, args.cpu_seconds)
+        rng = np.random.default_rng(1)
+        pick = rng.choice(n_series, size=min(n_series, 8), replace=False)
+        series = [(int(s), R[:, int(offsets[s]):int(offsets[s + 1])].cpu().numpy()) for s in pick]
+        result["cpu_baseline"] = _cpu_baseline(series, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)
     return 0
 

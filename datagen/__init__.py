@@ -28,6 +28,11 @@ Workload recipes (seeded numpy PCG64; data seed and sketch seed are recorded):
           16 dimensions (Section III-C).
 
 ``scale`` shrinks n (and the batch) so the same recipe yields small test cases.
+
+``make_c3_device`` draws the full-size ``c3`` batch (4.4e9 values) on a GPU
+with torch's seeded generator instead of numpy (same recipe; the values differ
+from ``make_c3``'s).  Checks that need the input on the host copy the series
+they use back from the device tensor.
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["Workload", "make", "random_walk_sine", "tiny_series", "CONFIGS"]
+__all__ = ["Workload", "make", "make_c3_device", "random_walk_sine", "tiny_series", "CONFIGS"]
 
 
 @dataclass
@@ -243,6 +248,65 @@ def make_c4(scale: float = 1.0, data_seed: int = 1004, sketch_seed: int = 2004) 
                     k=32, kind="gauss", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="fp16x3", planted=planted,
                     update={"T_add": np.ascontiguousarray(T_add), "add_ids": add_ids, "rem_ids": rem_ids})
+
+
+def make_c3_device(torch, device, scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
+                   n_series: Optional[int] = None):
+    """The c3 recipe drawn on ``device``: returns (Workload with T = None, T as a
+    d x N float32 device tensor).  Lengths, spiky series and spike positions come
+    from numpy (seeded); the Poisson counts from torch's generator seeded with
+    data_seed; the 5-tap box filter replicates each series' edge samples."""
+    rng = _rng(data_seed)
+    d, m = 32, 64
+    if n_series is None:
+        n_series = max(4, int(4096 * scale))
+    lo, hi = 2048, 65536
+    if scale < 1.0:
+        lo, hi = max(4 * m, int(lo * scale)), max(8 * m, int(hi * scale))
+    L = rng.integers(lo, hi + 1, size=n_series)
+    offsets = np.zeros(n_series + 1, np.int64)
+    offsets[1:] = np.cumsum(L)
+    N = int(offsets[-1])
+    n_spiky = max(1, int(np.ceil(0.01 * n_series)))
+    spiky = np.sort(rng.choice(n_series, size=n_spiky, replace=False))
+    planted, rows, cols = [], [], []
+    for s in spiky:
+        dim = int(rng.integers(0, d))
+        o = int(rng.integers(0, int(L[s]) - m))
+        pos = o + rng.choice(m, size=6, replace=False)
+        planted.append((int(s), dim, o, m))
+        rows.extend([dim] * 6)
+        cols.extend((offsets[s] + pos).tolist())
+    g = torch.Generator(device=device)
+    g.manual_seed(int(data_seed))
+    cnt = torch.empty((d, N), dtype=torch.float32, device=device)
+    for a in range(0, N, 1 << 26):  # chunks keep the rate tensor small
+        b = min(N, a + (1 << 26))
+        rate = torch.full((d, b - a), 3.0, dtype=torch.float32, device=device)
+        cnt[:, a:b] = torch.poisson(rate, generator=g)
+        del rate
+    if rows:
+        cnt[torch.tensor(rows, device=device), torch.tensor(cols, device=device)] += 20.0
+    # 5-tap box filter over the concatenation, then the two samples at either
+    # end of every series recomputed with that series' edge sample repeated
+    T = torch.empty_like(cnt)
+    T[:, 2:N - 2] = (cnt[:, 0:N - 4] + cnt[:, 1:N - 3] + cnt[:, 2:N - 2] + cnt[:, 3:N - 1] + cnt[:, 4:N]) / 5.0
+    first = torch.from_numpy(offsets[:-1]).to(device)
+    last = torch.from_numpy(offsets[1:] - 1).to(device)
+
+    def col(ix):
+        return cnt[:, ix]
+
+    x0, x1, x2, x3 = col(first), col(first + 1), col(first + 2), col(first + 3)
+    T[:, first] = (3 * x0 + x1 + x2) / 5.0
+    T[:, first + 1] = (2 * x0 + x1 + x2 + x3) / 5.0
+    y0, y1, y2, y3 = col(last), col(last - 1), col(last - 2), col(last - 3)
+    T[:, last] = (3 * y0 + y1 + y2) / 5.0
+    T[:, last - 1] = (2 * y0 + y1 + y2 + y3) / 5.0
+    del cnt
+    w = Workload("c3", None, offsets, np.arange(d, dtype=np.int64), k=4, kind="gauss", m=m, excl=m // 4,
+                 sketch_seed=sketch_seed, data_seed=data_seed, precision="fp32", planted=planted)
+    return w, T
 
 
 CONFIGS = {"c0": make_c0, "c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4}

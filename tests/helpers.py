@@ -65,3 +65,50 @@ def discords_equivalent(gpu_list, ora_list, A_ora, m, tol):
             ties += 1
         alive[max(0, i - m + 1):min(n_sub, i + m)] = False
     return ties
+
+
+def certified_top(c_oracle, R_np, m, excl, P_gpu, I_gpu, top_k):
+    """Exact greedy top-K without a full oracle profile.
+
+    U_g[i] = d(i, I_gpu[g, i]) is an upper bound of the exact P_g[i].  Rows are
+    taken in descending max_g U; their exact profiles are computed until every
+    greedy pick on exact values beats the largest bound of the rows not yet
+    computed.  Returns (top list, A_exact dict, U matrix).
+    """
+    k, n_sub = P_gpu.shape
+    rows = np.arange(n_sub)
+    U = np.stack([c_oracle.pair_dist(R_np[g], m, rows, I_gpu[g]) for g in range(k)])
+    U = np.where(I_gpu >= 0, U, -np.inf)
+    AU = U.max(axis=0)
+    order = np.argsort(-AU, kind="stable")
+    exact = {}
+    batch = 64
+    pos = 0
+    while True:
+        new = order[pos:pos + batch]
+        pos += len(new)
+        Pn = np.stack([c_oracle.profile(R_np[g], m, excl, rows=new)[0] for g in range(k)])
+        for q, i in enumerate(new):
+            col = Pn[:, q]
+            col = np.where(np.isfinite(col), col, -np.inf)
+            exact[int(i)] = (float(col.max()), int(np.argmax(col)))
+        tau_rows = order[pos:]
+        alive = np.ones(n_sub, bool)
+        picks = []
+        certified = True
+        for _ in range(top_k):
+            cand = [(v, i) for i, (v, g) in exact.items() if alive[i] and v > -np.inf]
+            rest = tau_rows[alive[tau_rows]]
+            tau = AU[rest].max() if rest.size else -np.inf
+            if not cand:
+                # every computed row is masked: uncomputed live rows may still hold picks
+                certified = not (tau > -np.inf)
+                break
+            v, i = max(cand, key=lambda t: (t[0], -t[1]))
+            if tau >= v:
+                certified = False
+                break
+            picks.append((i, exact[i][1], v))
+            alive[max(0, i - m + 1):min(n_sub, i + m)] = False
+        if certified or pos >= n_sub:
+            return picks, exact, U
