@@ -152,8 +152,17 @@ def main() -> int:
            torch.empty((n_series, 10), dtype=torch.int32, device=dev),
            torch.empty((n_series, 10), dtype=torch.float64, device=dev),
            torch.empty((n_series,), dtype=torch.int32, device=dev))
-    cells = w.cells()
-    valid = k * sum(_valid_half_pairs(int(x), w.excl) for x in n_subs)
+    # the large single-series workload also adds and removes dimensions and
+    # recomputes the profile of the changed groups inside every step
+    upd = w.update if args.workload == "c4" else None
+    joins = 2 if upd else 1
+    if upd:
+        T_add = torch.from_numpy(upd["T_add"]).to(dev)
+        rem_ids = upd["rem_ids"]
+        T_rem = T[torch.from_numpy(rem_ids).to(dev)].contiguous()
+        rem_idx = torch.from_numpy(rem_ids).to(dev)
+    cells = w.cells() * joins
+    valid = k * sum(_valid_half_pairs(int(x), w.excl) for x in n_subs)  # per self-join launch
     # window columns (P and I are defined there only)
     wmask_h = np.zeros(N, dtype=bool)
     for a, ns in zip(offsets[:-1], n_subs):
@@ -168,6 +177,13 @@ def main() -> int:
             skmp.sketch_build(T, offsets, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R, stats=stats)
             skmp.mp_selfjoin(R, offsets, k, m, w.excl, prec=pr, refresh=rf, P=P, I=I, workspace=ws)
             skmp.top_discords(P, offsets, k, m, 10, out=out)
+            if upd:
+                _, changed = skmp.sketch_update_dims(R, w.kind, k, w.sketch_seed, T_add=T_add,
+                                                     add_ids=upd["add_ids"], T_rem=T_rem, rem_ids=rem_ids,
+                                                     rem_stats=stats[0].index_select(0, rem_idx))
+                skmp.mp_selfjoin(R, offsets, k, m, w.excl, prec=pr, refresh=rf, group_mask=changed, P=P, I=I,
+                                 workspace=ws)
+                skmp.top_discords(P, offsets, k, m, 10, out=out)
 
         for _ in range(warmup):
             step()
@@ -274,8 +290,9 @@ def main() -> int:
         "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec),
         "data": "synthetic",
         "graph": bool(args.graph),
-        "config": {"workload": DESCR[args.workload], "precision": prec, "refresh": refresh,
-                   "n_series": n_series, "cells_per_step": cells, "valid_half_pairs": valid,
+        "config": {"workload": DESCR[args.workload] + (" + add/remove 16 dims and recompute" if upd else ""),
+                   "precision": prec, "refresh": refresh, "self_joins_per_step": joins,
+                   "n_series": n_series, "cells_per_step": cells, "valid_half_pairs_per_join": valid,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "paths": paths,
