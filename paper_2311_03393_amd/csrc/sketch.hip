@@ -93,7 +93,7 @@ int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int6
 }
 
 // ------------------------------------------------------------- kernels
-constexpr int STAT_CHUNK = 1 << 16;
+constexpr int STAT_CHUNK = 1 << 13;
 constexpr int STAT_THREADS = 256;
 
 __global__ void fill_u32(unsigned int* p, unsigned int v, int64_t count) {
@@ -128,6 +128,7 @@ __global__ __launch_bounds__(STAT_THREADS) void dimstats_partial(const TIn* __re
   const double shift = (double)row[a];
   double s1 = 0.0, s2 = 0.0, mx = 0.0;
   unsigned int bad = 0;
+#pragma unroll 8
   for (int64_t t = a + threadIdx.x; t < b; t += STAT_THREADS) {
     double x = (double)row[t];
     bad += isfinite(x) ? 0u : 1u;
@@ -196,31 +197,75 @@ __global__ void dimstats_finalize(const StatPartial* __restrict__ part, const in
   stats[idx * 2 + 1] = sd;
 }
 
-// mode: 0 store, +1 accumulate, -1 subtract
+// R[g][t] (mode 0: =, +1: +=, -1: -=) sum_j S[g][j] (T[j][t] - mu_j) / sigma_j
+// (Algorithm 1; sigma_j = 0 marks a constant dimension, which contributes 0).
+// A block covers 64 columns with SL waves, wave w summing the dimensions of
+// slice w; each lane keeps PF loads of T in flight, so the pass runs at
+// memory speed even for d in the thousands, and the slices' partial sums
+// meet in LDS.  Coefficients S are uniform (scalar loads); coef holds
+// (mu, 1/sigma) per (series, dimension) (1/sigma = 0 for a constant
+// dimension), so normalising costs a subtract and a multiply.
+constexpr int PROJ_PF = 8;
+
 template <typename TIn, int KB>
-__global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T, int64_t ldt, int64_t d, int64_t N,
-                                                      const int64_t* __restrict__ offsets, int n_series,
-                                                      const double* __restrict__ stats, const double* __restrict__ S,
-                                                      int k, double* __restrict__ R, int64_t ldr, int mode) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N) return;
+__device__ __forceinline__ void project_slice(const TIn* __restrict__ T, int64_t ldt, int64_t j0, int64_t j1,
+                                              int64_t tt, const double* __restrict__ st,
+                                              const double* __restrict__ S, int64_t d, int k, double (&acc)[KB]) {
+  for (int64_t j = j0; j < j1; j += PROJ_PF) {
+    double x[PROJ_PF];
+#pragma unroll
+    for (int u = 0; u < PROJ_PF; ++u) x[u] = (j + u < j1) ? (double)T[(j + u) * ldt + tt] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PROJ_PF; ++u) {
+      if (j + u < j1) {
+        const double xb = (x[u] - st[2 * (j + u)]) * st[2 * (j + u) + 1];
+#pragma unroll
+        for (int g = 0; g < KB; ++g)
+          if (g < k) acc[g] = fma(S[(int64_t)g * d + j + u], xb, acc[g]);
+      }
+    }
+  }
+}
+
+template <typename TIn, int KB, int SL>
+__global__ __launch_bounds__(64 * SL) void project_kernel(const TIn* __restrict__ T, int64_t ldt, int64_t d, int64_t N,
+                                                          const int64_t* __restrict__ offsets, int n_series,
+                                                          const double* __restrict__ coef,
+                                                          const double* __restrict__ S, int k, double* __restrict__ R,
+                                                          int64_t ldr, int mode) {
+  __shared__ double part[(SL > 1 ? SL - 1 : 1) * KB * 64];
+  const int lane = threadIdx.x & 63;
+  const int sl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's slice (uniform)
+  const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = t < N;
+  const int64_t tt = valid ? t : N - 1;
   int lo = 0, hi = n_series - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= t) lo = mid; else hi = mid - 1;
+    if (offsets[mid] <= tt) lo = mid; else hi = mid - 1;
   }
-  const double* st = stats + (int64_t)lo * d * 2;
+  const int64_t j0 = d * sl / SL, j1 = d * (sl + 1) / SL;
   double acc[KB];
 #pragma unroll
   for (int g = 0; g < KB; ++g) acc[g] = 0.0;
-  for (int64_t j = 0; j < d; ++j) {
-    const double x = (double)T[j * ldt + t];
-    const double mu = st[2 * j], sd = st[2 * j + 1];
-    const double xb = sd > 0.0 ? (x - mu) / sd : 0.0;
+  // a wave inside one series reads (mu, 1/sigma) through a uniform pointer (scalar loads)
+  const int lo0 = __builtin_amdgcn_readfirstlane(lo);
+  if (__builtin_amdgcn_ballot_w64(lo != lo0) == 0)
+    project_slice<TIn, KB>(T, ldt, j0, j1, tt, coef + (int64_t)lo0 * d * 2, S, d, k, acc);
+  else
+    project_slice<TIn, KB>(T, ldt, j0, j1, tt, coef + (int64_t)lo * d * 2, S, d, k, acc);
+  if (SL > 1) {
+    if (sl > 0) {
+#pragma unroll
+      for (int g = 0; g < KB; ++g) part[((sl - 1) * KB + g) * 64 + lane] = acc[g];
+    }
+    __syncthreads();
+    if (sl > 0) return;
 #pragma unroll
     for (int g = 0; g < KB; ++g)
-      if (g < k) acc[g] = fma(S[(int64_t)g * d + j], xb, acc[g]);
+      for (int q = 0; q < SL - 1; ++q) acc[g] += part[(q * KB + g) * 64 + lane];
   }
+  if (!valid) return;
 #pragma unroll
   for (int g = 0; g < KB; ++g) {
     if (g < k) {
@@ -232,20 +277,32 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
   }
 }
 
+__global__ void prep_coef(const double* __restrict__ stats, int64_t pairs, double* __restrict__ coef) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pairs) return;
+  const double sd = stats[2 * i + 1];
+  coef[2 * i] = stats[2 * i];
+  coef[2 * i + 1] = sd > 0.0 ? 1.0 / sd : 0.0;
+}
+
+// coef: workspace of n_series * d * 2 doubles
 template <typename TIn>
 static void launch_project(const void* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
-                           const double* stats, const double* S, int k, double* R, int64_t ldr, int mode,
-                           hipStream_t st) {
-  dim3 grid((unsigned)((N + 255) / 256)), block(256);
+                           const double* stats, double* coef, const double* S, int k, double* R, int64_t ldr,
+                           int mode, hipStream_t st) {
+  const int64_t pairs = (int64_t)n_series * d;
+  hipLaunchKernelGGL(prep_coef, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, stats, pairs, coef);
+  const dim3 grid((unsigned)((N + 63) / 64));
   const TIn* Tp = static_cast<const TIn*>(T);
-#define SKMP_PROJ(KB) \
-  hipLaunchKernelGGL((project_kernel<TIn, KB>), grid, block, 0, st, Tp, ldt, d, N, offsets, n_series, stats, S, k, R, ldr, mode)
-  if (k <= 1) SKMP_PROJ(1);
-  else if (k <= 4) SKMP_PROJ(4);
-  else if (k <= 8) SKMP_PROJ(8);
-  else if (k <= 16) SKMP_PROJ(16);
-  else if (k <= 32) SKMP_PROJ(32);
-  else SKMP_PROJ(64);
+#define SKMP_PROJ(KB, SL)                                                                                     \
+  hipLaunchKernelGGL((project_kernel<TIn, KB, SL>), grid, dim3(64 * SL), 0, st, Tp, ldt, d, N, offsets, n_series, \
+                     coef, S, k, R, ldr, mode)
+  if (k <= 1) SKMP_PROJ(1, 4);
+  else if (k <= 4) SKMP_PROJ(4, 4);
+  else if (k <= 8) SKMP_PROJ(8, 4);
+  else if (k <= 16) SKMP_PROJ(16, 4);
+  else if (k <= 32) SKMP_PROJ(32, 2);
+  else SKMP_PROJ(64, 2);
 #undef SKMP_PROJ
 }
 
@@ -328,6 +385,7 @@ extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int6
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
   Carve cv(nullptr, 0);
   cv.take<double>((size_t)k * (size_t)d);
+  cv.take<double>((size_t)n_series * (size_t)d * 2);
   stats_workspace(d, n_series, cpre[n_series], cv, nullptr);
   return cv.used + 256;
 }
@@ -353,6 +411,7 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
   Carve cv(workspace, ws_bytes);
   double* S_dev = cv.take<double>((size_t)k * (size_t)d);
+  double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
   StatsBuffers sb;
   stats_workspace(d, n_series, cpre[n_series], cv, &sb);
   if (!workspace || !cv.fits()) {
@@ -365,9 +424,9 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   rc = run_dimstats(T, dtype, ldt, d, n_series, offsets, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
   if (dtype == SKMP_F64)
-    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, S_dev, k, R, ldr, 0, st);
+    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, st);
   else
-    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, S_dev, k, R, ldr, 0, st);
+    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, st);
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }
@@ -379,6 +438,7 @@ extern "C" size_t sketch_update_workspace(int64_t n, int64_t d_add, int64_t d_re
   Carve cv(nullptr, 0);
   cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_add, 1));
   cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_rem, 1));
+  cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
   stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, nullptr);
   return cv.used + 256;
 }
@@ -423,6 +483,7 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
   Carve cv(workspace, ws_bytes);
   double* Sa_dev = cv.take<double>(Sa.size());
   double* Sr_dev = cv.take<double>(Sr.size());
+  double* coef = cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
   StatsBuffers sb;
   stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, &sb);
   if (!workspace || !cv.fits()) {
@@ -436,9 +497,9 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
     rc = run_dimstats(T_add, dtype, ldt, d_add, 1, offs, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
     if (rc) return rc;
     if (dtype == SKMP_F64)
-      launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, Sa_dev, k, R, ldr, +1, st);
+      launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1, st);
     else
-      launch_project<float>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, Sa_dev, k, R, ldr, +1, st);
+      launch_project<float>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1, st);
     for (int g = 0; g < k; ++g)
       for (int64_t j = 0; j < d_add; ++j)
         if (Sa[(size_t)g * d_add + j] != 0.0) mask |= 1ull << g;
@@ -448,9 +509,9 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
     if (!d_add)
       if (int rc2 = upload_async(sb.offsets_dev, offs, sizeof(offs), st)) return rc2;
     if (dtype == SKMP_F64)
-      launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, Sr_dev, k, R, ldr, -1, st);
+      launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1, st);
     else
-      launch_project<float>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, Sr_dev, k, R, ldr, -1, st);
+      launch_project<float>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1, st);
     for (int g = 0; g < k; ++g)
       for (int64_t j = 0; j < d_rem; ++j)
         if (Sr[(size_t)g * d_rem + j] != 0.0) mask |= 1ull << g;
