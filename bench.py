@@ -67,6 +67,8 @@ def _parse():
                          "an extra eager pass)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB MiB before the steps (reference for HBM byte counters)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the FP64 / FP32 launch configuration first (on up to 64 series of a batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -259,6 +261,21 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = {}
+    if args.autotune:
+        skmp.sketch_build(T, offsets, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R, stats=stats)
+        sub = np.arange(n_series) if n_series <= 64 else np.sort(np.random.default_rng(2).choice(n_series, 64, False))
+        if n_series > 64:  # a representative subset: its own concatenation of the chosen series
+            cols = np.concatenate([np.arange(offsets[s], offsets[s + 1]) for s in sub])
+            R_t = R[:, torch.from_numpy(cols).to(dev)].contiguous()
+            offs_t = np.concatenate([[0], np.cumsum(lens[sub])])
+        else:
+            R_t, offs_t = R, offsets
+        for pr in sorted({prec, "fp64"} & {"fp64", "fp32"}):
+            tuned[pr] = skmp.mp_selfjoin_autotune(R_t, offs_t, k, m, w.excl, prec=pr,
+                                                  refresh=refresh if pr == prec else 0, reps=1)
+        del R_t
+        torch.cuda.synchronize()
     also = args.also
     if also is None:
         also = "fp64" if args.workload in ("c3", "c4") else "fp64,fp32,bf16x3,fp16x3"
@@ -317,6 +334,7 @@ def main() -> int:
         "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec),
         "data": "synthetic",
         "graph": bool(args.graph),
+        "autotuned": tuned or None,
         "config": {"workload": DESCR[args.workload] + (" + add/remove 16 dims and recompute" if upd else ""),
                    "precision": prec, "refresh": refresh, "self_joins_per_step": joins,
                    "n_series": n_series, "cells_per_step": cells, "valid_half_pairs_per_join": valid,

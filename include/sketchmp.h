@@ -168,6 +168,42 @@ int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* o
                 int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P, int64_t* I,
                 int64_t ldp, void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Autotuning of the self-join's launch configuration for batched runs: the
+ * tile-kernel variant (diagonals per lane, prefetch depth, waves per SIMD,
+ * column-maximum scheme) and, for SKMP_FP64, the strip of rows per work unit
+ * (1024, 2048 or 4096; an SKMP_FP32 strip is its refresh period).  Runs
+ * mp_selfjoin over every candidate on the caller's input, one warm-up and
+ * `reps` timed runs each (HIP events on `stream`, minimum kept), and records
+ * the fastest for this process under the shape class (prec, ceil(log2 m),
+ * ceil(log2 of the largest series' window count)); later mp_selfjoin calls
+ * of that class use it (environment overrides SKMP_FP64_VARIANT,
+ * SKMP_FP32_VARIANT, SKMP_STRIP still win).  Tuning a representative subset of
+ * a batch tunes the batch, since the class ignores the number of series.
+ * Arguments as for mp_selfjoin (all groups; P, I end up holding a complete
+ * result of the last candidate; the workspace size from
+ * mp_selfjoin_workspace covers every candidate).  prec must be SKMP_FP64 or
+ * SKMP_FP32; 1 <= reps <= 100.  Synchronous: waits for the GPU, and fails
+ * with SKMP_EINVAL under graph capture.
+ *   variant, strip, best_ms   host out (may be NULL): the choice and its time.
+ */
+int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
+                         int32_t m, int32_t excl, int32_t prec, int32_t refresh, double* P, int64_t* I, int64_t ldp,
+                         void* workspace, size_t ws_bytes, void* stream, int32_t reps, int32_t* variant,
+                         int32_t* strip, double* best_ms);
+
+/*
+ * The process's tuning table as text, one line per shape class:
+ * "prec mlog nlog variant strip ms".  skmp_tuning_export writes at most len
+ * bytes (NUL-terminated) into buf (may be NULL) and returns the size needed
+ * including the NUL; skmp_tuning_import adds or replaces the entries of such
+ * text (SKMP_EINVAL on a malformed line or an unknown variant, nothing
+ * changed); skmp_tuning_clear empties the table.  Host-only, thread-safe.
+ */
+size_t skmp_tuning_export(char* buf, size_t len);
+int skmp_tuning_import(const char* text);
+int skmp_tuning_clear(void);
+
 /* Workspace bytes needed by top_discords. */
 size_t top_discords_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m);
 

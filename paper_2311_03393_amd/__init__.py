@@ -36,6 +36,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 # every symbol include/sketchmp.h declares
 EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
+            "mp_selfjoin_autotune", "skmp_tuning_export", "skmp_tuning_import", "skmp_tuning_clear",
             "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4}
 
@@ -80,6 +81,11 @@ def lib():
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
                                    _vp]
+        L.mp_selfjoin_autotune.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i64,
+                                           _vp, _sz, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]
+        L.skmp_tuning_export.argtypes = [ctypes.c_char_p, _sz]
+        L.skmp_tuning_export.restype = _sz
+        L.skmp_tuning_import.argtypes = [ctypes.c_char_p]
         L.skmp_timing_enable.argtypes = [ctypes.c_int]
         L.skmp_timing_read.argtypes = [_i32, _i32, _dp, _i64p]
         _lib = L
@@ -229,6 +235,45 @@ def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refre
                              refresh, mask, P.data_ptr(), I.data_ptr(), _ld(P), workspace.data_ptr(),
                              workspace.numel(), _stream(torch)))
     return P, I
+
+
+def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0,
+                         reps: int = 2, P=None, I=None, workspace=None) -> dict:
+    """Time every launch configuration of the self-join on this input and keep the
+    fastest for later calls of the same shape class; returns {variant, strip, ms}."""
+    torch = _torch()
+    offs = _i64arr(offsets)
+    n_series = offs.size - 1
+    N = int(offs[-1])
+    if P is None:
+        P = torch.empty((k, N), dtype=torch.float64, device=R.device)
+    if I is None:
+        I = torch.empty((k, N), dtype=torch.int64, device=R.device)
+    if workspace is None:
+        ws_n = lib().mp_selfjoin_workspace(n_series, _ptr64(offs), k, m, PRECISIONS[prec])
+        workspace = _workspace(torch, ws_n, R.device)
+    v, sp, ms = ctypes.c_int32(-1), ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().mp_selfjoin_autotune(R.data_ptr(), _ld(R), n_series, _ptr64(offs), k, m, excl, PRECISIONS[prec],
+                                      refresh, P.data_ptr(), I.data_ptr(), _ld(P), workspace.data_ptr(),
+                                      workspace.numel(), _stream(torch), reps, ctypes.byref(v), ctypes.byref(sp),
+                                      ctypes.byref(ms)))
+    return {"variant": v.value, "strip": sp.value, "ms": ms.value}
+
+
+def tuning_export() -> str:
+    """The process's tuning table, one 'prec mlog nlog variant strip ms' line per shape class."""
+    n = lib().skmp_tuning_export(None, 0)
+    buf = ctypes.create_string_buffer(n)
+    lib().skmp_tuning_export(buf, n)
+    return buf.value.decode()
+
+
+def tuning_import(text: str) -> None:
+    _check(lib().skmp_tuning_import(text.encode()))
+
+
+def tuning_clear() -> None:
+    _check(lib().skmp_tuning_clear())
 
 
 def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0, out=None):

@@ -28,7 +28,12 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <iterator>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -953,35 +958,78 @@ static const Fp64Variant kFp32Variants[] = {
 #undef SKMP_FP32_V
 constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
 
-static const Fp64Variant& fp32_variant() {
-  static int idx = [] {
-    const char* e = getenv("SKMP_FP32_VARIANT");
-    int v = e ? atoi(e) : 1;
-    return (v >= 0 && v < kNumFp32Variants) ? v : 1;
-  }();
-  return kFp32Variants[idx];
+// ------------------------------------------------------------- tuning
+// Launch configuration of a self-join: the tile-kernel variant and the strip
+// (rows per work unit).  Chosen, in this order, by SKMP_FP64_VARIANT /
+// SKMP_FP32_VARIANT / SKMP_STRIP (sweeps), by the autotuned table (entries
+// keyed by precision and the log2 buckets of m and of the longest series'
+// window count), or by the built-in defaults.  FP32 units restart from an
+// exact FP64 seed, so their strip is always the refresh period.
+constexpr int kDefaultFp64Variant = 0;
+constexpr int kDefaultFp32Variant = 1;
+static const int kTuneStrips[] = {1024, 2048, 4096};
+
+struct TuneKey {
+  int prec, mlog, nlog;
+  bool operator<(const TuneKey& o) const {
+    return prec != o.prec ? prec < o.prec : (mlog != o.mlog ? mlog < o.mlog : nlog < o.nlog);
+  }
+};
+struct TuneChoice {
+  int variant, strip;
+  double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneChoice> g_tune;
+
+static int ceil_log2(int64_t x) {
+  int b = 0;
+  while ((1ll << b) < x) ++b;
+  return b;
 }
 
-static const Fp64Variant& fp64_variant() {
-  static int idx = [] {
-    const char* e = getenv("SKMP_FP64_VARIANT");
-    int v = e ? atoi(e) : 0;
-    return (v >= 0 && v < kNumFp64Variants) ? v : 0;
-  }();
-  return kFp64Variants[idx];
+static TuneKey tune_key(int prec, int m, int64_t n_series, const int64_t* offsets) {
+  int64_t nmax = 1;
+  for (int64_t s = 0; s < n_series; ++s) nmax = std::max<int64_t>(nmax, offsets[s + 1] - offsets[s] - m + 1);
+  return TuneKey{prec, ceil_log2(m), ceil_log2(nmax)};
 }
 
-// Work-unit strip.  FP64 needs no refresh (SKMP_STRIP overrides its strip
-// for tuning).  FP32 restarts from an exact FP64 seed at every unit start, so
-// its strip is the refresh period.
-static int strip_for(int prec, int refresh) {
-  static const int target = [] {
-    const char* e = getenv("SKMP_STRIP");
-    const int v = e ? atoi(e) : 0;
-    return (v >= 256 && v <= (1 << 20)) ? v : 0;
-  }();
-  if (prec != SKMP_FP32) return target ? target : DEFAULT_STRIP;
-  return refresh > 0 ? refresh : DEFAULT_REFRESH_FP32;
+static int env_int(const char* name, int lo, int hi) {
+  const char* e = getenv(name);
+  if (!e) return -1;
+  const int v = atoi(e);
+  return (v >= lo && v <= hi) ? v : -1;
+}
+
+static const Fp64Variant* variants_of(int prec, int* count) {
+  if (prec == SKMP_FP32) {
+    *count = kNumFp32Variants;
+    return kFp32Variants;
+  }
+  *count = kNumFp64Variants;
+  return kFp64Variants;
+}
+
+static void select_config(int prec, int refresh, const TuneKey& key, int* vidx, int* strip) {
+  static const int env64 = env_int("SKMP_FP64_VARIANT", 0, kNumFp64Variants - 1);
+  static const int env32 = env_int("SKMP_FP32_VARIANT", 0, kNumFp32Variants - 1);
+  static const int env_strip = env_int("SKMP_STRIP", 256, 1 << 20);
+  int v = (prec == SKMP_FP32) ? kDefaultFp32Variant : kDefaultFp64Variant;
+  int sp = DEFAULT_STRIP;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      v = it->second.variant;
+      sp = it->second.strip;
+    }
+  }
+  const int env_v = (prec == SKMP_FP32) ? env32 : env64;
+  if (env_v >= 0) v = env_v;
+  if (env_strip > 0) sp = env_strip;
+  if (prec == SKMP_FP32) sp = refresh > 0 ? refresh : DEFAULT_REFRESH_FP32;
+  *vidx = v;
+  *strip = sp;
 }
 
 static int grid_for(const void* kernel, int block, size_t lds) {
@@ -1006,21 +1054,27 @@ static int active_groups(int32_t k, uint64_t group_mask, GroupList& gl) {
 extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
                                         int32_t prec) {
   if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
-  PlanInfo pl;
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
-  const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
-  const int strip = strip_for(prec, 0);
-  if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, mfma ? 0 : var.C, strip, pl, false) != SKMP_OK) return 0;
-  Carve cv(nullptr, 0);
-  SJBuffers b;
-  carve_sj(cv, pl, n_series, k, prec, b);
-  return cv.used + 256;
+  int nv = 0;
+  const Fp64Variant* vs = variants_of(prec, &nv);
+  size_t need = 0;
+  // the largest over the compiled variants, so a tuned choice always fits
+  for (int v = 0; v < (mfma ? 1 : nv); ++v) {
+    PlanInfo pl;
+    if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, mfma ? 0 : vs[v].C, DEFAULT_STRIP, pl, false) !=
+        SKMP_OK)
+      return 0;
+    Carve cv(nullptr, 0);
+    SJBuffers b;
+    carve_sj(cv, pl, n_series, k, prec, b);
+    need = std::max(need, cv.used + 256);
+  }
+  return need;
 }
 
-extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
-                           int32_t m, int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P,
-                           int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes, void* stream) {
-  clear_error();
+static int validate_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
+                             int32_t m, int32_t excl, int32_t prec, int32_t refresh, double* P, int64_t* I,
+                             int64_t ldp) {
   SKMP_REQUIRE(R && P && I && offsets, "null pointer argument");
   SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
   SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
@@ -1034,15 +1088,18 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   SKMP_REQUIRE(ldr >= N && ldp >= N, "row strides must be >= the total number of samples");
   for (int64_t s = 0; s < n_series; ++s)
     SKMP_REQUIRE(offsets[s + 1] - offsets[s] < (int64_t)INT_MAX - 2 * PADR, "series too long");
-  if (k < 64) group_mask &= (1ull << k) - 1;
-  GroupList gl;
-  if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   SKMP_REQUIRE(!mfma || m <= 1024, "the BF16x3 / FP16x3 self-join supports m <= 1024");
+  return SKMP_OK;
+}
+
+// Everything after validation, with an explicit launch configuration.
+static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                        int32_t excl, int32_t prec, const GroupList& gl, double* P, int64_t* I, int64_t ldp,
+                        void* workspace, size_t ws_bytes, hipStream_t st, const Fp64Variant& var, int strip) {
+  const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   const int kact = gl.count;
   PlanInfo pl;
-  const Fp64Variant& var = (prec == SKMP_FP32) ? fp32_variant() : fp64_variant();
-  const int strip = strip_for(prec, refresh);
   int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true);
   if (rc) return rc;
   Carve cv(workspace, ws_bytes);
@@ -1052,7 +1109,6 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
     return SKMP_ENOMEM;
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
   if (int rc = upload_async(b.plan, pl.sp.data(), sizeof(SeriesPlan) * n_series, st)) return rc;
 
   SJState s;
@@ -1124,5 +1180,142 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
     hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
   }
   SKMP_CHECK_HIP(hipGetLastError());
+  return SKMP_OK;
+}
+
+extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
+                           int32_t m, int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P,
+                           int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (int rc = validate_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, refresh, P, I, ldp)) return rc;
+  if (k < 64) group_mask &= (1ull << k) - 1;
+  GroupList gl;
+  if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
+  int vidx = 0, strip = DEFAULT_STRIP;
+  select_config(prec, refresh, tune_key(prec, m, n_series, offsets), &vidx, &strip);
+  int nv = 0;
+  const Fp64Variant* vs = variants_of(prec, &nv);
+  return run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes,
+                      static_cast<hipStream_t>(stream), vs[vidx], strip);
+}
+
+extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets,
+                                    int32_t k, int32_t m, int32_t excl, int32_t prec, int32_t refresh, double* P,
+                                    int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes, void* stream,
+                                    int32_t reps, int32_t* variant, int32_t* strip, double* best_ms) {
+  clear_error();
+  if (int rc = validate_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, refresh, P, I, ldp)) return rc;
+  SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "only the FP64 and FP32 self-joins have tuning variants");
+  SKMP_REQUIRE(reps >= 1 && reps <= 100, "reps must lie in [1, 100]");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SKMP_REQUIRE(!stream_capturing(st), "autotuning waits for the GPU and cannot run under graph capture");
+  GroupList gl;
+  active_groups(k, k < 64 ? (1ull << k) - 1 : ~0ull, gl);
+  int nv = 0;
+  const Fp64Variant* vs = variants_of(prec, &nv);
+  std::vector<int> strips;
+  if (prec == SKMP_FP32) strips.push_back(refresh > 0 ? refresh : DEFAULT_REFRESH_FP32);
+  else strips.assign(std::begin(kTuneStrips), std::end(kTuneStrips));
+  hipEvent_t e0, e1;
+  SKMP_CHECK_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return SKMP_EDEVICE;
+  }
+  int best_v = -1, best_s = 0, rc = SKMP_OK;
+  double best = 1e300;
+  for (int v = 0; v < nv && rc == SKMP_OK; ++v) {
+    for (int sp : strips) {
+      rc = run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes, st, vs[v],
+                        sp);  // warm-up
+      if (rc) break;
+      double t_min = 1e300;
+      for (int r = 0; r < reps && rc == SKMP_OK; ++r) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = SKMP_EDEVICE;
+        if (!rc) rc = run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes,
+                                   st, vs[v], sp);
+        if (!rc && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = SKMP_EDEVICE;
+        if (!rc) t_min = std::min(t_min, (double)ms);
+      }
+      if (rc) break;
+      if (t_min < best) {
+        best = t_min;
+        best_v = v;
+        best_s = sp;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    if (rc == SKMP_EDEVICE) set_error("HIP event timing failed during autotuning");
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(prec, m, n_series, offsets)] = TuneChoice{best_v, best_s, best};
+  }
+  if (variant) *variant = best_v;
+  if (strip) *strip = best_s;
+  if (best_ms) *best_ms = best;
+  return SKMP_OK;
+}
+
+extern "C" size_t skmp_tuning_export(char* buf, size_t len) {
+  std::string text;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune) {
+      char line[160];
+      snprintf(line, sizeof(line), "%d %d %d %d %d %.6f\n", kv.first.prec, kv.first.mlog, kv.first.nlog,
+               kv.second.variant, kv.second.strip, kv.second.ms);
+      text += line;
+    }
+  }
+  if (buf && len > 0) {
+    const size_t n = std::min(len - 1, text.size());
+    memcpy(buf, text.data(), n);
+    buf[n] = '\0';
+  }
+  return text.size() + 1;
+}
+
+extern "C" int skmp_tuning_import(const char* text) {
+  clear_error();
+  SKMP_REQUIRE(text, "null pointer argument");
+  std::vector<std::pair<TuneKey, TuneChoice>> rows;
+  const char* p = text;
+  while (*p) {
+    const char* e = strchr(p, '\n');
+    std::string line(p, e ? (size_t)(e - p) : strlen(p));
+    p = e ? e + 1 : p + line.size();
+    if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+    int prec, mlog, nlog, v, sp;
+    double ms;
+    char extra;
+    if (sscanf(line.c_str(), "%d %d %d %d %d %lf %c", &prec, &mlog, &nlog, &v, &sp, &ms, &extra) != 6) {
+      set_error("malformed tuning line: " + line);
+      return SKMP_EINVAL;
+    }
+    int nv = 0;
+    variants_of(prec, &nv);
+    SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "tuning line for a precision without variants");
+    SKMP_REQUIRE(v >= 0 && v < nv, "tuning line names an unknown variant");
+    SKMP_REQUIRE(sp >= 64 && sp <= (1 << 20), "tuning line strip out of range");
+    SKMP_REQUIRE(mlog >= 0 && mlog <= 12 && nlog >= 0 && nlog <= 32, "tuning line shape class out of range");
+    rows.push_back({TuneKey{prec, mlog, nlog}, TuneChoice{v, sp, ms}});
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& r : rows) g_tune[r.first] = r.second;
+  return SKMP_OK;
+}
+
+extern "C" int skmp_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
   return SKMP_OK;
 }

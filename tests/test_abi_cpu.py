@@ -106,3 +106,32 @@ def test_build_and_discords_reject_bad_arguments(L):
     ids = np.array([3, 3], dtype=np.int64)
     assert L.sketch_update_dims(fake, 100, 100, 2, 1, 0, 0, 100, fake, 2, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 fake, None, 0, None, None, 0, None, fake, 1 << 20, None) == -1  # duplicate id
+
+
+def test_tuning_table_round_trip_and_validation(L):
+    skmp.tuning_clear()
+    assert skmp.tuning_export() == ""
+    text = "0 7 16 3 4096 3.25\n1 6 15 1 256 2.000000\n"
+    skmp.tuning_import(text)
+    rows = sorted(line.split() for line in skmp.tuning_export().splitlines())
+    assert rows == [["0", "7", "16", "3", "4096", "3.250000"], ["1", "6", "15", "1", "256", "2.000000"]]
+    skmp.tuning_import("0 7 16 5 1024 1.0\n")  # replaces the FP64 class entry
+    assert "0 7 16 5 1024 1.000000" in skmp.tuning_export()
+    for bad in ["0 7 16 99 2048 1.0", "2 7 16 0 2048 1.0", "0 7 16 1 2048", "0 7 16 1 2048 1.0 x", "1 6 15 1 16 1"]:
+        with pytest.raises(skmp.SketchMPError):
+            skmp.tuning_import(bad)
+    assert len(skmp.tuning_export().splitlines()) == 2   # a rejected import changes nothing
+    skmp.tuning_clear()
+    assert skmp.tuning_export() == ""
+
+
+def test_autotune_rejects_bad_arguments_before_launch(L):
+    a, p = _offs(0, 300)
+    fake = ctypes.c_void_p(16)
+    v, sp, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    args = lambda prec, reps, k=2: (fake, 300, 1, p, k, 16, 4, prec, 0, fake, fake, 300, fake, 1 << 30, None, reps,
+                                    ctypes.byref(v), ctypes.byref(sp), ctypes.byref(ms))
+    assert L.mp_selfjoin_autotune(*args(2, 2)) == -1   # BF16x3 has no variants to tune
+    assert L.mp_selfjoin_autotune(*args(0, 0)) == -1   # reps
+    assert L.mp_selfjoin_autotune(*args(0, 2, k=0)) == -1
+    assert L.skmp_last_error()

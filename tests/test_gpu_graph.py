@@ -1,4 +1,5 @@
-"""HIP graph capture of the whole hot path (sketch, self-join, top discords).
+"""HIP graph capture of the whole hot path (sketch, self-join, top discords),
+and the autotuned launch configuration.
 
 One eager call per argument set comes first (it creates the library's pinned
 copies of the host tables); the same sequence is then captured into a graph
@@ -102,3 +103,37 @@ def test_graph_replays_match_eager(prec):
         _say("replay", rep, "top", got[3][0].tolist())
         same(got, ref)
     del g
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_choice_is_used_and_exact(prec, c_oracle):
+    """The autotuner times every candidate configuration, records the fastest
+    for the shape class, and later calls (which use it) still match the oracle."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    from oracle import sketchmp_oracle as O
+    from tests.helpers import check_neighbours, fp64_tol, mixed_tol, profile_close
+    dev = torch.device("cuda:0")
+    n, m, excl, k = 6000, 64, 16, 2
+    _say("autotune", prec, n, m)
+    T = datagen.tiny_series(41, 5, n)
+    R_np, _, _, _ = O.build(T, "gauss", k, 41)
+    R = torch.from_numpy(R_np).to(dev)
+    skmp.tuning_clear()
+    choice = skmp.mp_selfjoin_autotune(R, [0, n], k, m, excl, prec=prec, reps=1)
+    assert choice["variant"] >= 0 and choice["ms"] > 0
+    assert choice["strip"] in ((1024, 2048, 4096) if prec == "fp64" else (256,))
+    rows = [line.split() for line in skmp.tuning_export().splitlines()]
+    assert len(rows) == 1 and int(rows[0][0]) == {"fp64": 0, "fp32": 1}[prec]
+    assert int(rows[0][3]) == choice["variant"] and int(rows[0][4]) == choice["strip"]
+    P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec)
+    torch.cuda.synchronize()
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    n_sub = n - m + 1
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
+    for g in range(k):
+        P_o, _ = c_oracle.profile(R_np[g], m, excl)
+        ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
+        assert ok.all(), err
+        check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
+    skmp.tuning_clear()
