@@ -320,6 +320,15 @@ def main() -> int:
         "basis": "VALU issue: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 6 lane-ops (2 FMA, 2 MUL, 2 MAX) "
                  "per valid half-matrix cell",
     }
+    # the sketch stage is HBM-bound: T is read twice (statistics, projection), R written once
+    sk_ms = head["stages_ms_per_step"]["sketch"]
+    sk_bytes = 2.0 * d * N * T.element_size() + k * N * 8.0
+    sketch = {"ms_per_step": sk_ms, "bytes": sk_bytes,
+              "GB_per_s": sk_bytes / (sk_ms * 1e-3) / 1e9 if sk_ms > 0 else None,
+              "frac_of_hbm": sk_bytes / (sk_ms * 1e-3) / 8e12 if sk_ms > 0 else None,
+              "basis": "2 reads of T + 1 write of R against 8 TB/s"}
+    if upd:
+        sketch["note"] = "ms_per_step also holds the update's dimension statistics and projections"
     result = {
         "metric": "matrix-profile cells/sec (k*n^2/2 per s)",
         "value": head["cells_per_s"],
@@ -340,6 +349,7 @@ def main() -> int:
                    "n_series": n_series, "cells_per_step": cells, "valid_half_pairs_per_join": valid,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "sketch": sketch,
         "paths": paths,
     }
     if not args.no_cpu_baseline:
