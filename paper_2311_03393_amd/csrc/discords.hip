@@ -48,6 +48,7 @@ struct DiscState {
   int32_t* G;
   double* bval;   // per block: max of A over the block (-inf if none)
   int32_t* bidx;  // its first window (index within the series), -1 if none
+  int8_t* bgrp;   // the group of that window
   int64_t* idx;   // outputs
   int32_t* group;
   double* score;
@@ -65,6 +66,20 @@ __device__ __forceinline__ void wave_best(double& v, int& i) {
     if (better(ov, oi, v, i)) {
       v = ov;
       i = oi;
+    }
+  }
+}
+
+// the same, carrying a payload that follows the winner
+__device__ __forceinline__ void wave_best(double& v, int& i, int& pay) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(v, off);
+    const int oi = __shfl_down(i, off);
+    const int op = __shfl_down(pay, off);
+    if (better(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+      pay = op;
     }
   }
 }
@@ -124,6 +139,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__
       }
     st.bval[b] = bv;
     st.bidx[b] = bv > -INFINITY ? bi : -1;
+    st.bgrp[b] = bv > -INFINITY ? (int8_t)st.G[sr.col + bi] : (int8_t)-1;
   }
 }
 
@@ -136,9 +152,10 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_lds[];
   double* sv = reinterpret_cast<double*>(sel_lds);
   int* si = reinterpret_cast<int*>(sv + SEL_LDS_BLOCKS);
+  int8_t* sg = reinterpret_cast<int8_t*>(si + SEL_LDS_BLOCKS);
   __shared__ int64_t picks[MAX_TOPK];
   __shared__ double wv[SEL_WAVES];
-  __shared__ int wi[SEL_WAVES];
+  __shared__ int wi[SEL_WAVES], wb[SEL_WAVES];
   __shared__ double pv;
   __shared__ int pi;
   const int s = blockIdx.x;
@@ -150,22 +167,25 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
   for (int b = tid; b < nb; b += SEL_THREADS) {
     sv[b] = st.bval[sr.blk_base + b];
     si[b] = st.bidx[sr.blk_base + b];
+    sg[b] = st.bgrp[sr.blk_base + b];
   }
   __syncthreads();
   int found = 0;
   for (int pass = 0; pass < st.top_k; ++pass) {
     // best block
     double v = -INFINITY;
-    int bi = INT_MAX;
+    int bi = INT_MAX, bb = -1;
     for (int b = tid; b < nb; b += SEL_THREADS)
       if (sv[b] > -INFINITY && better(sv[b], si[b], v, bi)) {
         v = sv[b];
         bi = si[b];
+        bb = b;
       }
-    wave_best(v, bi);
+    wave_best(v, bi, bb);
     if (lane == 0) {
       wv[wave] = v;
       wi[wave] = bi;
+      wb[wave] = bb;
     }
     __syncthreads();
     if (tid == 0) {
@@ -173,13 +193,14 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
         if (better(wv[q], wi[q], v, bi)) {
           v = wv[q];
           bi = wi[q];
+          bb = wb[q];
         }
       pv = v;
       pi = bi;
       const int64_t o = (int64_t)s * st.top_k + pass;
       if (v > -INFINITY) {
         st.idx[o] = bi;
-        st.group[o] = st.G[sr.col + bi];
+        st.group[o] = sg[bb];
         st.score[o] = v;
         picks[pass] = bi;
       }
@@ -199,9 +220,10 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
         const int64_t w0 = (int64_t)b << st.shift;
         const int64_t w1 = min(w0 + B, sr.n_sub);
         double x = -INFINITY;
-        int xi = INT_MAX;
+        int xi = INT_MAX, xg = -1;
         for (int64_t i = w0 + lane; i < w1; i += 64) {
           const double a = st.A[sr.col + i];
+          const int ga = st.G[sr.col + i];
           if (!(a > -INFINITY) || !better(a, i, x, xi)) continue;
           bool masked = false;
           for (int q = 0; q <= pass; ++q) {
@@ -211,29 +233,27 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
           if (!masked) {
             x = a;
             xi = (int)i;
+            xg = ga;
           }
         }
-        wave_best(x, xi);
+        wave_best(x, xi, xg);
         if (lane == 0) {
           sv[b] = x;
           si[b] = x > -INFINITY ? xi : -1;
+          sg[b] = (int8_t)(x > -INFINITY ? xg : -1);
         }
       }
     }
     __syncthreads();
   }
-  if (tid == 0) st.n_found[s] = found;
-}
-
-__global__ void init_outputs(DiscState st) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)st.n_series * st.top_k;
-  if (t < total) {
-    st.idx[t] = -1;
-    st.group[t] = -1;
-    st.score[t] = __longlong_as_double(0x7FF8000000000000ll);
+  // entries past the last pick
+  for (int p = found + tid; p < st.top_k; p += SEL_THREADS) {
+    const int64_t o = (int64_t)s * st.top_k + p;
+    st.idx[o] = -1;
+    st.group[o] = -1;
+    st.score[o] = __longlong_as_double(0x7FF8000000000000ll);
   }
-  if (t < st.n_series) st.n_found[t] = 0;
+  if (tid == 0) st.n_found[s] = found;
 }
 
 // Block size (log2) and per-series block ranges.
@@ -276,6 +296,7 @@ extern "C" size_t top_discords_workspace(int64_t n_series, const int64_t* offset
   cv.take<int32_t>(offsets[n_series]);
   cv.take<double>(blocks);
   cv.take<int32_t>(blocks);
+  cv.take<int8_t>(blocks);
   return cv.used + 256;
 }
 
@@ -311,6 +332,7 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   st.G = cv.take<int32_t>(N);
   st.bval = cv.take<double>(blocks);
   st.bidx = cv.take<int32_t>(blocks);
+  st.bgrp = cv.take<int8_t>(blocks);
   st.idx = idx;
   st.group = group;
   st.score = score;
@@ -322,13 +344,10 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   hipStream_t stream_ = static_cast<hipStream_t>(stream);
   if (int rc = upload_async(ser, ds.data(), sizeof(DiscSeries) * n_series, stream_)) return rc;
   StageTimer tm(SKMP_TIMER_DISCORDS, stream_);
-  const int64_t outs = std::max<int64_t>(n_series * top_k, n_series);
-  hipLaunchKernelGGL(init_outputs, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, stream_, st);
-  if (blocks > 0) {
+  if (blocks > 0)
     hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, stream_, P, ldp, k, st);
-    const size_t lds = (size_t)SEL_LDS_BLOCKS * (sizeof(double) + sizeof(int));
-    hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), lds, stream_, st);
-  }
+  const size_t lds = (size_t)SEL_LDS_BLOCKS * (sizeof(double) + sizeof(int) + sizeof(int8_t));
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), lds, stream_, st);
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }

@@ -41,16 +41,6 @@
 
 namespace skmp {
 
-__global__ void fill_u64(unsigned long long* p, unsigned long long v, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-__global__ void fill_i32(int32_t* p, int32_t v, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
 // chunk (256 padded windows of one (series, group slot)) -> (s, gi, x0)
 struct ChunkPos {
   int s, gi;
@@ -73,7 +63,7 @@ __device__ __forceinline__ ChunkPos decode_chunk(const SJState& st, int64_t chun
 // per thread; whenever the (series, group) changes (and at the end) the block
 // reduces it and issues one 64-bit atomic max, so an address receives a few
 // atomics instead of one per wave.
-constexpr int SCALE_CHUNKS = 32;
+constexpr int SCALE_CHUNKS = 8;
 
 __device__ __forceinline__ void scale_flush(double v, unsigned long long* dst, double* red) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off));
@@ -84,6 +74,21 @@ __device__ __forceinline__ void scale_flush(double v, unsigned long long* dst, d
     if (b > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(b));
   }
   __syncthreads();
+}
+
+// Start values of the per-(series, group) and per-block arrays and of the
+// work counter, in one launch.
+__global__ __launch_bounds__(256) void init_small(SJState st, int64_t n_sg, int64_t n_blk) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < max(n_sg, n_blk);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n_sg) {
+      reinterpret_cast<unsigned long long*>(st.scale)[i] = 0ull;
+      st.flat_first[i] = INT_MAX;
+      st.flat_last[i] = -1;
+    }
+    if (i < n_blk) st.flat_blk[i] = INT_MAX;
+    if (i < 64) st.counter[i] = 0u;
+  }
 }
 
 __global__ __launch_bounds__(256) void scale_kernel(SJState st) {
@@ -127,6 +132,8 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   const int64_t sidx = gbase + PADL + x;
   const int64_t xp = x + PADL;
   const int64_t tidx = gbase + (xp % st.cstride) * (sp.lpad / st.cstride) + xp / st.cstride;
+  st.rowkey[sidx] = 0ull;  // the tile kernels' max targets start at zero
+  st.colkey[sidx] = 0ull;
   if (x < 0 || x >= sp.n_sub) {
     const double qnan = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
     st.dfdg[sidx] = make_double2(0.0, 0.0);
@@ -790,12 +797,21 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64
         // exact distance from explicit differences of the normalised windows
         const double ax = invn[x] * sqrt_m, ap = invn[partner] * sqrt_m;
         const double mx = mu[x], mp = mu[partner];
-        double acc = 0.0;
-        for (int q = 0; q < m; ++q) {
-          const double e = (r[x + q] - mx) * ax - (r[partner + q] - mp) * ap;
-          acc = fma(e, e, acc);
+        // four independent partial sums keep several gathers of the partner in flight
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 4 <= m; q += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double e = (r[x + q + u] - mx) * ax - (r[partner + q + u] - mp) * ap;
+            acc[u] = fma(e, e, acc[u]);
+          }
         }
-        best = sqrt(acc);
+        for (; q < m; ++q) {
+          const double e = (r[x + q] - mx) * ax - (r[partner + q] - mp) * ap;
+          acc[0] = fma(e, e, acc[0]);
+        }
+        best = sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
       }
       arg = partner;
     }
@@ -1143,16 +1159,13 @@ static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const in
   s.total_chunks = pl.total_chunks;
   s.strip = strip;
 
-  const size_t cells = (size_t)kact * (size_t)pl.gstride;
-  const dim3 fb(256), fg(2048);
-  hipLaunchKernelGGL(fill_u64, fg, fb, 0, st, b.rowkey, 0ull, (int64_t)cells);
-  hipLaunchKernelGGL(fill_u64, fg, fb, 0, st, b.colkey, 0ull, (int64_t)cells);
-  hipLaunchKernelGGL(fill_u64, dim3(64), fb, 0, st, reinterpret_cast<unsigned long long*>(b.scale), 0ull,
-                     (int64_t)n_series * kact);
-  hipLaunchKernelGGL(fill_i32, dim3(64), fb, 0, st, b.flat_first, (int32_t)INT_MAX, (int64_t)n_series * kact);
-  hipLaunchKernelGGL(fill_i32, dim3(64), fb, 0, st, b.flat_last, (int32_t)-1, (int64_t)n_series * kact);
-  hipLaunchKernelGGL(fill_i32, fg, fb, 0, st, b.flat_blk, (int32_t)INT_MAX, (int64_t)kact * pl.blk_stride);
-  hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t*>(b.counter), 0, (int64_t)64);
+  const dim3 fb(256);
+  {
+    const int64_t n_sg = (int64_t)n_series * kact, n_blk = (int64_t)kact * pl.blk_stride;
+    const int64_t big = std::max<int64_t>(std::max<int64_t>(n_sg, n_blk), 64);
+    hipLaunchKernelGGL(init_small, dim3((unsigned)std::min<int64_t>((big + 255) / 256, 4096)), fb, 0, st, s, n_sg,
+                       n_blk);
+  }
   SKMP_CHECK_HIP(hipGetLastError());
 
   const dim3 cg((unsigned)pl.total_chunks);
