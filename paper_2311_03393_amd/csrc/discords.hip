@@ -4,7 +4,7 @@
 //   combine:  A[i] = max over groups of P[g][i] with the first group kept on
 //             ties (Algorithm 2 replaces its best only on a strictly larger
 //             score); non-finite scores (no admissible neighbour) are dropped.
-//   select:   one 1024-thread block per series runs all K greedy passes: each
+//   select:   one 256-thread block per series runs all K greedy passes: each
 //             pass takes the first maximum of A among windows not masked by
 //             earlier picks; a pick masks |i - i*| < halfwidth.  Maxima per
 //             block of windows (computed with A) make a pass a reduction over
@@ -24,7 +24,7 @@ namespace skmp {
 // every series has at most SEL_LDS_BLOCKS blocks (they live in LDS during
 // the selection).
 constexpr int DISC_BLK_MIN_SHIFT = 8;
-constexpr int SEL_THREADS = 1024;
+constexpr int SEL_THREADS = 256;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int MAX_TOPK = 256;
 constexpr int SEL_LDS_BLOCKS = 4096;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const double* __restrict__
   }
 }
 
-// One 1024-thread block per series runs the K greedy passes.  The block maxima
+// One 256-thread block per series runs the K greedy passes.  The block maxima
 // sit in LDS; a pass takes the best block (its maximum is the best unmasked
 // window: ties resolve to the smallest window, as blocks are in window order),
 // records it, and re-scans only the blocks that the new mask |i - i*| < h
@@ -188,13 +188,14 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
       wb[wave] = bb;
     }
     __syncthreads();
+    if (wave == 0) {
+      // second level: the wave maxima, reduced by wave 0
+      v = lane < SEL_WAVES ? wv[lane] : -INFINITY;
+      bi = lane < SEL_WAVES ? wi[lane] : INT_MAX;
+      bb = lane < SEL_WAVES ? wb[lane] : -1;
+      wave_best(v, bi, bb);
+    }
     if (tid == 0) {
-      for (int q = 1; q < SEL_WAVES; ++q)
-        if (better(wv[q], wi[q], v, bi)) {
-          v = wv[q];
-          bi = wi[q];
-          bb = wb[q];
-        }
       pv = v;
       pi = bi;
       const int64_t o = (int64_t)s * st.top_k + pass;
