@@ -149,8 +149,10 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  *   m        subsequence length, 4 <= m; every series needs n_s >= m.
  *   excl     trivial-match exclusion: (i, j) is excluded iff |i - j| < excl; 1 <= excl.
  *   prec     SKMP_FP64 | SKMP_FP32 | SKMP_BF16X3 | SKMP_FP16X3.
- *   refresh  mixed precisions: rows between exact FP64 recomputations of the
- *            running covariance (0 = default 256); ignored for SKMP_FP64.
+ *   refresh  SKMP_FP32: rows between exact FP64 recomputations of the running
+ *            covariance (0 = the larger of 256 and 2.5 m rounded up to a
+ *            multiple of 256); ignored by the other precisions (SKMP_FP64 needs
+ *            none, BF16x3 / FP16x3 compute every tile afresh from the sketch).
  *   group_mask bit g selects group g (~0 = all); unselected rows of P/I are untouched.
  *   P        device out, k x N doubles, row stride ldp: P[g][offsets[s] + i] for
  *            i < n_s - m + 1 is the distance from subsequence i of R^(g) in

@@ -925,7 +925,10 @@ static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, 
 
 // tile configuration of the FP64 kernel
 constexpr int DEFAULT_STRIP = 2048;
-constexpr int DEFAULT_REFRESH_FP32 = 256;
+// Default FP32 refresh period: at least 256 rows and at least 2.5 m (rounded up
+// to 256), so the exact seeds (m FP64 FMAs per diagonal per period) stay near
+// 0.4 FMA per cell whatever the window length.
+static inline int default_refresh(int m) { return std::max(256, ((5 * m / 2 + 255) / 256) * 256); }
 
 // Compiled variants of the FP64 tile kernel: diagonals per lane C, prefetch
 // depth PD and the waves-per-SIMD occupancy the register allocation is held to.
@@ -987,6 +990,7 @@ static const int kTuneStrips[] = {1024, 2048, 4096};
 
 struct TuneKey {
   int prec, mlog, nlog;
+  int m;  // not part of the class (ordering ignores it)
   bool operator<(const TuneKey& o) const {
     return prec != o.prec ? prec < o.prec : (mlog != o.mlog ? mlog < o.mlog : nlog < o.nlog);
   }
@@ -1007,7 +1011,7 @@ static int ceil_log2(int64_t x) {
 static TuneKey tune_key(int prec, int m, int64_t n_series, const int64_t* offsets) {
   int64_t nmax = 1;
   for (int64_t s = 0; s < n_series; ++s) nmax = std::max<int64_t>(nmax, offsets[s + 1] - offsets[s] - m + 1);
-  return TuneKey{prec, ceil_log2(m), ceil_log2(nmax)};
+  return TuneKey{prec, ceil_log2(m), ceil_log2(nmax), m};
 }
 
 static int env_int(const char* name, int lo, int hi) {
@@ -1043,7 +1047,7 @@ static void select_config(int prec, int refresh, const TuneKey& key, int* vidx, 
   const int env_v = (prec == SKMP_FP32) ? env32 : env64;
   if (env_v >= 0) v = env_v;
   if (env_strip > 0) sp = env_strip;
-  if (prec == SKMP_FP32) sp = refresh > 0 ? refresh : DEFAULT_REFRESH_FP32;
+  if (prec == SKMP_FP32) sp = refresh > 0 ? refresh : default_refresh(key.m);
   *vidx = v;
   *strip = sp;
 }
@@ -1227,7 +1231,7 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   int nv = 0;
   const Fp64Variant* vs = variants_of(prec, &nv);
   std::vector<int> strips;
-  if (prec == SKMP_FP32) strips.push_back(refresh > 0 ? refresh : DEFAULT_REFRESH_FP32);
+  if (prec == SKMP_FP32) strips.push_back(refresh > 0 ? refresh : default_refresh(m));
   else strips.assign(std::begin(kTuneStrips), std::end(kTuneStrips));
   hipEvent_t e0, e1;
   SKMP_CHECK_HIP(hipEventCreate(&e0));
@@ -1320,7 +1324,7 @@ extern "C" int skmp_tuning_import(const char* text) {
     SKMP_REQUIRE(v >= 0 && v < nv, "tuning line names an unknown variant");
     SKMP_REQUIRE(sp >= 64 && sp <= (1 << 20), "tuning line strip out of range");
     SKMP_REQUIRE(mlog >= 0 && mlog <= 12 && nlog >= 0 && nlog <= 32, "tuning line shape class out of range");
-    rows.push_back({TuneKey{prec, mlog, nlog}, TuneChoice{v, sp, ms}});
+    rows.push_back({TuneKey{prec, mlog, nlog, 0}, TuneChoice{v, sp, ms}});
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const auto& r : rows) g_tune[r.first] = r.second;
