@@ -298,6 +298,7 @@ def main() -> int:
                 "finite_pattern_equal": bool(torch.equal(torch.isfinite(ref), torch.isfinite(got))),
                 "tolerance_dP": tol,
                 "top10_equal_all_series": bool(torch.equal(picks[v["precision"]], picks["fp64"])),
+                "series_with_different_top10": int((picks[v["precision"]] != picks["fp64"]).any(dim=1).sum()),
             }
             del got, both, err, sq
         del ref

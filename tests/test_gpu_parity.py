@@ -436,3 +436,33 @@ def test_selfjoin_fp32_refresh_periods(dev, c_oracle, refresh):
         ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
         assert ok.all(), f"refresh {refresh} group {g}: {np.count_nonzero(~ok)} rows out of tolerance, max err {err}"
         check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_selfjoin_long_windows_and_many_groups(dev, c_oracle, prec):
+    """Window lengths near the limit (the exact seeds stage several chunks of
+    the window; the padding covers m - 1 samples past the end) and k = 64."""
+    import torch
+    from tests.helpers import mixed_tol
+    tol_of = fp64_tol if prec == "fp64" else mixed_tol
+    for (n, m, excl, k, seed) in [(4500, 1500, 375, 2, 51), (5000, 2048, 512, 1, 52), (700, 16, 4, 64, 53)]:
+        _say("long/many", prec, n, m, excl, k)
+        T = datagen.tiny_series(seed, 6, n)
+        R_np, _, _, _ = O.build(T, "gauss", k, seed)
+        P, I = _run_selfjoin(torch, dev, R_np, [0, n], k, m, excl, prec=prec)
+        n_sub = n - m + 1
+        tol = tol_of(m)
+        for g in range(k):
+            P_o, _ = c_oracle.profile(R_np[g], m, excl)
+            ok, err = profile_close(P[g, :n_sub], P_o, m, tol)
+            assert ok.all(), (n, m, k, g, err)
+            check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
+
+
+def test_mfma_precisions_reject_long_windows(dev):
+    import torch
+    import paper_2311_03393_amd as skmp
+    R = torch.zeros((1, 4000), dtype=torch.float64, device=dev)
+    for prec in ("bf16x3", "fp16x3"):
+        with pytest.raises(skmp.SketchMPError):
+            skmp.mp_selfjoin(R, [0, 4000], 1, 1100, 275, prec=prec)
