@@ -382,40 +382,41 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
 // columns move down by TL and keep accumulating in the next block.  Every row
 // and column of a unit is thereby flushed once.  to_global(key, delta) forms
 // the global 64-bit key of a local key whose partner lies delta diagonals up.
-template <int C, int TL, typename K, typename G>
+template <int C, int TL, typename K, typename G, typename V>
 __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_sub, int t,
-                                            unsigned long long* gro, unsigned long long* gco, G to_global) {
+                                            unsigned long long* gro, unsigned long long* gco, K empty, G to_global,
+                                            V valid) {
   constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
   constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
   constexpr uint32_t LMAX = (64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u);
   __syncthreads();
   K kr[RPL], kc[CPL];
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) kr[q] = (t + 64 * q < NROW) ? rowk[t + 64 * q] : K(0);
+  for (int q = 0; q < RPL; ++q) kr[q] = (t + 64 * q < NROW) ? rowk[t + 64 * q] : empty;
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) kc[q] = (t + 64 * q < NCOL) ? colk[t + 64 * q] : K(0);
+  for (int q = 0; q < CPL; ++q) kc[q] = (t + 64 * q < NCOL) ? colk[t + 64 * q] : empty;
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const int x = t + 64 * q;
     if (x < NROW) {
-      if (x >= NROW - TL) rowk[x] = K(0);                   // [64, NROW): cleared
-      if (x >= TL) rowk[x - TL] = last ? K(0) : kr[q];     // [TL, NROW) -> [0, 64)
+      if (x >= NROW - TL) rowk[x] = empty;                  // [64, NROW): cleared
+      if (x >= TL) rowk[x - TL] = last ? empty : kr[q];    // [TL, NROW) -> [0, 64)
     }
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int x = t + 64 * q;
     if (x < NCOL) {
-      if (x >= NCOL - TL) colk[x] = K(0);                   // [64 C, NCOL): cleared
-      if (x >= TL) colk[x - TL] = last ? K(0) : kc[q];     // [TL, NCOL) -> [0, 64 C)
+      if (x >= NCOL - TL) colk[x] = empty;                  // [64 C, NCOL): cleared
+      if (x >= TL) colk[x - TL] = last ? empty : kc[q];    // [TL, NCOL) -> [0, 64 C)
     }
   }
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const int xl = t + 64 * q;
     const int x = u0 - 63 + xl;
-    if (kr[q] && (last || xl < TL) && xl < NROW && x >= 0 && x < n_sub) {
+    if (valid(kr[q]) && (last || xl < TL) && xl < NROW && x >= 0 && x < n_sub) {
       const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
       atomicMax(gro + x, to_global(kr[q], delta));
     }
@@ -424,7 +425,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
   for (int q = 0; q < CPL; ++q) {
     const int xl = t + 64 * q;
     const int j = u0 + db + xl;
-    if (kc[q] && (last || xl < TL) && xl < NCOL && j < n_sub) {
+    if (valid(kc[q]) && (last || xl < TL) && xl < NCOL && j < n_sub) {
       const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
       atomicMax(gco + j, to_global(kc[q], delta));
     }
@@ -524,10 +525,10 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
         for (int q = 0; q < C - 1; ++q)
           atomicMax(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
       }
-      flush_block<C, TL>(rowk, colk, last, u0, db, n_sub, t, gro, gco,
-                         [GMAX](unsigned long long key, int delta) {
-                           return (key & ~GMAX) | (GMAX - (unsigned long long)delta);
-                         });
+      flush_block<C, TL>(
+          rowk, colk, last, u0, db, n_sub, t, gro, gco, 0ull,
+          [GMAX](unsigned long long key, int delta) { return (key & ~GMAX) | (GMAX - (unsigned long long)delta); },
+          [](unsigned long long key) { return key != 0ull; });
     }
   }
 }
@@ -538,9 +539,16 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
 // statistics and the keys in FP32: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
 // in FP32 from an exact FP64 seed recomputed at the start of every strip
 // (the strip length is the refresh period).  Keys are the bits of the FP32
-// value rho + 2 in [1, 3] with the local diagonal in the low LBITS bits;
-// as positive floats they order like unsigned integers, so the maxima use
-// 32-bit integer max (v_max3_u32 for the row).
+// value 1 - rho + 2^-16 in (0, 2] with the local diagonal in the low LBITS
+// bits; as positive floats they order like unsigned integers, so the nearest
+// neighbour is a 32-bit integer minimum (v_min3_u32).  Relative to rho + 2 in
+// [1, 3] this resolves candidates relative to their own distance (for
+// 1 - rho ~ 0.2 about 3e-6 in rho instead of 2.4e-4), so near ties between
+// neighbours are decided far below the tolerance.  Padded cells give NaN
+// keys, whose bits lie above every real key, so the minima ignore them.
+// Flushing converts a key f to the global form 3 - f = rho + 2 + ... (maxima).
+constexpr float KEY_ONE = 1.0f + 1.52587890625e-5f;  // 1 + 2^-16
+
 struct StepLoadF {
   float2 rs;
   float rinv;
@@ -591,7 +599,7 @@ struct LaneStateF {
   uint32_t colacc[C];
 };
 
-template <int C, bool EDGE, int PD>
+template <int C, int PD>
 __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], const uint32_t (&code)[C],
                                                uint32_t keep, int ngroups, int u0, int db, const StatRsrcF& R,
                                                uint32_t* rowk, uint32_t* colk, int t) {
@@ -614,17 +622,18 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
       for (int q = 0; q < C; ++q) {
         const int sl = (p + q) % C;
         const float a = ls.Cq[q] * ls.cinv[sl];
-        float kf = __builtin_fmaf(a, cur.rinv, 2.0f);
-        uint32_t key = (__float_as_uint(kf) & keep) | code[q];
-        if (EDGE) key = __float_as_uint(vmaxf(0.0f, __uint_as_float(key)));  // padded cells (NaN) -> 0
-        rowp = (q == 0) ? key : max(rowp, key);
+        // 1 - rho (+ 2^-16 so FP32 rounding never makes it negative): a positive
+        // float, resolved relative to itself, so close candidates stay apart
+        const float kf = __builtin_fmaf(-a, cur.rinv, KEY_ONE);
+        const uint32_t key = (__float_as_uint(kf) & keep) | code[q];  // padded cells: NaN bits, above every key
+        rowp = (q == 0) ? key : min(rowp, key);
         if (q == C - 1) ls.colacc[sl] = key;
-        else ls.colacc[sl] = max(ls.colacc[sl], key);
+        else ls.colacc[sl] = min(ls.colacc[sl], key);
         ls.Cq[q] = __builtin_fmaf(cur.rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = __builtin_fmaf(ls.cdf[sl], cur.rs.y, ls.Cq[q]);
       }
-      atomicMax(&rowk[us + 63 - t], rowp);
-      atomicMax(&colk[us + t * (C - 1)], ls.colacc[p]);
+      atomicMin(&rowk[us + 63 - t], rowp);
+      atomicMin(&colk[us + t * (C - 1)], ls.colacc[p]);
     }
   }
 }
@@ -641,8 +650,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   __shared__ uint32_t colk[NCOL];
   __shared__ double sseed[seed_stage_len<C>()];
   const int t = threadIdx.x;
-  for (int x = t; x < NROW; x += 64) rowk[x] = 0u;
-  for (int x = t; x < NCOL; x += 64) colk[x] = 0u;
+  for (int x = t; x < NROW; x += 64) rowk[x] = 0xFFFFFFFFu;
+  for (int x = t; x < NCOL; x += 64) colk[x] = 0xFFFFFFFFu;
   __syncthreads();
   const uint32_t keep = ~LMAX;
   uint32_t code[C];
@@ -702,7 +711,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
         ls.cdf[q] = cs.x;
         ls.cdg[q] = cs.y;
         ls.cinv[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
-        ls.colacc[q] = 0u;
+        ls.colacc[q] = 0xFFFFFFFFu;
       }
     }
     StepLoadF ring[PD];
@@ -710,21 +719,21 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     for (int k = 0; k < PD; ++k) ring[k] = load_step_f<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
-      const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
-      if (edge)
-        sjf_run_groups<C, true, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
-      else
-        sjf_run_groups<C, false, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
+      sjf_run_groups<C, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
       const bool last = (u0 + TL >= u_end);
       if (last) {
 #pragma unroll
-        for (int q = 0; q < C - 1; ++q) atomicMax(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
+        for (int q = 0; q < C - 1; ++q) atomicMin(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
       }
-      flush_block<C, TL>(rowk, colk, last, u0, db, n_sub, t, gro, gco, [GMAX](uint32_t key, int delta) {
-        const double v = (double)__uint_as_float(key & ~LMAX);
-        const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-        return (kb & ~GMAX) | (GMAX - (unsigned long long)delta);
-      });
+      flush_block<C, TL>(
+          rowk, colk, last, u0, db, n_sub, t, gro, gco, 0xFFFFFFFFu,
+          [GMAX](uint32_t key, int delta) {
+            // local keys order by 1 - rho (min); the global ones by 3 - that = rho + 2 (max)
+            const double v = 3.0 - (double)__uint_as_float(key & ~LMAX);
+            const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+            return (kb & ~GMAX) | (GMAX - (unsigned long long)delta);
+          },
+          [](uint32_t key) { return key < 0x7F800000u; });
     }
   }
 }

@@ -22,10 +22,11 @@
 // Work unit: one row panel (128 rows) times a segment of MFMA_SEG column
 // tiles of one (series, group).  4 waves, each a 64 x 64 quarter of the tile
 // (4 x 4 MFMA blocks).  Epilogue per cell: covariance correction, normalise,
-// key = bits(rho + 2) with the diagonal offset inside the segment in the low
-// 10 bits, running row maxima (kept across the segment) and column maxima
-// (flushed per tile); keys merge into the same global row/column key arrays
-// as the FP64 kernel, so the FP64 merge and polish are shared.
+// key = bits(1 - rho + 2^-16) with the diagonal offset inside the segment in
+// the low 10 bits, running row minima (kept across the segment) and column
+// minima (flushed per tile); keys merge into the same global row/column key
+// arrays (as 3 - key, maxima) as the FP64 kernel's, so the FP64 merge and
+// polish are shared.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -119,11 +120,15 @@ __device__ __forceinline__ void build_vectors(typename Elem<PREC>::T* dst, doubl
   }
 }
 
-__device__ __forceinline__ unsigned long long global_key(uint32_t key, int delta) {
-  // key: float bits of (rho + 2) with CODE_BITS low bits of code; keep the float part
-  const double v = (double)__uint_as_float(key & ~CODE_MASK);
+// Local keys: bits of the float 1 - rho + 2^-16 (ordered by minimum) with the
+// diagonal code in the low CODE_BITS bits; invalid cells carry 0xFFFFFFFF.
+// The global (merged) keys order by maximum: 3 - f = rho + 2 - 2^-16.
+constexpr float KEY_ONE = 1.0f + 1.52587890625e-5f;  // 1 + 2^-16
+constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned long long global_key(uint32_t key) {
+  const double v = 3.0 - (double)__uint_as_float(key & ~CODE_MASK);
   return (unsigned long long)__double_as_longlong(v);
-  (void)delta;
 }
 
 template <int PREC>
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
         const bool ok = i < n_sub;
         ma[rb][v] = ok ? (float)(-(double)m * (mu[i] - c)) : 0.f;
         ri[rb][v] = ok ? (float)invn[i] : 0.f;
-        rowacc[rb][v] = 0u;
+        rowacc[rb][v] = KEY_NONE;
       }
 
     for (int jt = jt0; jt <= jt1; ++jt) {
@@ -262,7 +267,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
       const bool masked = (J0 - (I0 + MT - 1) < st.excl) || (J0 + MT > n_sub) || (I0 + MT > n_sub);
       uint32_t colp[4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) colp[cb] = 0u;
+      for (int cb = 0; cb < 4; ++cb) colp[cb] = KEY_NONE;
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -270,30 +275,30 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float C = __builtin_fmaf(ma[rb][v], bj[cb], acc[rb][cb][v]);
-            const float kf = __builtin_fmaf(C * cj[cb], ri[rb][v], 2.0f);
+            const float kf = __builtin_fmaf(-(C * cj[cb]), ri[rb][v], KEY_ONE);  // 1 - rho + 2^-16
             uint32_t key = (__float_as_uint(kf) & ~CODE_MASK) | (uint32_t)(code_tile + 16 * (rb - cb) + v);
             if (masked) {
               const int i = I0 + 64 * wr + 16 * rb + 4 * lg + v;
               const int j = J0 + 64 * wc + 16 * cb + l16;
-              if (j - i < st.excl || j >= n_sub || i >= n_sub) key = 0u;
+              if (j - i < st.excl || j >= n_sub || i >= n_sub) key = KEY_NONE;
             }
-            rowacc[rb][v] = max(rowacc[rb][v], key);
-            colp[cb] = max(colp[cb], key);
+            rowacc[rb][v] = min(rowacc[rb][v], key);
+            colp[cb] = min(colp[cb], key);
           }
       // column maxima: combine the four lane groups holding the same column
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
-        colp[cb] = max(colp[cb], (uint32_t)__shfl_xor((int)colp[cb], 16));
-        colp[cb] = max(colp[cb], (uint32_t)__shfl_xor((int)colp[cb], 32));
+        colp[cb] = min(colp[cb], (uint32_t)__shfl_xor((int)colp[cb], 16));
+        colp[cb] = min(colp[cb], (uint32_t)__shfl_xor((int)colp[cb], 32));
       }
       if (lg == 0) {
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           const uint32_t key = colp[cb];
-          if (key) {
+          if (key < 0x7F800000u) {
             const int j = J0 + 64 * wc + 16 * cb + l16;
             const int delta = (Jseg0 - I0) + (CODE_TOP - (int)(key & CODE_MASK));
-            atomicMax(gco + j, (global_key(key, delta) & ~GMAX) | (GMAX - (unsigned long long)delta));
+            atomicMax(gco + j, (global_key(key) & ~GMAX) | (GMAX - (unsigned long long)delta));
           }
         }
       }
@@ -304,10 +309,10 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         uint32_t x = rowacc[rb][v];
-        x = max(x, (uint32_t)__shfl_xor((int)x, 1));
-        x = max(x, (uint32_t)__shfl_xor((int)x, 2));
-        x = max(x, (uint32_t)__shfl_xor((int)x, 4));
-        x = max(x, (uint32_t)__shfl_xor((int)x, 8));
+        x = min(x, (uint32_t)__shfl_xor((int)x, 1));
+        x = min(x, (uint32_t)__shfl_xor((int)x, 2));
+        x = min(x, (uint32_t)__shfl_xor((int)x, 4));
+        x = min(x, (uint32_t)__shfl_xor((int)x, 8));
         rowacc[rb][v] = x;
       }
     if (l16 == 0) {
@@ -316,10 +321,10 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const uint32_t key = rowacc[rb][v];
-          if (key) {
+          if (key < 0x7F800000u) {
             const int i = I0 + 64 * wr + 16 * rb + 4 * lg + v;
             const int delta = (Jseg0 - I0) + (CODE_TOP - (int)(key & CODE_MASK));
-            atomicMax(gro + i, (global_key(key, delta) & ~GMAX) | (GMAX - (unsigned long long)delta));
+            atomicMax(gro + i, (global_key(key) & ~GMAX) | (GMAX - (unsigned long long)delta));
           }
         }
     }
