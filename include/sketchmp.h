@@ -69,9 +69,10 @@ extern "C" {
 
 /* self-join precisions */
 #define SKMP_FP64 0   /* FP64 diagonal recurrence */
-#define SKMP_FP32 1   /* FP32 MFMA tiles, FP64 seeds and polish */
-#define SKMP_BF16X3 2 /* BF16 hi+lo split MFMA tiles, FP32 accumulation */
-#define SKMP_FP16X3 3 /* FP16 hi+lo split MFMA tiles, FP32 accumulation */
+#define SKMP_FP32 1   /* FP32 diagonal recurrence, exact FP64 seed every `refresh` rows */
+#define SKMP_BF16X3 2 /* Hankel tiles on MFMA, BF16 hi+lo split products, FP32 accumulation */
+#define SKMP_FP16X3 3 /* Hankel tiles on MFMA, FP16 hi+lo split products, FP32 accumulation */
+/* Every precision reports the exact FP64 distance of the neighbour it finds. */
 
 /* flags for sketch_build / sketch_update_dims */
 #define SKMP_FLAG_CHECK_FINITE 1u /* synchronise and reject NaN/Inf input */
@@ -146,7 +147,8 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  * Self-join matrix profile of every sketched series (Def. 6 with
  * T_test = T_train, Section III-B), z-normalised Euclidean distance (Def. 3).
  *   R        device, k x N doubles, row stride ldr (sketch_build output).
- *   m        subsequence length, 4 <= m; every series needs n_s >= m.
+ *   m        subsequence length, 4 <= m <= 2048 (<= 1024 for BF16x3 / FP16x3);
+ *            every series needs n_s >= m.
  *   excl     trivial-match exclusion: (i, j) is excluded iff |i - j| < excl; 1 <= excl.
  *   prec     SKMP_FP64 | SKMP_FP32 | SKMP_BF16X3 | SKMP_FP16X3.
  *   refresh  SKMP_FP32: rows between exact FP64 recomputations of the running

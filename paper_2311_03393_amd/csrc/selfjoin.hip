@@ -2,11 +2,12 @@
 // self-join variant of Section III-B), FP64 diagonal kernel + shared stages.
 //
 // Stages (all on the caller's stream):
-//   fill      zero the key arrays, queue head and flat-window summaries;
+//   init      queue head and flat-window summaries;
 //   scale     max |r| per (series, group): the flat-window threshold;
 //   substats  per window x: mean, 1/(sqrt(m) sigma) (0 if flat), and the
 //             difference terms df_x = (r[x+m] - r[x]) / 2,
-//             dg_x = (r[x+m] - mu[x+1]) + (r[x] - mu[x]), all FP64;
+//             dg_x = (r[x+m] - mu[x+1]) + (r[x] - mu[x]), all FP64 (plus
+//             FP32 copies for the FP32 kernel); zeroes the key arrays;
 //   tiles     the diagonal recurrence of the centred covariance
 //             C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i, seeded exactly in
 //             FP64, rho = C / (m sigma_i sigma_j), row and column maxima with the
@@ -19,9 +20,12 @@
 // sits on row i = u - t, so the 64 lanes touch 64 distinct rows and, through
 // the sliding window of C columns each lane keeps, 64 distinct retiring
 // columns: per-step partial maxima go to LDS with ds_max_u64 without
-// conflicts.  Every TL steps the LDS partials are flushed into the global key
-// arrays with 64-bit atomic max.  A work unit is one strip of S steps of one
-// band of one (series, group); the queue hands units out dynamically.
+// conflicts.  Every TL steps the rows and columns that no later step of the
+// unit can reach are flushed into the global key arrays with 64-bit atomic
+// max; the others stay in LDS.  A work unit is one strip of S steps of one
+// band of one (series, group); the queue hands units out dynamically.  The
+// FP32 kernel (below) walks the same geometry; the BF16x3 / FP16x3 MFMA
+// tiles are in selfjoin_mixed.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -584,12 +588,6 @@ __device__ __forceinline__ StepLoadF load_step_f(const StatRsrcF& R, int u, int 
   l.cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
   l.cinv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
   return l;
-}
-
-__device__ __forceinline__ float vmaxf(float a, float b) {
-  float r;
-  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-  return r;
 }
 
 template <int C>
