@@ -10,8 +10,9 @@
 //             FP32 copies for the FP32 kernel); zeroes the key arrays;
 //   tiles     the diagonal recurrence of the centred covariance
 //             C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i, seeded exactly in
-//             FP64, rho = C / (m sigma_i sigma_j), row and column maxima with the
-//             partner encoded in the low mantissa bits of (rho + 2);
+//             FP64, rho = C / (m sigma_i sigma_j), row and column nearest
+//             neighbours as minima of 1 - rho with the partner encoded in the
+//             low mantissa bits;
 //   merge     pick the best row / column key, apply the flat-window rule and
 //             recompute the reported distance exactly from explicit differences.
 //
@@ -19,7 +20,7 @@
 // diagonals, lane t owning diagonals db + t*C + q (q < C).  At step u lane t
 // sits on row i = u - t, so the 64 lanes touch 64 distinct rows and, through
 // the sliding window of C columns each lane keeps, 64 distinct retiring
-// columns: per-step partial maxima go to LDS with ds_max_u64 without
+// columns: per-step partial minima go to LDS with ds_min_u64 without
 // conflicts.  Every TL steps the rows and columns that no later step of the
 // unit can reach are flushed into the global key arrays with 64-bit atomic
 // max; the others stay in LDS.  A work unit is one strip of S steps of one
@@ -195,14 +196,23 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   }
 }
 
-// v_max_f64 without the canonicalising copy the compiler adds to IEEE fmax for
+// v_min_f64 without the canonicalising copy the compiler adds to IEEE fmin for
 // operands it cannot prove canonical (the keys are bit-manipulated).  IEEE-mode
-// max returns the non-NaN operand, which masks padded cells.
-__device__ __forceinline__ double vmax(double a, double b) {
+// min returns the non-NaN operand, which masks padded cells.
+__device__ __forceinline__ double vmin(double a, double b) {
   double r;
-  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
   return r;
 }
+
+// FP64 local keys: 1 - rho + 2^-40 (positive; FP64 rounding of rho is far
+// below the bias) with the lane's diagonal code in the low bits, ordered by
+// minimum; as positive doubles their bit patterns order like u64, so the LDS
+// partials use ds_min_u64.  ~0 marks an empty partial, NaN bits (padded
+// cells) lie above every real key.  Flushing converts to the global form
+// 3 - key (= rho + 2, ordered by maximum).
+constexpr double KEY_ONE64 = 1.0 + 9.094947017729282e-13;  // 1 + 2^-40
+constexpr unsigned long long KEY_NONE64 = ~0ull;
 
 __device__ __forceinline__ double embed(double x, uint32_t keep, uint32_t code) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x);
@@ -331,7 +341,7 @@ __device__ __forceinline__ StepLoad load_step(const StatRsrc& R, int u, int U, i
 // CL = false: each lane keeps a running maximum per open column and retires
 // one column per step into LDS; CL = true: every cell's key goes straight to
 // LDS with ds_max_u64 (fewer VALU max instructions, more LDS atomics).
-template <int C, bool EDGE, int PD, bool CL>
+template <int C, int PD, bool CL>
 __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)[PD], const uint32_t (&code)[C],
                                               uint32_t keep, int ngroups, int u0, int db, const StatRsrc& R,
                                               unsigned long long* rowk, unsigned long long* colk, int t) {
@@ -358,21 +368,21 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
       for (int q = 0; q < C; ++q) {
         const int sl = (p + q) % C;
         const double a = ls.Cq[q] * ls.cinv[sl];
-        double key = fma(a, rinv, 2.0);
+        double key = fma(-a, rinv, KEY_ONE64);  // 1 - rho + 2^-40
         key = embed(key, keep, code[q]);
-        if (q == 0) rowp = EDGE ? vmax(0.0, key) : key;
-        else rowp = vmax(rowp, key);
+        if (q == 0) rowp = key;
+        else rowp = vmin(rowp, key);
         if (CL) {
-          atomicMax(&colk[us + t * (C - 1) + q], kbits(EDGE ? vmax(0.0, key) : key));
+          atomicMin(&colk[us + t * (C - 1) + q], kbits(key));
         } else {
-          if (q == C - 1) ls.colacc[sl] = EDGE ? vmax(0.0, key) : key;
-          else ls.colacc[sl] = vmax(ls.colacc[sl], key);
+          if (q == C - 1) ls.colacc[sl] = key;
+          else ls.colacc[sl] = vmin(ls.colacc[sl], key);
         }
         ls.Cq[q] = fma(rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = fma(ls.cdf[sl], rs.y, ls.Cq[q]);
       }
-      atomicMax(&rowk[us + 63 - t], kbits(rowp));
-      if (!CL) atomicMax(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
+      atomicMin(&rowk[us + 63 - t], kbits(rowp));
+      if (!CL) atomicMin(&colk[us + t * (C - 1)], kbits(ls.colacc[p]));
     }
   }
 }
@@ -448,8 +458,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   __shared__ unsigned long long colk[NCOL];
   __shared__ double sseed[seed_stage_len<C>()];
   const int t = threadIdx.x;
-  for (int x = t; x < NROW; x += 64) rowk[x] = 0ull;
-  for (int x = t; x < NCOL; x += 64) colk[x] = 0ull;
+  for (int x = t; x < NROW; x += 64) rowk[x] = KEY_NONE64;
+  for (int x = t; x < NCOL; x += 64) colk[x] = KEY_NONE64;
   __syncthreads();
   const uint32_t keep = ~LMAX;
   uint32_t code[C];
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
         ls.cdf[q] = cs.x;
         ls.cdg[q] = cs.y;
         ls.cinv[q] = invn[J + q];
-        ls.colacc[q] = 0.0;
+        ls.colacc[q] = __longlong_as_double((long long)KEY_NONE64);
       }
     }
 
@@ -517,22 +527,21 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
     for (int k = 0; k < PD; ++k) ring[k] = load_step<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
-      const bool edge = (u0 < 63) || ((int64_t)u0 + (int64_t)ngroups * C + db + 64 * C - 64 > n_sub);
-      if (edge)
-        sj_run_groups<C, true, PD, CL>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
-      else
-        sj_run_groups<C, false, PD, CL>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
+      sj_run_groups<C, PD, CL>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
       const bool last = (u0 + TL >= u_end);
       if (last && !CL) {
         // retire the columns still open in the window (phase 0 after full groups)
 #pragma unroll
         for (int q = 0; q < C - 1; ++q)
-          atomicMax(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
+          atomicMin(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
       }
       flush_block<C, TL>(
-          rowk, colk, last, u0, db, n_sub, t, gro, gco, 0ull,
-          [GMAX](unsigned long long key, int delta) { return (key & ~GMAX) | (GMAX - (unsigned long long)delta); },
-          [](unsigned long long key) { return key != 0ull; });
+          rowk, colk, last, u0, db, n_sub, t, gro, gco, KEY_NONE64,
+          [GMAX](unsigned long long key, int delta) {
+            const double v = 3.0 - __longlong_as_double((long long)(key & ~(unsigned long long)LMAX));
+            return ((unsigned long long)__double_as_longlong(v) & ~GMAX) | (GMAX - (unsigned long long)delta);
+          },
+          [](unsigned long long key) { return key < 0x7FF0000000000000ull; });
     }
   }
 }
@@ -962,7 +971,7 @@ static void launch_fp64(dim3 grid, hipStream_t st, const SJState& s) {
 static const Fp64Variant kFp64Variants[] = {
     SKMP_FP64_V(8, 1, 2, false), SKMP_FP64_V(8, 1, 2, true),  SKMP_FP64_V(8, 2, 2, true),
     SKMP_FP64_V(10, 1, 2, true), SKMP_FP64_V(12, 1, 2, true), SKMP_FP64_V(6, 1, 3, true),
-    SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true),
+    SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true), SKMP_FP64_V(8, 1, 3, false),
 };
 #undef SKMP_FP64_V
 constexpr int kNumFp64Variants = sizeof(kFp64Variants) / sizeof(kFp64Variants[0]);
@@ -979,7 +988,7 @@ static void launch_fp32(dim3 grid, hipStream_t st, const SJState& s) {
   }
 static const Fp64Variant kFp32Variants[] = {
     SKMP_FP32_V(8, 1, 2), SKMP_FP32_V(16, 1, 2), SKMP_FP32_V(8, 1, 3), SKMP_FP32_V(12, 1, 2), SKMP_FP32_V(8, 2, 3),
-    SKMP_FP32_V(16, 2, 2),
+    SKMP_FP32_V(16, 2, 2), SKMP_FP32_V(16, 1, 3), SKMP_FP32_V(16, 2, 3),
 };
 #undef SKMP_FP32_V
 constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
@@ -992,7 +1001,7 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 // window count), or by the built-in defaults.  FP32 units restart from an
 // exact FP64 seed, so their strip is always the refresh period.
 constexpr int kDefaultFp64Variant = 0;
-constexpr int kDefaultFp32Variant = 1;
+constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 1, 3 waves per SIMD (spills 12 VGPRs outside the inner loop; fastest measured)
 static const int kTuneStrips[] = {1024, 2048, 4096};
 
 struct TuneKey {
