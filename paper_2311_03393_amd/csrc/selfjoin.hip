@@ -1001,7 +1001,7 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 // window count), or by the built-in defaults.  FP32 units restart from an
 // exact FP64 seed, so their strip is always the refresh period.
 constexpr int kDefaultFp64Variant = 0;
-constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 1, 3 waves per SIMD (spills 12 VGPRs outside the inner loop; fastest measured)
+constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (spills 12 VGPRs outside the inner loop; fastest measured)
 static const int kTuneStrips[] = {1024, 2048, 4096};
 
 struct TuneKey {
