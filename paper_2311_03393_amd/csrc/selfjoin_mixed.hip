@@ -78,45 +78,54 @@ static __host__ __device__ inline int centring_block(int m) { return m <= 64 ? 1
 static __host__ __device__ inline int block_len(int m) { return centring_block(m) + mpad(m); }
 static __host__ __device__ inline int block_stride(int m) { return block_len(m) + 8; }
 
+// staged positions per centring block (the copies read up to block_len + 6)
+static __host__ __device__ inline int stage_len(int m) { return block_len(m) + 8; }
+
 size_t mfma_lds_bytes(int m) {
   const int nb = MT / centring_block(m);
-  // a and b: nb blocks x 2 parts x 8 copies x block_stride 16-bit elements; staging doubles
-  return (size_t)2 * nb * 16 * block_stride(m) * 2 + (size_t)(MT + mpad(m) + 8) * 8;
+  // a and b: nb blocks x 2 parts x 8 copies x block_stride 16-bit elements;
+  // staging: nb blocks x 2 parts x stage_len 16-bit elements
+  return (size_t)2 * nb * 16 * block_stride(m) * 2 + (size_t)nb * 2 * stage_len(m) * 2;
 }
 
-// Stage r[base + x] (0 past the series), then for every centring block q build
-// the hi / lo copies of v_q[x] = r[base + q BC + x] - c_q: copy s of block q
-// holds v_q[P + s] at position P.  Layout: ((q * 2 + part) * 8 + s) * bs + P.
+// For every centring block q, v_q[x] = r[base + q BC + x] - c_q (0 past the
+// series) is split once into 16-bit hi + lo (hi = v rounded, lo = v - hi
+// rounded; v - hi is exact in FP32) and staged; then the eight copies are
+// assembled from the staged halves: copy s of block q holds v_q[P + s] at
+// position P, so a lane's 8-element K fragment is one aligned 16-byte read.
+// Layout: copies ((q * 2 + part) * 8 + s) * bs + P; staging (q * 2 + part) *
+// stage_len + x.
 template <int PREC>
-__device__ __forceinline__ void build_vectors(typename Elem<PREC>::T* dst, double* stage, const double* __restrict__ r,
-                                              const double* __restrict__ mu, int64_t base, int64_t n, int n_sub, int m,
-                                              int tid) {
+__device__ __forceinline__ void build_vectors(typename Elem<PREC>::T* dst, uint16_t* st16,
+                                              const double* __restrict__ r, const double* __restrict__ mu,
+                                              int64_t base, int64_t n, int n_sub, int m, int tid) {
   using E = Elem<PREC>;
   using T = typename E::T;
   const int bc = centring_block(m), nbk = MT / bc, blen = block_len(m), bs = block_stride(m);
-  const int span = MT + mpad(m) + 8;
-  for (int x = tid; x < span; x += 256) {
-    const int64_t q = base + x;
-    stage[x] = (q < n) ? r[q] : 0.0;
+  const int sl = stage_len(m);
+  for (int w = tid; w < nbk * sl; w += 256) {
+    const int q = w / sl, x = w - q * sl;
+    const int64_t g = base + q * bc + x;
+    const double c = mu[min((int)base + q * bc + bc / 2, n_sub - 1)];
+    const float f = (g < n) ? (float)(r[g] - c) : 0.0f;
+    const T h = E::cvt(f);
+    const T l = E::cvt(f - E::back(h));
+    st16[(q * 2 + 0) * sl + x] = __builtin_bit_cast(uint16_t, h);
+    st16[(q * 2 + 1) * sl + x] = __builtin_bit_cast(uint16_t, l);
   }
   __syncthreads();
   const int nblk = blen / 8;
-  for (int w = tid; w < nbk * 8 * nblk; w += 256) {
-    const int q = w / (8 * nblk);
-    const int rem = w - q * 8 * nblk;
+  for (int w = tid; w < nbk * 2 * 8 * nblk; w += 256) {
+    const int qp = w / (8 * nblk);  // q * 2 + part
+    const int rem = w - qp * 8 * nblk;
     const int s = rem / nblk, blk = rem - s * nblk;
-    const double c = mu[min((int)base + q * bc + bc / 2, n_sub - 1)];
-    typename E::V hi, lo;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int x = q * bc + blk * 8 + s + e;
-      const double v = (base + x < n) ? stage[x] - c : 0.0;
-      const T h = E::cvt((float)v);
-      hi[e] = h;
-      lo[e] = E::cvt((float)(v - (double)E::back(h)));
-    }
-    *reinterpret_cast<typename E::V*>(dst + ((q * 2 + 0) * 8 + s) * bs + blk * 8) = hi;
-    *reinterpret_cast<typename E::V*>(dst + ((q * 2 + 1) * 8 + s) * bs + blk * 8) = lo;
+    const uint16_t* src = st16 + qp * sl + blk * 8 + s;
+    uint4 v;
+    v.x = (uint32_t)src[0] | ((uint32_t)src[1] << 16);
+    v.y = (uint32_t)src[2] | ((uint32_t)src[3] << 16);
+    v.z = (uint32_t)src[4] | ((uint32_t)src[5] << 16);
+    v.w = (uint32_t)src[6] | ((uint32_t)src[7] << 16);
+    *reinterpret_cast<uint4*>(dst + (qp * 8 + s) * bs + blk * 8) = v;
   }
 }
 
@@ -145,7 +154,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
   const int nbk = MT / bc;
   T* acp = reinterpret_cast<T*>(lds);
   T* bcp = acp + nbk * 16 * bs;
-  double* stage = reinterpret_cast<double*>(bcp + nbk * 16 * bs);
+  uint16_t* stage = reinterpret_cast<uint16_t*>(bcp + nbk * 16 * bs);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
