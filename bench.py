@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 # (FP64 FMA is full rate; FP32 without packed math issues at the same rate)
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MAX (row, column)
+MFMA_16BIT_PEAK = 2.5e15  # dense BF16 / FP16 matrix-core peak of MI355X, FLOP/s
 NAMED = {"c0": ("fp64", 0), "c1": ("fp32", 256), "c2": ("bf16x3", 0), "c3": ("fp32", 256), "c4": ("fp16x3", 0)}
 DESCR = {
     "c0": "random-walk+sine d=8 n=4096 sum sketch k=1 m=64 excl=16",
@@ -142,6 +143,10 @@ def _cpu_baseline(R_host_series, w, target_s: float):
     }
 
 
+def _progress(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def main() -> int:
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -215,6 +220,7 @@ def main() -> int:
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        _progress(f"{pr}: {warmup} warmup step(s) done")
         graph = None
         if args.graph:
             graph = torch.cuda.CUDAGraph()
@@ -238,6 +244,7 @@ def main() -> int:
                 step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        _progress(f"{pr}: {steps} timed step(s), {(t1 - t0) * 1e3 / steps:.3f} ms each")
         skmp.timing_enable(False)
         stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
         del ws, graph
@@ -250,6 +257,8 @@ def main() -> int:
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
             "tile_frac_of_valu_issue": OPS_PER_CELL * valid / tile_avg_s / VALU_LANE_OPS_PEAK,
+            "tile_frac_of_mfma_peak": (6.0 * m * valid / tile_avg_s / MFMA_16BIT_PEAK
+                                       if pr in ("bf16x3", "fp16x3") else None),
             "stages_ms_per_step": {st: v[0] / max(steps, 1) for st, v in stage.items()},
             "top10": [int(x) for x in out[0][0].cpu()],
         }
@@ -305,22 +314,42 @@ def main() -> int:
     profiles.clear()
 
     tile_avg_s = head["tile_kernel_ms"] * 1e-3
-    achieved = OPS_PER_CELL * valid / tile_avg_s
     tr = _traffic(KERNELS[prec], args.workload)
-    roofline = {
-        "bound": "alu",
-        "achieved": achieved / 1e12,
-        "peak": VALU_LANE_OPS_PEAK / 1e12,
-        "unit": "Tops/s",
-        "frac": achieved / VALU_LANE_OPS_PEAK,
-        "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
-        "traffic_detail": tr,
-        "kernel": KERNELS[prec],
-        "per_launch": {"cells": valid, "ops_per_cell": OPS_PER_CELL, "avg_ms": head["tile_kernel_ms"],
-                       "launches": head["tile_launches"]},
-        "basis": "VALU issue: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 6 lane-ops (2 FMA, 2 MUL, 2 MAX) "
-                 "per valid half-matrix cell",
-    }
+    if prec in ("bf16x3", "fp16x3"):
+        # Hankel-block products on the matrix cores: three 16-bit products (hi*hi, hi*lo, lo*hi) of
+        # length m per valid cell, 2 flops per multiply-add
+        flops = 6.0 * m * valid
+        achieved = flops / tile_avg_s
+        roofline = {
+            "bound": "mfma",
+            "achieved": achieved / 1e12,
+            "peak": MFMA_16BIT_PEAK / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / MFMA_16BIT_PEAK,
+            "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
+            "traffic_detail": tr,
+            "kernel": KERNELS[prec],
+            "per_launch": {"cells": valid, "flops_per_cell": 6 * m, "avg_ms": head["tile_kernel_ms"],
+                           "launches": head["tile_launches"]},
+            "basis": "dense 16-bit MFMA peak 2.5 PFLOP/s; 3 products x 2m flops per valid half-matrix cell",
+            "valu_equivalent_frac": OPS_PER_CELL * valid / tile_avg_s / VALU_LANE_OPS_PEAK,
+        }
+    else:
+        achieved = OPS_PER_CELL * valid / tile_avg_s
+        roofline = {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": VALU_LANE_OPS_PEAK / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved / VALU_LANE_OPS_PEAK,
+            "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
+            "traffic_detail": tr,
+            "kernel": KERNELS[prec],
+            "per_launch": {"cells": valid, "ops_per_cell": OPS_PER_CELL, "avg_ms": head["tile_kernel_ms"],
+                           "launches": head["tile_launches"]},
+            "basis": "VALU issue: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 6 lane-ops (2 FMA, 2 MUL, "
+                     "2 MAX) per valid half-matrix cell",
+        }
     # the sketch stage is HBM-bound: T is read twice (statistics, projection), R written once
     sk_ms = head["stages_ms_per_step"]["sketch"]
     sk_bytes = 2.0 * d * N * T.element_size() + k * N * 8.0
