@@ -28,6 +28,7 @@ constexpr int SEL_THREADS = 256;
 constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int MAX_TOPK = 256;
 constexpr int SEL_LDS_BLOCKS = 4096;
+constexpr int RESCAN_BATCH = 4;  // (1 << DISC_BLK_MIN_SHIFT) / 64: a whole minimum-size block per lane
 
 struct DiscSeries {
   int64_t col;
@@ -222,19 +223,31 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
         const int64_t w1 = min(w0 + B, sr.n_sub);
         double x = -INFINITY;
         int xi = INT_MAX, xg = -1;
-        for (int64_t i = w0 + lane; i < w1; i += 64) {
-          const double a = st.A[sr.col + i];
-          const int ga = st.G[sr.col + i];
-          if (!(a > -INFINITY) || !better(a, i, x, xi)) continue;
-          bool masked = false;
-          for (int q = 0; q <= pass; ++q) {
-            const int64_t p = picks[q];
-            masked |= (i - p < h) && (p - i < h);
+        // all RESCAN_BATCH loads of a lane are issued before any is used, so a
+        // pass waits for one memory round trip instead of one per load
+        for (int64_t i0 = w0 + lane; i0 < w1; i0 += 64 * RESCAN_BATCH) {
+          double a[RESCAN_BATCH];
+          int ga[RESCAN_BATCH];
+#pragma unroll
+          for (int u = 0; u < RESCAN_BATCH; ++u) {
+            const int64_t i = i0 + 64 * u;
+            a[u] = i < w1 ? st.A[sr.col + i] : -INFINITY;
+            ga[u] = i < w1 ? st.G[sr.col + i] : -1;
           }
-          if (!masked) {
-            x = a;
-            xi = (int)i;
-            xg = ga;
+#pragma unroll
+          for (int u = 0; u < RESCAN_BATCH; ++u) {
+            const int64_t i = i0 + 64 * u;
+            if (!(a[u] > -INFINITY) || !better(a[u], i, x, xi)) continue;
+            bool masked = false;
+            for (int q = 0; q <= pass; ++q) {
+              const int64_t p = picks[q];
+              masked |= (i - p < h) && (p - i < h);
+            }
+            if (!masked) {
+              x = a[u];
+              xi = (int)i;
+              xg = ga[u];
+            }
           }
         }
         wave_best(x, xi, xg);

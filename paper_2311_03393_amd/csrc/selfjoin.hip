@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void scale_kernel(SJState st) {
 }
 
 __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
-  extern __shared__ double sh_r[];  // 256 + m + 1 samples
+  extern __shared__ double sh_r[];  // 256 + m + 1 samples, then the 256 window means
   const ChunkPos c = decode_chunk(st, blockIdx.x);
   const SeriesPlan& sp = st.plan[c.s];
   const int m = st.m;
@@ -131,6 +131,19 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   }
   __syncthreads();
   const int64_t x = c.x0 + threadIdx.x;
+  const double* w = sh_r + threadIdx.x;
+  const double inv_m = 1.0 / m;
+  // window means first: the mean of window x + 1 (needed for dg) is read from
+  // its own thread, so both uses of it carry the same bits
+  double* smu = sh_r + span;
+  double mu = 0.0;
+  if (x >= 0 && x < sp.n_sub) {
+    double s = 0.0;
+    for (int q = 0; q < m; ++q) s += w[q];
+    mu = s * inv_m;
+  }
+  smu[threadIdx.x] = mu;
+  __syncthreads();
   // the chunk grid rounds each group's padded range up to 256: stay inside it
   if (x >= sp.lpad - PADL) return;
   const int64_t gbase = (int64_t)c.gi * st.gstride + sp.stat_base;
@@ -155,11 +168,6 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     }
     return;
   }
-  const double* w = sh_r + threadIdx.x;
-  const double inv_m = 1.0 / m;
-  double s = 0.0;
-  for (int q = 0; q < m; ++q) s += w[q];
-  const double mu = s * inv_m;
   double v = 0.0;
   for (int q = 0; q < m; ++q) {
     const double e = w[q] - mu;
@@ -170,9 +178,14 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   const bool flat = sd <= FLAT_REL * scale;
   double df = 0.0, dg = 0.0;
   if (x + 1 < sp.n_sub) {
-    double s1 = 0.0;
-    for (int q = 1; q <= m; ++q) s1 += w[q];
-    const double mu1 = s1 * inv_m;
+    double mu1;
+    if (threadIdx.x + 1 < 256) {
+      mu1 = smu[threadIdx.x + 1];
+    } else {  // window x + 1 belongs to the next chunk: same sum, same order
+      double s1 = 0.0;
+      for (int q = 1; q <= m; ++q) s1 += w[q];
+      mu1 = s1 * inv_m;
+    }
     df = 0.5 * (w[m] - w[0]);
     dg = (w[m] - mu1) + (w[0] - mu);
   }
@@ -1193,7 +1206,7 @@ static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const in
     StageTimer tm(SKMP_TIMER_SUBSTATS, st);
     hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((pl.total_chunks + SCALE_CHUNKS - 1) / SCALE_CHUNKS)), fb, 0, st,
                        s);
-    hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1), st, s);
+    hipLaunchKernelGGL(substats_kernel, cg, fb, sizeof(double) * (256 + m + 1 + 256), st, s);
   }
   SKMP_CHECK_HIP(hipGetLastError());
 

@@ -6,8 +6,9 @@
 //              reduces one 64K-sample chunk with a shifted sum (shift = the
 //              chunk's first value); chunk partials (n, mean, M2) are merged in
 //              order with Chan's pairwise update.
-//   project:   one thread per time column walks the d dimensions, normalises
-//              each value and accumulates k sketch rows in FP64:
+//   project:   a wave owns 64 V consecutive time columns, walks the
+//              dimensions of its slice, normalises each value and accumulates
+//              k sketch rows in FP64:
 //              R[g][t] = sum_j S[g][j] * (T[j][t] - mu_j) / sigma_j.
 // The coefficient matrix S is drawn on the host (integer hashing and glibc
 // libm) and copied to the workspace; it is a pure function of (kind, k, seed,
@@ -16,6 +17,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -199,80 +201,207 @@ __global__ void dimstats_finalize(const StatPartial* __restrict__ part, const in
 
 // R[g][t] (mode 0: =, +1: +=, -1: -=) sum_j S[g][j] (T[j][t] - mu_j) / sigma_j
 // (Algorithm 1; sigma_j = 0 marks a constant dimension, which contributes 0).
-// A block covers 64 columns with SL waves, wave w summing the dimensions of
-// slice w; each lane keeps PF loads of T in flight, so the pass runs at
-// memory speed even for d in the thousands, and the slices' partial sums
-// meet in LDS.  Coefficients S are uniform (scalar loads); coef holds
-// (mu, 1/sigma) per (series, dimension) (1/sigma = 0 for a constant
-// dimension), so normalising costs a subtract and a multiply.
+//
+// A wave owns a tile of 64 V consecutive columns (V per lane, one 8- or
+// 16-byte load per row) and walks the rows of its slice of the dimensions
+// (SL waves per block split d; their partial sums meet in LDS in a fixed
+// order, so results are reproducible bit for bit).  PROJ_PF rows are loaded
+// before any is used.  The coefficients are stored transposed and padded to
+// KB groups (St[j][g], zero past k), so one row's coefficients are one
+// contiguous uniform read (scalar loads, SGPR operands of the FMAs) and the
+// inner loops carry no guards.  (mu, 1/sigma) per (series, dimension) comes
+// from coef.  A block walks tiles_per_block consecutive tiles; the series of a
+// tile is found by a wave-wide 64-ary search and kept while the tiles stay
+// inside it.  Tiles that straddle a series boundary or the end of the data
+// take a per-column path.
 constexpr int PROJ_PF = 8;
+constexpr int PROJ_LDS_BYTES = 48 * 1024;
 
-template <typename TIn, int KB>
-__device__ __forceinline__ void project_slice(const TIn* __restrict__ T, int64_t ldt, int64_t j0, int64_t j1,
-                                              int64_t tt, const double* __restrict__ st,
-                                              const double* __restrict__ S, int64_t d, int k, double (&acc)[KB]) {
-  for (int64_t j = j0; j < j1; j += PROJ_PF) {
-    double x[PROJ_PF];
+// The series s with offsets[s] <= c < offsets[s + 1], by all 64 lanes of a
+// wave (c uniform, 0 <= c < offsets[n_series]): every round probes 64 evenly
+// spaced entries and keeps the span between the last probe <= c and the next.
+__device__ __forceinline__ int series_of(const int64_t* __restrict__ offsets, int n_series, int64_t c, int lane) {
+  int lo = 0, hi = n_series - 1;
+  while (hi > lo) {
+    const int step = (hi - lo + 64) / 64;
+    const int p = lo + lane * step;
+    const bool le = p <= hi && offsets[p] <= c;
+    const unsigned long long b = __ballot(le);  // a prefix of the lanes (offsets increase); lane 0 always
+    const int L = 64 - __clzll(b);
+    lo = lo + (L - 1) * step;
+    hi = min(hi, lo + step - 1);
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Per-lane binary search (columns of a tile that straddles a series boundary).
+__device__ __forceinline__ int series_of_lane(const int64_t* __restrict__ offsets, int n_series, int64_t c) {
+  int lo = 0, hi = n_series - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offsets[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename TIn, int V>
+__device__ __forceinline__ void load_cols(const TIn* __restrict__ p, TIn (&x)[V]) {
+  static_assert(V == 1 || sizeof(TIn) * V == 8 || sizeof(TIn) * V == 16, "8- or 16-byte column groups");
+  if constexpr (V == 1) {
+    x[0] = p[0];
+  } else if constexpr (sizeof(TIn) * V == 8) {
+    const float2 q = *reinterpret_cast<const float2*>(p);
+    x[0] = q.x;
+    x[1] = q.y;
+  } else if constexpr (sizeof(TIn) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    x[0] = q.x;
+    x[1] = q.y;
+    x[2] = q.z;
+    x[3] = q.w;
+  } else {
+    const double2 q = *reinterpret_cast<const double2*>(p);
+    x[0] = q.x;
+    x[1] = q.y;
+  }
+}
+
+// Rows [j0, j1) of a full tile inside one series: cu = that series' coef row (uniform).
+template <typename TIn, int KB, int V>
+__device__ __forceinline__ void rows_uniform(const TIn* __restrict__ T, int64_t ldt, int j0, int j1, int64_t t,
+                                             const double* __restrict__ cu, const double* __restrict__ St,
+                                             double (&acc)[KB][V]) {
+  int j = j0;
+  for (; j + PROJ_PF <= j1; j += PROJ_PF) {
+    TIn x[PROJ_PF][V];
 #pragma unroll
-    for (int u = 0; u < PROJ_PF; ++u) x[u] = (j + u < j1) ? (double)T[(j + u) * ldt + tt] : 0.0;
+    for (int u = 0; u < PROJ_PF; ++u) load_cols<TIn, V>(T + (int64_t)(j + u) * ldt + t, x[u]);
 #pragma unroll
     for (int u = 0; u < PROJ_PF; ++u) {
-      if (j + u < j1) {
-        const double xb = (x[u] - st[2 * (j + u)]) * st[2 * (j + u) + 1];
+      const double mu = cu[2 * (j + u)], is = cu[2 * (j + u) + 1];
+      const double* __restrict__ sr = St + (int64_t)(j + u) * KB;
+      double xb[V];
 #pragma unroll
-        for (int g = 0; g < KB; ++g)
-          if (g < k) acc[g] = fma(S[(int64_t)g * d + j + u], xb, acc[g]);
+      for (int v = 0; v < V; ++v) xb[v] = ((double)x[u][v] - mu) * is;
+#pragma unroll
+      for (int g = 0; g < KB; ++g) {
+        const double c = sr[g];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[g][v] = fma(c, xb[v], acc[g][v]);
       }
+    }
+  }
+  for (; j < j1; ++j) {
+    TIn x[V];
+    load_cols<TIn, V>(T + (int64_t)j * ldt + t, x);
+    const double mu = cu[2 * j], is = cu[2 * j + 1];
+    const double* __restrict__ sr = St + (int64_t)j * KB;
+#pragma unroll
+    for (int g = 0; g < KB; ++g) {
+      const double c = sr[g];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[g][v] = fma(c, ((double)x[v] - mu) * is, acc[g][v]);
     }
   }
 }
 
-template <typename TIn, int KB, int SL>
-__global__ __launch_bounds__(64 * SL) void project_kernel(const TIn* __restrict__ T, int64_t ldt, int64_t d, int64_t N,
-                                                          const int64_t* __restrict__ offsets, int n_series,
-                                                          const double* __restrict__ coef,
-                                                          const double* __restrict__ S, int k, double* __restrict__ R,
-                                                          int64_t ldr, int mode) {
-  __shared__ double part[(SL > 1 ? SL - 1 : 1) * KB * 64];
-  const int lane = threadIdx.x & 63;
-  const int sl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's slice (uniform)
-  const int64_t t = (int64_t)blockIdx.x * 64 + lane;
-  const bool valid = t < N;
-  const int64_t tt = valid ? t : N - 1;
-  int lo = 0, hi = n_series - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (offsets[mid] <= tt) lo = mid; else hi = mid - 1;
+// Rows [j0, j1) for columns t + v that may lie past N or in different series.
+template <typename TIn, int KB, int V>
+__device__ __forceinline__ void rows_general(const TIn* __restrict__ T, int64_t ldt, int64_t d, int j0, int j1,
+                                             int64_t t, int64_t N, const int64_t* __restrict__ offsets,
+                                             int n_series, const double* __restrict__ coef,
+                                             const double* __restrict__ St, double (&acc)[KB][V]) {
+  const double* cp[V];
+  bool ok[V];
+  int64_t cc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    ok[v] = t + v < N;
+    cc[v] = ok[v] ? t + v : N - 1;
+    cp[v] = coef + (int64_t)series_of_lane(offsets, n_series, cc[v]) * d * 2;
   }
-  const int64_t j0 = d * sl / SL, j1 = d * (sl + 1) / SL;
-  double acc[KB];
+  for (int j = j0; j < j1; ++j) {
+    const double* __restrict__ sr = St + (int64_t)j * KB;
+    double xb[V];
 #pragma unroll
-  for (int g = 0; g < KB; ++g) acc[g] = 0.0;
-  // a wave inside one series reads (mu, 1/sigma) through a uniform pointer (scalar loads)
-  const int lo0 = __builtin_amdgcn_readfirstlane(lo);
-  if (__builtin_amdgcn_ballot_w64(lo != lo0) == 0)
-    project_slice<TIn, KB>(T, ldt, j0, j1, tt, coef + (int64_t)lo0 * d * 2, S, d, k, acc);
-  else
-    project_slice<TIn, KB>(T, ldt, j0, j1, tt, coef + (int64_t)lo * d * 2, S, d, k, acc);
-  if (SL > 1) {
-    if (sl > 0) {
-#pragma unroll
-      for (int g = 0; g < KB; ++g) part[((sl - 1) * KB + g) * 64 + lane] = acc[g];
+    for (int v = 0; v < V; ++v) {
+      const double x = (double)T[(int64_t)j * ldt + cc[v]];
+      xb[v] = ok[v] ? (x - cp[v][2 * j]) * cp[v][2 * j + 1] : 0.0;
     }
-    __syncthreads();
-    if (sl > 0) return;
+#pragma unroll
+    for (int g = 0; g < KB; ++g) {
+      const double c = sr[g];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[g][v] = fma(c, xb[v], acc[g][v]);
+    }
+  }
+}
+
+template <typename TIn, int KB, int V>
+__global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T, int64_t ldt, int64_t d, int64_t N,
+                                                      const int64_t* __restrict__ offsets, int n_series,
+                                                      const double* __restrict__ coef, const double* __restrict__ St,
+                                                      int k, double* __restrict__ R, int64_t ldr, int mode,
+                                                      int64_t tiles_per_block) {
+  extern __shared__ double part[];  // (SL - 1) x KB x V x 64
+  constexpr int TW = 64 * V;
+  const int lane = threadIdx.x & 63;
+  const int SL = blockDim.x >> 6;
+  const int sl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's slice of the dimensions
+  const int j0 = (int)(d * sl / SL), j1 = (int)(d * (sl + 1) / SL);
+  const int64_t n_tiles = (N + TW - 1) / TW;
+  const int64_t tile0 = (int64_t)blockIdx.x * tiles_per_block;
+  const int64_t tile1 = min(tile0 + tiles_per_block, n_tiles);
+  int s = 0;
+  int64_t s_end = -1;  // first column after series s (uniform)
+  for (int64_t tile = tile0; tile < tile1; ++tile) {
+    const int64_t c0 = tile * TW;
+    if (c0 >= s_end) {
+      s = series_of(offsets, n_series, c0, lane);
+      s_end = offsets[s + 1];
+    }
+    const int64_t t = c0 + (int64_t)lane * V;
+    double acc[KB][V];
 #pragma unroll
     for (int g = 0; g < KB; ++g)
-      for (int q = 0; q < SL - 1; ++q) acc[g] += part[(q * KB + g) * 64 + lane];
-  }
-  if (!valid) return;
 #pragma unroll
-  for (int g = 0; g < KB; ++g) {
-    if (g < k) {
-      double* dst = R + (int64_t)g * ldr + t;
-      if (mode == 0) *dst = acc[g];
-      else if (mode > 0) *dst += acc[g];
-      else *dst -= acc[g];
+      for (int v = 0; v < V; ++v) acc[g][v] = 0.0;
+    if (c0 + TW <= s_end)  // a full tile inside series s (s_end <= N)
+      rows_uniform<TIn, KB, V>(T, ldt, j0, j1, t, coef + (int64_t)s * d * 2, St, acc);
+    else
+      rows_general<TIn, KB, V>(T, ldt, d, j0, j1, t, N, offsets, n_series, coef, St, acc);
+    if (SL > 1) {
+      if (sl > 0) {
+#pragma unroll
+        for (int g = 0; g < KB; ++g)
+#pragma unroll
+          for (int v = 0; v < V; ++v) part[(((sl - 1) * KB + g) * V + v) * 64 + lane] = acc[g][v];
+      }
+      __syncthreads();
+      if (sl == 0) {
+        for (int q = 0; q < SL - 1; ++q)
+#pragma unroll
+          for (int g = 0; g < KB; ++g)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[g][v] += part[((q * KB + g) * V + v) * 64 + lane];
+      }
+      __syncthreads();  // part is rewritten by the next tile
+    }
+    if (sl == 0) {
+#pragma unroll
+      for (int g = 0; g < KB; ++g) {
+        if (g < k) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            if (t + v < N) {
+              double* dst = R + (int64_t)g * ldr + t + v;
+              if (mode == 0) *dst = acc[g][v];
+              else if (mode > 0) *dst += acc[g][v];
+              else *dst -= acc[g][v];
+            }
+          }
+        }
+      }
     }
   }
 }
@@ -285,54 +414,140 @@ __global__ void prep_coef(const double* __restrict__ stats, int64_t pairs, doubl
   coef[2 * i + 1] = sd > 0.0 ? 1.0 / sd : 0.0;
 }
 
-// coef: workspace of n_series * d * 2 doubles
+// Sketch rows padded to the kernel's group count: 1, 4, 8, 16, 32 or 64.
+static int proj_kb(int k) { return k <= 1 ? 1 : k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64; }
+
+// S [k][d] (row-major) -> St [d][KB], zero for g >= k.
+static std::vector<double> transpose_coeffs(const std::vector<double>& S, int k, int64_t d) {
+  const int kb = proj_kb(k);
+  std::vector<double> St((size_t)d * kb, 0.0);
+  for (int g = 0; g < k; ++g)
+    for (int64_t j = 0; j < d; ++j) St[(size_t)j * kb + g] = S[(size_t)g * d + j];
+  return St;
+}
+
+// Columns per lane: 16-byte loads while the lane's accumulators (KB x V
+// doubles) stay within 32 doubles; 1 when T's rows are not aligned for them.
 template <typename TIn>
-static void launch_project(const void* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
-                           const double* stats, double* coef, const double* S, int k, double* R, int64_t ldr,
+static int proj_vec(int kb, const void* T, int64_t ldt) {
+  int v = sizeof(TIn) == 8 ? (kb <= 16 ? 2 : 1) : (kb <= 8 ? 4 : kb <= 16 ? 2 : 1);
+  while (v > 1 && ((reinterpret_cast<uintptr_t>(T) % (v * sizeof(TIn))) != 0 || ldt % v != 0)) v /= 2;
+  return v;
+}
+
+template <typename TIn, int KB, int V>
+static void launch_project_v(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
+                             const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
+                             hipStream_t st) {
+  constexpr int TW = 64 * V;
+  const int64_t n_tiles = (N + TW - 1) / TW;
+  // slices of the dimensions while the tiles alone leave the chip under-filled
+  // (4096 waves), each slice at least PROJ_PF rows, partial sums within the LDS budget
+  int SL = 1;
+  while (SL < 4 && n_tiles * SL < 4096 && d >= 2 * SL * PROJ_PF &&
+         (size_t)(2 * SL - 1) * KB * V * 64 * sizeof(double) <= PROJ_LDS_BYTES)
+    SL *= 2;
+  // at most two blocks per resident slot (8192 waves); more tiles go to each block
+  const int64_t max_blocks = std::max<int64_t>(1, 16384 / SL);
+  const int64_t tpb = (n_tiles + max_blocks - 1) / max_blocks;
+  const int64_t blocks = (n_tiles + tpb - 1) / tpb;
+  const size_t lds = (size_t)(SL - 1) * KB * V * 64 * sizeof(double);
+  hipLaunchKernelGGL((project_kernel<TIn, KB, V>), dim3((unsigned)blocks), dim3(64 * SL), lds, st, T, ldt, d, N,
+                     offsets, n_series, coef, St, k, R, ldr, mode, tpb);
+}
+
+template <typename TIn, int KB>
+static void launch_project_kb(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
+                              const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
+                              hipStream_t st) {
+  const int v = proj_vec<TIn>(KB, T, ldt);
+  constexpr int VMAX = sizeof(TIn) == 8 ? (KB <= 16 ? 2 : 1) : (KB <= 8 ? 4 : KB <= 16 ? 2 : 1);
+  if constexpr (VMAX >= 4) {
+    if (v == 4) return launch_project_v<TIn, KB, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+  }
+  if constexpr (VMAX >= 2) {
+    if (v == 2) return launch_project_v<TIn, KB, 2>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+  }
+  launch_project_v<TIn, KB, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+}
+
+// coef: workspace of n_series * d * 2 doubles; St: transpose_coeffs(S) on the device
+template <typename TIn>
+static void launch_project(const void* Tv, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
+                           const double* stats, double* coef, const double* St, int k, double* R, int64_t ldr,
                            int mode, hipStream_t st) {
   const int64_t pairs = (int64_t)n_series * d;
   hipLaunchKernelGGL(prep_coef, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, stats, pairs, coef);
-  const dim3 grid((unsigned)((N + 63) / 64));
-  const TIn* Tp = static_cast<const TIn*>(T);
-#define SKMP_PROJ(KB, SL)                                                                                     \
-  hipLaunchKernelGGL((project_kernel<TIn, KB, SL>), grid, dim3(64 * SL), 0, st, Tp, ldt, d, N, offsets, n_series, \
-                     coef, S, k, R, ldr, mode)
-  if (k <= 1) SKMP_PROJ(1, 4);
-  else if (k <= 4) SKMP_PROJ(4, 4);
-  else if (k <= 8) SKMP_PROJ(8, 4);
-  else if (k <= 16) SKMP_PROJ(16, 4);
-  else if (k <= 32) SKMP_PROJ(32, 2);
-  else SKMP_PROJ(64, 2);
-#undef SKMP_PROJ
+  const TIn* T = static_cast<const TIn*>(Tv);
+  switch (proj_kb(k)) {
+    case 1: return launch_project_kb<TIn, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    case 4: return launch_project_kb<TIn, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    case 8: return launch_project_kb<TIn, 8>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    case 16: return launch_project_kb<TIn, 16>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    case 32: return launch_project_kb<TIn, 32>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    default: return launch_project_kb<TIn, 64>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+  }
 }
 
 // Per-dimension statistics of the columns [offsets[s], offsets[s+1]) of every series.
 struct StatsBuffers {
-  int64_t* offsets_dev;
-  int64_t* cprefix_dev;
+  int64_t* offsets_dev;  // n_series + 1 (a table of the call's blob)
+  int64_t* cprefix_dev;  // n_series + 1 (a table of the call's blob)
   StatPartial* part;
   unsigned int* nonfinite;
 };
 
-static size_t stats_workspace(int64_t d, int64_t n_series, int64_t total_chunks, Carve& cv, StatsBuffers* out) {
-  StatsBuffers b;
-  b.offsets_dev = cv.take<int64_t>(n_series + 1);
-  b.cprefix_dev = cv.take<int64_t>(n_series + 1);
-  b.part = cv.take<StatPartial>((size_t)d * (size_t)total_chunks);
-  b.nonfinite = cv.take<unsigned int>(64);
-  if (out) *out = b;
+// The small host tables of one call (series offsets, chunk prefix, sketch
+// coefficients) sit next to each other in the workspace and go to the device
+// with one copy.  With a null workspace base it only sizes the region.
+class TableBlob {
+ public:
+  explicit TableBlob(Carve& cv) : cv_(cv), begin_(cv.used) {}
+  template <typename T>
+  T* put(const T* src, size_t count) {
+    const size_t off = (cv_.used + 255) & ~size_t(255);
+    T* dst = cv_.take<T>(count);
+    parts_.push_back({off, src, count * sizeof(T)});
+    return dst;
+  }
+  int upload(hipStream_t st) const {
+    const size_t end = parts_.empty() ? begin_ : parts_.back().off + parts_.back().bytes;
+    std::vector<unsigned char> host(end - begin_, 0);
+    for (const Part& p : parts_)
+      if (p.bytes) std::memcpy(host.data() + (p.off - begin_), p.src, p.bytes);
+    return host.empty() ? SKMP_OK : upload_async(cv_.base + begin_, host.data(), host.size(), st);
+  }
+
+ private:
+  struct Part {
+    size_t off;
+    const void* src;
+    size_t bytes;
+  };
+  Carve& cv_;
+  size_t begin_;
+  std::vector<Part> parts_;
+};
+
+static size_t stats_workspace(int64_t d, int64_t total_chunks, Carve& cv, StatsBuffers* out) {
+  StatPartial* part = cv.take<StatPartial>((size_t)d * (size_t)total_chunks);
+  unsigned int* nonfinite = cv.take<unsigned int>(64);
+  if (out) {
+    out->part = part;
+    out->nonfinite = nonfinite;
+  }
   return cv.used;
 }
 
+// Enqueues the statistics pass; the offsets and chunk-prefix tables of b must
+// already be on their way (the call's table blob).
 static int run_dimstats(const void* T, int32_t dtype, int64_t ldt, int64_t d, int64_t n_series,
-                        const int64_t* offsets_host, const std::vector<int64_t>& cpre, const StatsBuffers& b,
-                        double* stats_out, bool check, hipStream_t st) {
+                        const std::vector<int64_t>& cpre, const StatsBuffers& b, double* stats_out, bool check,
+                        hipStream_t st) {
   if (check && stream_capturing(st)) {
     set_error("the non-finite input check reads its result back on the host and cannot run under graph capture");
     return SKMP_EINVAL;
   }
-  if (int rc = upload_async(b.offsets_dev, offsets_host, sizeof(int64_t) * (n_series + 1), st)) return rc;
-  if (int rc = upload_async(b.cprefix_dev, cpre.data(), sizeof(int64_t) * (n_series + 1), st)) return rc;
   if (check) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, st, b.nonfinite, 0u, (int64_t)1);
   const int64_t total_chunks = cpre[n_series];
   dim3 grid((unsigned)(d * total_chunks)), block(STAT_THREADS);
@@ -384,9 +599,12 @@ extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int6
   if (d < 1 || n_series < 1 || !offsets || k < 1) return 0;
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
   Carve cv(nullptr, 0);
-  cv.take<double>((size_t)k * (size_t)d);
+  TableBlob tb(cv);
+  tb.put<int64_t>(nullptr, n_series + 1);
+  tb.put<int64_t>(nullptr, n_series + 1);
+  tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)d);
   cv.take<double>((size_t)n_series * (size_t)d * 2);
-  stats_workspace(d, n_series, cpre[n_series], cv, nullptr);
+  stats_workspace(d, cpre[n_series], cv, nullptr);
   return cv.used + 256;
 }
 
@@ -410,18 +628,22 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   if (rc) return rc;
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
   Carve cv(workspace, ws_bytes);
-  double* S_dev = cv.take<double>((size_t)k * (size_t)d);
-  double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
+  TableBlob tb(cv);
   StatsBuffers sb;
-  stats_workspace(d, n_series, cpre[n_series], cv, &sb);
+  sb.offsets_dev = tb.put(offsets, n_series + 1);
+  sb.cprefix_dev = tb.put(cpre.data(), n_series + 1);
+  const std::vector<double> St = transpose_coeffs(S, k, d);
+  double* S_dev = tb.put(St.data(), St.size());
+  double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
+  stats_workspace(d, cpre[n_series], cv, &sb);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
     return SKMP_ENOMEM;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (int rc2 = upload_async(S_dev, S.data(), sizeof(double) * S.size(), st)) return rc2;
+  if (int rc2 = tb.upload(st)) return rc2;
   StageTimer tm(SKMP_TIMER_SKETCH, st);
-  rc = run_dimstats(T, dtype, ldt, d, n_series, offsets, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
+  rc = run_dimstats(T, dtype, ldt, d, n_series, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
   if (dtype == SKMP_F64)
     launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, st);
@@ -436,10 +658,13 @@ extern "C" size_t sketch_update_workspace(int64_t n, int64_t d_add, int64_t d_re
   int64_t offs[2] = {0, n};
   std::vector<int64_t> cpre = chunk_prefix(1, offs);
   Carve cv(nullptr, 0);
-  cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_add, 1));
-  cv.take<double>((size_t)k * (size_t)std::max<int64_t>(d_rem, 1));
+  TableBlob tb(cv);
+  tb.put<int64_t>(nullptr, 2);
+  tb.put<int64_t>(nullptr, 2);
+  tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)std::max<int64_t>(d_add, 1));
+  tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)std::max<int64_t>(d_rem, 1));
   cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
-  stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, nullptr);
+  stats_workspace(std::max<int64_t>(d_add, 1), cpre[1], cv, nullptr);
   return cv.used + 256;
 }
 
@@ -481,20 +706,25 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
   int64_t offs[2] = {0, n};
   std::vector<int64_t> cpre = chunk_prefix(1, offs);
   Carve cv(workspace, ws_bytes);
-  double* Sa_dev = cv.take<double>(Sa.size());
-  double* Sr_dev = cv.take<double>(Sr.size());
-  double* coef = cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
+  TableBlob tb(cv);
   StatsBuffers sb;
-  stats_workspace(std::max<int64_t>(d_add, 1), 1, cpre[1], cv, &sb);
+  sb.offsets_dev = tb.put(offs, 2);
+  sb.cprefix_dev = tb.put(cpre.data(), 2);
+  const std::vector<double> Sat = transpose_coeffs(Sa, k, std::max<int64_t>(d_add, 1));
+  const std::vector<double> Srt = transpose_coeffs(Sr, k, std::max<int64_t>(d_rem, 1));
+  double* Sa_dev = tb.put(Sat.data(), Sat.size());
+  double* Sr_dev = tb.put(Srt.data(), Srt.size());
+  double* coef = cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
+  stats_workspace(std::max<int64_t>(d_add, 1), cpre[1], cv, &sb);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
     return SKMP_ENOMEM;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc2 = tb.upload(st)) return rc2;
   uint64_t mask = 0;
   if (d_add) {
-    if (int rc2 = upload_async(Sa_dev, Sa.data(), sizeof(double) * Sa.size(), st)) return rc2;
-    rc = run_dimstats(T_add, dtype, ldt, d_add, 1, offs, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
+    rc = run_dimstats(T_add, dtype, ldt, d_add, 1, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
     if (rc) return rc;
     if (dtype == SKMP_F64)
       launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1, st);
@@ -505,9 +735,6 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
         if (Sa[(size_t)g * d_add + j] != 0.0) mask |= 1ull << g;
   }
   if (d_rem) {
-    if (int rc2 = upload_async(Sr_dev, Sr.data(), sizeof(double) * Sr.size(), st)) return rc2;
-    if (!d_add)
-      if (int rc2 = upload_async(sb.offsets_dev, offs, sizeof(offs), st)) return rc2;
     if (dtype == SKMP_F64)
       launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1, st);
     else

@@ -75,6 +75,69 @@ def test_sketch_build_parity(dev, case):
         assert np.allclose(stats[s, :, 1], sd_o, rtol=1e-12, atol=0)
 
 
+# (input dtype, k, series lengths, d, leading columns of the view): the projection's
+# column groups per lane (4 / 2 / 1), tiles across series boundaries and past the
+# end, dimension slices, and the padded group counts 1, 4, 8, 16, 32, 64
+PROJ_CASES = [
+    ("f32", 5, [1, 3, 130, 257, 7], 9, 0),    # short series inside one tile, N % 4 = 2
+    ("f32", 4, [300] * 20, 12, 0),             # 4 columns per lane, boundaries inside tiles
+    ("f32", 16, [2049, 4096], 33, 0),          # odd N: 1 column per lane
+    ("f32", 3, [4000], 20, 1),                 # view off by one column: unaligned rows
+    ("f64", 8, [5001, 64], 51, 0),             # slices of the dimensions, ragged tail
+    ("f64", 17, [1000, 23], 40, 0),            # 32 padded groups
+    ("f64", 33, [515], 70, 0),                 # 64 padded groups
+    ("f64", 1, [3000], 5, 1),                  # k = 1, unaligned rows
+]
+
+
+@pytest.mark.parametrize("case", PROJ_CASES)
+def test_sketch_projection_layouts(dev, case):
+    import torch
+    import paper_2311_03393_amd as skmp
+    dt, k, lens, d, lead = case
+    _say("projection layout", case)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    N = int(offsets[-1])
+    T = np.concatenate([datagen.tiny_series(70 + q, d, L) for q, L in enumerate(lens)], axis=1)
+    if dt == "f32":
+        T = T.astype(np.float32)
+    wide = np.zeros((d, N + lead), dtype=T.dtype)
+    wide[:, lead:] = T
+    Tw = _to_dev(torch, wide, dev)[:, lead:]
+    R, stats = skmp.sketch_build(Tw, offsets, k, "gauss", 19)
+    torch.cuda.synchronize()
+    R, stats = R.cpu().numpy(), stats.cpu().numpy()
+    for s in range(len(lens)):
+        a, b = offsets[s], offsets[s + 1]
+        R_o, _, mu_o, sd_o = O.build(T[:, a:b].astype(np.float64), "gauss", k, 19)
+        scale = max(1.0, float(np.max(np.abs(R_o))))
+        assert np.max(np.abs(R[:, a:b] - R_o)) <= 1e-12 * scale, (case, s)
+        assert np.allclose(stats[s, :, 1], sd_o, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n", [4096, 4097])
+def test_update_dims_fp32_input(dev, n):
+    """Add and remove with FP32 input: 4 columns per lane (n = 4096) and 1 (odd n)."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, k = 24, 6
+    T = datagen.tiny_series(81, d, n).astype(np.float32)
+    T_add = datagen.tiny_series(82, 3, n).astype(np.float32)
+    ids = np.arange(d)
+    rem = np.array([2, 5, 11, 20])
+    R, stats = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, "gauss", 23, dim_ids=ids)
+    Td = _to_dev(torch, T, dev)
+    rem_idx = torch.from_numpy(rem).to(dev)
+    skmp.sketch_update_dims(R, "gauss", k, 23, T_add=_to_dev(torch, T_add, dev), add_ids=[30, 31, 32],
+                            T_rem=Td[rem_idx].contiguous(), rem_ids=rem,
+                            rem_stats=stats[0].index_select(0, rem_idx).contiguous())
+    torch.cuda.synchronize()
+    keep = np.setdiff1d(ids, rem)
+    R_ref, _, _, _ = O.build(np.concatenate([T[keep], T_add]).astype(np.float64), "gauss", k, 23,
+                             np.concatenate([keep, [30, 31, 32]]))
+    assert np.max(np.abs(R.cpu().numpy() - R_ref)) <= 1e-11 * np.max(np.abs(R_ref))
+
+
 def test_sketch_constant_dimension_and_nonfinite(dev):
     import torch
     import paper_2311_03393_amd as skmp
