@@ -35,6 +35,12 @@ class _COracle:
         lib.oracle_pair_dist.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ip, ip, ctypes.c_int64, dp]
         lib.oracle_pair_dist.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_ab_rows.argtypes = [dp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_int, ip, ctypes.c_int64, dp,
+                                       ip]
+        lib.oracle_ab_rows.restype = ctypes.c_int
+        lib.oracle_ab_pair_dist.argtypes = [dp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_int, ip, ip,
+                                            ctypes.c_int64, dp]
+        lib.oracle_ab_pair_dist.restype = ctypes.c_int
 
     @staticmethod
     def _d(a):
@@ -71,6 +77,36 @@ class _COracle:
         rc = self.lib.oracle_pair_dist(self._d(r), r.size, m, self._i(pi), self._i(pj), pi.size, self._d(out))
         if rc != 0:
             raise RuntimeError("oracle_pair_dist failed")
+        return out
+
+
+    def ab_profile(self, ra, rb, m: int, rows=None):
+        """AB-join: nearest subsequence of rb for every (listed) subsequence of ra."""
+        ra = np.ascontiguousarray(ra, dtype=np.float64)
+        rb = np.ascontiguousarray(rb, dtype=np.float64)
+        if rows is None:
+            cnt, rp = ra.size - m + 1, None
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            cnt, rp = rows.size, self._i(rows)
+        P = np.empty(cnt)
+        I = np.empty(cnt, np.int64)
+        rc = self.lib.oracle_ab_rows(self._d(ra), ra.size, self._d(rb), rb.size, m, rp, 0 if rows is None else cnt,
+                                     self._d(P), self._i(I))
+        if rc != 0:
+            raise RuntimeError(f"oracle_ab_rows failed ({rc})")
+        return P, I
+
+    def ab_pair_dist(self, ra, rb, m: int, pi, pj):
+        ra = np.ascontiguousarray(ra, dtype=np.float64)
+        rb = np.ascontiguousarray(rb, dtype=np.float64)
+        pi = np.ascontiguousarray(pi, dtype=np.int64)
+        pj = np.ascontiguousarray(pj, dtype=np.int64)
+        out = np.empty(pi.size)
+        rc = self.lib.oracle_ab_pair_dist(self._d(ra), ra.size, self._d(rb), rb.size, m, self._i(pi), self._i(pj),
+                                          pi.size, self._d(out))
+        if rc != 0:
+            raise RuntimeError("oracle_ab_pair_dist failed")
         return out
 
 

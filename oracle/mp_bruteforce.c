@@ -18,6 +18,11 @@
  *   - (i, j) is a trivial match iff |i - j| < excl;
  *   - nearest-neighbour ties go to the smallest j; no admissible j gives
  *     P = +inf, I = -1.
+ * The AB-join (oracle_ab_rows) is Def. 6 with two different series, as in
+ * the train/test procedure of Section III-B (Alg. 2's AB-join): for every
+ * subsequence of a, the nearest subsequence of b.  There is no trivial-match
+ * zone between different series; flatness is judged in each series against
+ * its own max|r|.
  * Distances are evaluated from explicit differences of the normalised
  * vectors, never through a correlation, so there is no cancellation.
  * Parallelism: OpenMP over rows (each row is independent).
@@ -176,6 +181,123 @@ int oracle_pair_dist(const double* r, int64_t n, int m, const int64_t* pi, const
             double acc = 0.0;
             for (int t = 0; t < m; ++t) {
                 double e = (r[a + t] - mu[0]) / sd[0] - (r[b + t] - mu[1]) / sd[1];
+                acc += e * e;
+            }
+            out[q] = sqrt(acc);
+        }
+    }
+    return 0;
+}
+
+/* AB-join rows: for each listed subsequence i of a (all when rows == NULL),
+ * the nearest subsequence of b.  Returns 0, or -1 / -2 on bad arguments / no memory. */
+int oracle_ab_rows(const double* a, int64_t na, const double* b, int64_t nb, int m, const int64_t* rows,
+                   int64_t nrows, double* P, int64_t* I) {
+    if (m < 2 || na < m || nb < m) return -1;
+    int64_t na_sub = na - m + 1, nb_sub = nb - m + 1;
+    double* Za = (double*)malloc(sizeof(double) * (size_t)na_sub * (size_t)m);
+    double* Zb = (double*)malloc(sizeof(double) * (size_t)nb_sub * (size_t)m);
+    unsigned char* fa = (unsigned char*)malloc((size_t)na_sub);
+    unsigned char* fb = (unsigned char*)malloc((size_t)nb_sub);
+    if (!Za || !Zb || !fa || !fb) {
+        free(Za);
+        free(Zb);
+        free(fa);
+        free(fb);
+        return -2;
+    }
+    normalise_windows(a, na, m, Za, fa);
+    normalise_windows(b, nb, m, Zb, fb);
+    double sqrt_m = sqrt((double)m);
+    int64_t count = rows ? nrows : na_sub;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < count; ++q) {
+        int64_t i = rows ? rows[q] : q;
+        if (i < 0 || i >= na_sub) {
+            P[q] = NAN;
+            I[q] = -2;
+            continue;
+        }
+        const double* zi = Za + i * (int64_t)m;
+        double best = INFINITY;
+        int64_t arg = -1;
+        for (int64_t j = 0; j < nb_sub; ++j) {
+            double d;
+            if (fa[i] && fb[j]) {
+                d = 0.0;
+            } else if (fa[i] || fb[j]) {
+                d = sqrt_m;
+            } else {
+                const double* zj = Zb + j * (int64_t)m;
+                double acc = 0.0;
+                for (int t = 0; t < m; ++t) {
+                    double e = zi[t] - zj[t];
+                    acc += e * e;
+                }
+                d = sqrt(acc);
+            }
+            if (d < best) {  /* strict: the smallest j keeps a tie */
+                best = d;
+                arg = j;
+            }
+        }
+        P[q] = best;
+        I[q] = arg;
+    }
+    free(Za);
+    free(Zb);
+    free(fa);
+    free(fb);
+    return 0;
+}
+
+static void window_moments(const double* r, int64_t w, int m, double* mu, double* sd) {
+    double acc = 0.0;
+    for (int t = 0; t < m; ++t) acc += r[w + t];
+    *mu = acc / m;
+    double v = 0.0;
+    for (int t = 0; t < m; ++t) {
+        double e = r[w + t] - *mu;
+        v += e * e;
+    }
+    *sd = sqrt(v / m);
+}
+
+static double max_abs(const double* r, int64_t n) {
+    double s = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+        double x = fabs(r[t]);
+        if (x > s) s = x;
+    }
+    return s;
+}
+
+/* Exact distance of explicit pairs (subsequence pi[q] of a, subsequence pj[q] of b). */
+int oracle_ab_pair_dist(const double* a, int64_t na, const double* b, int64_t nb, int m, const int64_t* pi,
+                        const int64_t* pj, int64_t npairs, double* out) {
+    if (m < 2 || na < m || nb < m) return -1;
+    int64_t na_sub = na - m + 1, nb_sub = nb - m + 1;
+    double sa = max_abs(a, na), sb = max_abs(b, nb);
+    double sqrt_m = sqrt((double)m);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < npairs; ++q) {
+        int64_t i = pi[q], j = pj[q];
+        if (i < 0 || j < 0 || i >= na_sub || j >= nb_sub) {
+            out[q] = NAN;
+            continue;
+        }
+        double mu_a, sd_a, mu_b, sd_b;
+        window_moments(a, i, m, &mu_a, &sd_a);
+        window_moments(b, j, m, &mu_b, &sd_b);
+        int f1 = sd_a <= FLAT_REL * sa, f2 = sd_b <= FLAT_REL * sb;
+        if (f1 && f2) {
+            out[q] = 0.0;
+        } else if (f1 || f2) {
+            out[q] = sqrt_m;
+        } else {
+            double acc = 0.0;
+            for (int t = 0; t < m; ++t) {
+                double e = (a[i + t] - mu_a) / sd_a - (b[j + t] - mu_b) / sd_b;
                 acc += e * e;
             }
             out[q] = sqrt(acc);

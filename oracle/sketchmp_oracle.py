@@ -281,6 +281,31 @@ def matrix_profile(r: np.ndarray, m: int, excl: int, rows=None) -> Tuple[np.ndar
     return P, I
 
 
+def ab_join(ra: np.ndarray, rb: np.ndarray, m: int, rows=None) -> Tuple[np.ndarray, np.ndarray]:
+    """AB-join profile by brute force: for every subsequence of ``ra`` the
+    distance to, and index of, its nearest subsequence of ``rb``.
+
+    Def. 6 with distinct test (ra) and train (rb) series, the AB-join of
+    Section III-B / Alg. 2.  The series differ, so there is no trivial-match
+    zone; each series' flat subsequences are judged against its own max|r|.
+    """
+    Za, fa = znorm_windows(ra, m)
+    Zb, fb = znorm_windows(rb, m)
+    na_sub = Za.shape[0]
+    P = np.full(na_sub, np.nan)
+    I = np.full(na_sub, -2, dtype=np.int64)
+    for i in (range(na_sub) if rows is None else rows):
+        i = int(i)
+        if fa[i]:
+            dd = np.where(fb, 0.0, math.sqrt(m))
+        else:
+            dd = np.sqrt(np.sum((Zb - Za[i]) ** 2, axis=1))
+            dd = np.where(fb, math.sqrt(m), dd)
+        jj = int(np.argmin(dd))          # first (smallest j) minimum
+        P[i], I[i] = float(dd[jj]), jj
+    return P, I
+
+
 # ------------------------------------------------------------------ discords
 def time_detection(P_groups: np.ndarray) -> Tuple[int, int, float]:
     """Algorithm 2 on precomputed per-group profiles: returns (i*, g*, score).

@@ -255,6 +255,60 @@ def test_row_without_partner_is_infinite(c_oracle):
     assert all(np.isfinite(s) for _, _, s in O.top_discords(P[None], m, 5))
 
 
+# ------------------------------------------------------------------ AB-join
+def _scipy_ab(ra, rb, m):
+    """Row minima of the full cross-distance matrix, explicit windows through scipy."""
+    def z(r):
+        W = np.lib.stride_tricks.sliding_window_view(r, m)
+        mu = W.mean(axis=1, keepdims=True)
+        sd = W.std(axis=1, keepdims=True)
+        flat = (sd[:, 0] <= 1e-10 * np.max(np.abs(r)))
+        Z = np.where(flat[:, None], 0.0, (W - mu) / np.where(sd > 0, sd, 1.0))
+        return Z, flat
+    Za, fa = z(ra)
+    Zb, fb = z(rb)
+    D = cdist(Za, Zb)
+    D[fa[:, None] ^ fb[None, :]] = math.sqrt(m)   # flat vs non-flat
+    D[fa[:, None] & fb[None, :]] = 0.0
+    return D
+
+
+@pytest.mark.parametrize("na,nb,m", [(150, 300, 8), (400, 90, 16), (257, 257, 32), (40, 45, 5)])
+def test_ab_join_matches_scipy_cdist(na, nb, m, c_oracle):
+    ra = datagen.tiny_series(na + 7, 1, na)[0]
+    rb = datagen.tiny_series(nb + 11, 1, nb)[0]
+    rb[20:20 + 2 * m] = 1.5      # flat windows in b
+    ra[10:10 + m + 3] = -2.0      # and in a
+    D = _scipy_ab(ra, rb, m)
+    P, I = O.ab_join(ra, rb, m)
+    assert np.max(np.abs(P - D.min(axis=1))) < 1e-9
+    assert np.array_equal(I, D.argmin(axis=1))
+    Pc, Ic = c_oracle.ab_profile(ra, rb, m)
+    assert np.max(np.abs(Pc - P)) < 1e-12 and np.array_equal(Ic, I)
+    # the other direction is the column minima of the same matrix
+    Pb, Ib = c_oracle.ab_profile(rb, ra, m)
+    assert np.max(np.abs(Pb - D.min(axis=0))) < 1e-9 and np.array_equal(Ib, D.argmin(axis=0))
+    assert np.all((P >= 0) & (P <= 2 * math.sqrt(m) + 1e-12))
+
+
+def test_ab_join_planted_copy_and_self(c_oracle):
+    rng = np.random.default_rng(12)
+    m = 12
+    ra = rng.standard_normal(200).cumsum()
+    rb = rng.standard_normal(300).cumsum()
+    rb[137:137 + m] = 2.5 * ra[40:40 + m] - 7.0       # an affine copy of a's window 40 inside b
+    P, I = c_oracle.ab_profile(ra, rb, m)
+    assert P[40] < 1e-6 and I[40] == 137
+    Pb, Ib = c_oracle.ab_profile(rb, ra, m)
+    assert Pb[137] < 1e-6 and Ib[137] == 40
+    # a series joined with itself: every window is its own nearest neighbour (no exclusion zone)
+    Ps, Is = c_oracle.ab_profile(ra, ra, m)
+    assert np.max(Ps) < 1e-6 and np.array_equal(Is, np.arange(ra.size - m + 1))
+    # reported distances are the exact pair distances
+    d = c_oracle.ab_pair_dist(ra, rb, m, np.arange(ra.size - m + 1), I)
+    assert np.max(np.abs(d - P)) < 1e-12
+
+
 # ---------------------------------------------------------------- discords
 def test_time_detection_strict_greater_keeps_first_group():
     P = np.array([[0.1, 0.9, 0.2],
