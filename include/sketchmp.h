@@ -196,6 +196,37 @@ int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_series, const i
                          void* workspace, size_t ws_bytes, void* stream, int32_t reps, int32_t* variant,
                          int32_t* strip, double* best_ms);
 
+/* Workspace bytes needed by mp_abjoin (0 for an unsupported precision). */
+size_t mp_abjoin_workspace(int64_t na, int64_t nb, int32_t k, int32_t m, int32_t prec);
+
+/*
+ * AB-join matrix profile (Def. 6 with distinct test and train series: the
+ * join Algorithm 2 runs between a new series and a reference one, Section
+ * III-B): for every subsequence of the sketched series A, the distance to its
+ * nearest subsequence of the sketched series B, and optionally the converse.
+ * The two series are different, so there is no trivial-match zone.  Both
+ * directions come from one pass over the na' x nb' cross-distance matrix
+ * (na' = na - m + 1, nb' = nb - m + 1): the diagonals j - i >= 0 walked along
+ * A's rows, the diagonals i - j >= 1 along B's rows, each cell met once.
+ *   RA, RB   device, k x na / k x nb doubles, row strides lda >= na, ldb >= nb
+ *            (sketch_build outputs of the two series, same kind, k and seed).
+ *   m        subsequence length, 4 <= m <= 2048; na, nb >= m.
+ *   prec     SKMP_FP64 | SKMP_FP32 (FP32 recurrence with exact FP64 seeds every
+ *            `refresh` rows, as in mp_selfjoin); others give SKMP_EINVAL.
+ *   group_mask bit g selects group g (~0 = all); unselected rows are untouched.
+ *   PA, IA   device out, k x na' (row stride ldpa >= na): distance from
+ *            subsequence i of A to its nearest subsequence of B and that
+ *            subsequence's index in B (ties to the smallest index).
+ *   PB, IB   device out or both NULL, k x nb' (row stride ldpb >= nb): the same
+ *            from B to A.
+ * Flat subsequences are judged in each series against its own max|R^(g)|;
+ * distances follow mp_selfjoin (FP64 polish of the reported neighbour).
+ * Asynchronous on `stream`; the workspace comes from mp_abjoin_workspace.
+ */
+int mp_abjoin(const double* RA, int64_t lda, int64_t na, const double* RB, int64_t ldb, int64_t nb, int32_t k,
+              int32_t m, int32_t prec, int32_t refresh, uint64_t group_mask, double* PA, int64_t* IA, int64_t ldpa,
+              double* PB, int64_t* IB, int64_t ldpb, void* workspace, size_t ws_bytes, void* stream);
+
 /*
  * The process's tuning table as text, one line per shape class:
  * "prec mlog nlog variant strip ms".  skmp_tuning_export writes at most len

@@ -36,7 +36,8 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 # every symbol include/sketchmp.h declares
 EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
-            "mp_selfjoin_autotune", "skmp_tuning_export", "skmp_tuning_import", "skmp_tuning_clear",
+            "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "skmp_tuning_export",
+            "skmp_tuning_import", "skmp_tuning_clear",
             "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4}
 
@@ -77,6 +78,10 @@ def lib():
         L.mp_selfjoin_workspace.restype = _sz
         L.mp_selfjoin.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _i64, _vp,
                                   _sz, _vp]
+        L.mp_abjoin_workspace.argtypes = [_i64, _i64, _i32, _i32, _i32]
+        L.mp_abjoin_workspace.restype = _sz
+        L.mp_abjoin.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _i64, _vp,
+                                _vp, _i64, _vp, _sz, _vp]
         L.top_discords_workspace.argtypes = [_i64, _i64p, _i32, _i32]
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
@@ -235,6 +240,29 @@ def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refre
                              refresh, mask, P.data_ptr(), I.data_ptr(), _ld(P), workspace.data_ptr(),
                              workspace.numel(), _stream(torch)))
     return P, I
+
+
+def mp_abjoin(RA, RB, k: int, m: int, prec: str = "fp64", refresh: int = 0, group_mask: Optional[int] = None,
+              both: bool = False, workspace=None):
+    """AB-join: nearest subsequence of RB for every subsequence of RA (and, with
+    both=True, the converse).  Returns (PA, IA) or (PA, IA, PB, IB); PA/IA are
+    k x na with the last m - 1 columns unused, IA indexes windows of RB."""
+    torch = _torch()
+    na, nb = int(RA.shape[1]), int(RB.shape[1])
+    PA = torch.full((k, na), float("nan"), dtype=torch.float64, device=RA.device)
+    IA = torch.full((k, na), -2, dtype=torch.int64, device=RA.device)
+    PB = IB = None
+    if both:
+        PB = torch.full((k, nb), float("nan"), dtype=torch.float64, device=RA.device)
+        IB = torch.full((k, nb), -2, dtype=torch.int64, device=RA.device)
+    if workspace is None:
+        workspace = _workspace(torch, lib().mp_abjoin_workspace(na, nb, k, m, PRECISIONS[prec]), RA.device)
+    mask = (1 << 64) - 1 if group_mask is None else int(group_mask)
+    _check(lib().mp_abjoin(RA.data_ptr(), _ld(RA), na, RB.data_ptr(), _ld(RB), nb, k, m, PRECISIONS[prec], refresh,
+                           mask, PA.data_ptr(), IA.data_ptr(), _ld(PA), PB.data_ptr() if both else None,
+                           IB.data_ptr() if both else None, _ld(PB) if both else 0, workspace.data_ptr(),
+                           workspace.numel(), _stream(torch)))
+    return (PA, IA, PB, IB) if both else (PA, IA)
 
 
 def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0,

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void scale_kernel(SJState st) {
     }
     const SeriesPlan& sp = st.plan[c.s];
     const int64_t t = c.x0 + threadIdx.x;
-    const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
+    const double* r = sp.r0 + (int64_t)st.groups.g[c.gi] * sp.ldr;
     if (t >= 0 && t < sp.n) run = fmax(run, fabs(r[t]));
   }
   if (cur >= 0) scale_flush(run, reinterpret_cast<unsigned long long*>(st.scale) + cur, red);
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   const ChunkPos c = decode_chunk(st, blockIdx.x);
   const SeriesPlan& sp = st.plan[c.s];
   const int m = st.m;
-  const double* r = st.R + (int64_t)st.groups.g[c.gi] * st.ldr + sp.col;
+  const double* r = sp.r0 + (int64_t)st.groups.g[c.gi] * sp.ldr;
   const int span = 256 + m + 1;
   for (int q = threadIdx.x; q < span; q += 256) {
     const int64_t t = c.x0 + q;
@@ -241,13 +241,14 @@ __device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned
 // Exact FP64 seeds C(rr, j0 + q) = sum_x (r[rr+x] - mu[rr]) (r[j0+q+x] - mu[j0+q])
 // for the C consecutive diagonals of every lane of the wave at step u: lane t
 // is on row rr = max(u - t, 0) and its first diagonal starts at column
-// j0 = rr + db + t C.  Written as sum_x a_x r[j0+q+x] - mu[j0+q] sum_x a_x with
+// j0 = rr + db + t C.  Rows come from (r, mu), columns from the column series
+// (rc, muc): the same series in a self-join.  Written as sum_x a_x r[j0+q+x] - mu[j0+q] sum_x a_x with
 // a_x = r[rr+x] - mu[rr], so the r values of the C diagonals stream through
 // one sliding window.  The 64 rows span at most 64 + m samples and the 64 C
 // diagonals at most 64 C + m, so chunks of MCH samples of both ranges are
 // first staged in LDS with coalesced loads (stage: 64 + MCH + 64 C + MCH
 // doubles); every lane then reads its windows from LDS.  Diagonals that end
-// before row rr (j0 + q >= n_sub) read clamped samples and are zeroed.  Must be
+// before row rr (j0 + q >= n_cols) read clamped samples and are zeroed.  Must be
 // called by all 64 lanes with the same u.
 template <int C>
 constexpr int seed_chunk() { return (128 / C) * C; }
@@ -256,7 +257,9 @@ constexpr int seed_stage_len() { return 64 + seed_chunk<C>() + 64 * C + seed_chu
 
 template <int C>
 __device__ __forceinline__ void exact_seeds(double* stage, const double* __restrict__ r, const double* __restrict__ mu,
-                                            int u, int db, int t, int n_sub, int nlast, int m, double (&acc)[C]) {
+                                            const double* __restrict__ rc, const double* __restrict__ muc, int u,
+                                            int db, int t, int n_cols, int nlast, int nlast_c, int m,
+                                            double (&acc)[C]) {
   constexpr int MCH = seed_chunk<C>();
   double* srow = stage;
   double* scol = stage + 64 + MCH;
@@ -273,7 +276,7 @@ __device__ __forceinline__ void exact_seeds(double* stage, const double* __restr
   for (int x0 = 0; x0 < m; x0 += MCH) {
     __syncthreads();  // the previous chunk (or the caller's use of the stage) is done
     for (int i = t; i < 64 + MCH; i += 64) srow[i] = r[min(rbase + x0 + i, nlast)];
-    for (int i = t; i < 64 * C + MCH; i += 64) scol[i] = r[min(cbase + x0 + i, nlast)];
+    for (int i = t; i < 64 * C + MCH; i += 64) scol[i] = rc[min(cbase + x0 + i, nlast_c)];
     __syncthreads();
     const int xe = min(MCH, m - x0);
     for (int xx = 0; xx < xe; xx += C) {
@@ -290,7 +293,7 @@ __device__ __forceinline__ void exact_seeds(double* stage, const double* __restr
     }
   }
 #pragma unroll
-  for (int q = 0; q < C; ++q) acc[q] = (j0 + q < n_sub) ? fma(-mu[min(j0 + q, n_sub - 1)], sa, acc[q]) : 0.0;
+  for (int q = 0; q < C; ++q) acc[q] = (j0 + q < n_cols) ? fma(-muc[min(j0 + q, n_cols - 1)], sa, acc[q]) : 0.0;
 }
 
 template <int C>
@@ -321,13 +324,14 @@ struct StatRsrc {
 constexpr int kBufWord3 = 0x00020000;
 
 template <int C>
-__device__ __forceinline__ StatRsrc make_rsrc(const SJState& st, int64_t gbase, int64_t lpad) {
+__device__ __forceinline__ StatRsrc make_rsrc(const SJState& st, int64_t gbase, int64_t lpad, int64_t cgbase,
+                                              int64_t clpad) {
   StatRsrc r;
   r.rd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.dfdg + gbase), 0, (int)(lpad * 16), kBufWord3);
   r.ri = __builtin_amdgcn_make_buffer_rsrc((void*)(st.invn + gbase), 0, (int)(lpad * 8), kBufWord3);
-  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cdfdg + gbase), 0, (int)(lpad * 16), kBufWord3);
-  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cinvn + gbase), 0, (int)(lpad * 8), kBufWord3);
-  r.plane = (int)(lpad / (C - 1));
+  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cdfdg + cgbase), 0, (int)(clpad * 16), kBufWord3);
+  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.cinvn + cgbase), 0, (int)(clpad * 8), kBufWord3);
+  r.plane = (int)(clpad / (C - 1));
   return r;
 }
 
@@ -410,7 +414,7 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
 // and column of a unit is thereby flushed once.  to_global(key, delta) forms
 // the global 64-bit key of a local key whose partner lies delta diagonals up.
 template <int C, int TL, typename K, typename G, typename V>
-__device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_sub, int t,
+__device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_rows, int n_cols, int t,
                                             unsigned long long* gro, unsigned long long* gco, K empty, G to_global,
                                             V valid) {
   constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
@@ -443,7 +447,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
   for (int q = 0; q < RPL; ++q) {
     const int xl = t + 64 * q;
     const int x = u0 - 63 + xl;
-    if (valid(kr[q]) && (last || xl < TL) && xl < NROW && x >= 0 && x < n_sub) {
+    if (valid(kr[q]) && (last || xl < TL) && xl < NROW && x >= 0 && x < n_rows) {
       const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
       atomicMax(gro + x, to_global(kr[q], delta));
     }
@@ -452,7 +456,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
   for (int q = 0; q < CPL; ++q) {
     const int xl = t + 64 * q;
     const int j = u0 + db + xl;
-    if (valid(kc[q]) && (last || xl < TL) && xl < NCOL && j < n_sub) {
+    if (valid(kc[q]) && (last || xl < TL) && xl < NCOL && j < n_cols) {
       const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
       atomicMax(gco + j, to_global(kc[q], delta));
     }
@@ -487,54 +491,53 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
     unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
     if ((int64_t)unit >= st.total_units) break;
     const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
-    SeriesPlan sp = st.plan[s];
-    sp.unit_base = uni(sp.unit_base);
-    sp.nb = uni(sp.nb);
-    sp.ns = uni(sp.ns);
-    sp.n_sub = uni(sp.n_sub);
-    sp.stat_base = uni(sp.stat_base);
-    sp.lpad = uni(sp.lpad);
-    sp.col = uni(sp.col);
-    sp.n = uni(sp.n);
+    const SeriesPlan sp = load_plan(st, s);
     const int64_t local = (int64_t)unit - sp.unit_base;
     const int64_t per_group = (int64_t)sp.nb * sp.ns;
     const int gi = (int)(local / per_group);
     const int64_t rem = local - (int64_t)gi * per_group;
     const int sigma = (int)(rem / sp.nb);
     const int b = (int)(rem - (int64_t)sigma * sp.nb);
-    const int n_sub = (int)sp.n_sub;
-    const int db = st.excl + b * 64 * C;
-    const int Ub = n_sub - db;
+    const int n_sub = (int)sp.n_sub;    // rows: windows of this series
+    const int n_cols = (int)sp.n_cols;  // columns: windows of the column series
+    const int db = sp.d0 + b * 64 * C;
+    // steps of the band: lane t is on row u - t, so the walk lasts until the
+    // last lane has passed the last row of its longest diagonal (in a self-join
+    // that is the first diagonal's n_sub - db rows; rows past n_sub are padding)
+    const int Ub = min(n_sub + 63, n_cols - db);
     const int u_begin = sigma * st.strip;
     if (u_begin >= Ub) continue;
     const int u_end = min(u_begin + st.strip, Ub);
 
-    const int64_t sbase = (int64_t)gi * st.gstride + sp.stat_base + PADL;
-    const double2* __restrict__ dfdg = st.dfdg + sbase;
-    const double* __restrict__ invn = st.invn + sbase;
-    const double* __restrict__ mu = st.mu + sbase;
-    const double* __restrict__ r = st.R + (int64_t)st.groups.g[gi] * st.ldr + sp.col;
-    unsigned long long* gro = st.rowkey + sbase;
-    unsigned long long* gco = st.colkey + sbase;
+    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;    // rows
+    const int64_t cgbase = (int64_t)gi * st.gstride + sp.cstat_base;  // columns
+    const double2* __restrict__ cdfdg_n = st.dfdg + cgbase + PADL;
+    const double* __restrict__ cinvn_n = st.invn + cgbase + PADL;
+    const double* __restrict__ mu = st.mu + gbase + PADL;
+    const double* __restrict__ muc = st.mu + cgbase + PADL;
+    const int g = st.groups.g[gi];
+    const double* __restrict__ r = sp.r0 + (int64_t)g * sp.ldr;
+    const double* __restrict__ rc = sp.cr0 + (int64_t)g * sp.cldr;
+    unsigned long long* gro = st.rowkey + gbase + PADL;
+    unsigned long long* gco = st.colkey + cgbase + PADL;
 
     LaneState<C> ls;
     // exact FP64 seeds at the strip start: lane t's first row is u_begin - t
-    exact_seeds<C>(sseed, r, mu, u_begin, db, t, n_sub, (int)sp.n - 1, m, ls.Cq);
+    exact_seeds<C>(sseed, r, mu, rc, muc, u_begin, db, t, n_cols, (int)sp.n - 1, (int)sp.cn - 1, m, ls.Cq);
     // column window: columns J + q (q < C-1) in slots q, J = u_begin + db + t (C-1)
     {
       const int J = u_begin + db + t * (C - 1);
 #pragma unroll
       for (int q = 0; q < C - 1; ++q) {
-        const double2 cs = dfdg[J + q];
+        const double2 cs = cdfdg_n[J + q];
         ls.cdf[q] = cs.x;
         ls.cdg[q] = cs.y;
-        ls.cinv[q] = invn[J + q];
+        ls.cinv[q] = cinvn_n[J + q];
         ls.colacc[q] = __longlong_as_double((long long)KEY_NONE64);
       }
     }
 
-    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;
-    const StatRsrc R = make_rsrc<C>(st, gbase, sp.lpad);
+    const StatRsrc R = make_rsrc<C>(st, gbase, sp.lpad, cgbase, sp.clpad);
     StepLoad ring[PD];
 #pragma unroll
     for (int k = 0; k < PD; ++k) ring[k] = load_step<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
@@ -549,7 +552,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
           atomicMin(&colk[ngroups * C + t * (C - 1) + q], kbits(ls.colacc[q]));
       }
       flush_block<C, TL>(
-          rowk, colk, last, u0, db, n_sub, t, gro, gco, KEY_NONE64,
+          rowk, colk, last, u0, db, n_sub, n_cols, t, gro, gco, KEY_NONE64,
           [GMAX](unsigned long long key, int delta) {
             const double v = 3.0 - __longlong_as_double((long long)(key & ~(unsigned long long)LMAX));
             return ((unsigned long long)__double_as_longlong(v) & ~GMAX) | (GMAX - (unsigned long long)delta);
@@ -588,13 +591,14 @@ struct StatRsrcF {
 };
 
 template <int C>
-__device__ __forceinline__ StatRsrcF make_rsrc_f(const SJState& st, int64_t gbase, int64_t lpad) {
+__device__ __forceinline__ StatRsrcF make_rsrc_f(const SJState& st, int64_t gbase, int64_t lpad, int64_t cgbase,
+                                                 int64_t clpad) {
   StatRsrcF r;
   r.rd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fdfdg + gbase), 0, (int)(lpad * 8), kBufWord3);
   r.ri = __builtin_amdgcn_make_buffer_rsrc((void*)(st.finvn + gbase), 0, (int)(lpad * 4), kBufWord3);
-  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcdfdg + gbase), 0, (int)(lpad * 8), kBufWord3);
-  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcinvn + gbase), 0, (int)(lpad * 4), kBufWord3);
-  r.plane = (int)(lpad / (C - 1));
+  r.cd = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcdfdg + cgbase), 0, (int)(clpad * 8), kBufWord3);
+  r.ci = __builtin_amdgcn_make_buffer_rsrc((void*)(st.fcinvn + cgbase), 0, (int)(clpad * 4), kBufWord3);
+  r.plane = (int)(clpad / (C - 1));
   return r;
 }
 
@@ -686,42 +690,41 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
     if ((int64_t)unit >= st.total_units) break;
     const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
-    SeriesPlan sp = st.plan[s];
-    sp.unit_base = uni(sp.unit_base);
-    sp.nb = uni(sp.nb);
-    sp.ns = uni(sp.ns);
-    sp.n_sub = uni(sp.n_sub);
-    sp.stat_base = uni(sp.stat_base);
-    sp.lpad = uni(sp.lpad);
-    sp.col = uni(sp.col);
-    sp.n = uni(sp.n);
+    const SeriesPlan sp = load_plan(st, s);
     const int64_t local = (int64_t)unit - sp.unit_base;
     const int64_t per_group = (int64_t)sp.nb * sp.ns;
     const int gi = (int)(local / per_group);
     const int64_t rem = local - (int64_t)gi * per_group;
     const int sigma = (int)(rem / sp.nb);
     const int b = (int)(rem - (int64_t)sigma * sp.nb);
-    const int n_sub = (int)sp.n_sub;
-    const int db = st.excl + b * 64 * C;
-    const int Ub = n_sub - db;
+    const int n_sub = (int)sp.n_sub;    // rows: windows of this series
+    const int n_cols = (int)sp.n_cols;  // columns: windows of the column series
+    const int db = sp.d0 + b * 64 * C;
+    // steps of the band: lane t is on row u - t, so the walk lasts until the
+    // last lane has passed the last row of its longest diagonal (in a self-join
+    // that is the first diagonal's n_sub - db rows; rows past n_sub are padding)
+    const int Ub = min(n_sub + 63, n_cols - db);
     const int u_begin = sigma * st.strip;
     if (u_begin >= Ub) continue;
     const int u_end = min(u_begin + st.strip, Ub);
-    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;
-    const int64_t sbase = gbase + PADL;
-    const double* __restrict__ mu = st.mu + sbase;
-    const double* __restrict__ r = st.R + (int64_t)st.groups.g[gi] * st.ldr + sp.col;
-    unsigned long long* gro = st.rowkey + sbase;
-    unsigned long long* gco = st.colkey + sbase;
+    const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;    // rows
+    const int64_t cgbase = (int64_t)gi * st.gstride + sp.cstat_base;  // columns
+    const double* __restrict__ mu = st.mu + gbase + PADL;
+    const double* __restrict__ muc = st.mu + cgbase + PADL;
+    const int g = st.groups.g[gi];
+    const double* __restrict__ r = sp.r0 + (int64_t)g * sp.ldr;
+    const double* __restrict__ rc = sp.cr0 + (int64_t)g * sp.cldr;
+    unsigned long long* gro = st.rowkey + gbase + PADL;
+    unsigned long long* gco = st.colkey + cgbase + PADL;
 
     LaneStateF<C> ls;
     {  // exact FP64 seeds, rounded once to FP32
       double acc[C];
-      exact_seeds<C>(sseed, r, mu, u_begin, db, t, n_sub, (int)sp.n - 1, m, acc);
+      exact_seeds<C>(sseed, r, mu, rc, muc, u_begin, db, t, n_cols, (int)sp.n - 1, (int)sp.cn - 1, m, acc);
 #pragma unroll
       for (int q = 0; q < C; ++q) ls.Cq[q] = (float)acc[q];
     }
-    const StatRsrcF R = make_rsrc_f<C>(st, gbase, sp.lpad);
+    const StatRsrcF R = make_rsrc_f<C>(st, gbase, sp.lpad, cgbase, sp.clpad);
     {
       const int up = u_begin + db + PADL;
 #pragma unroll
@@ -746,7 +749,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
         for (int q = 0; q < C - 1; ++q) atomicMin(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
       }
       flush_block<C, TL>(
-          rowk, colk, last, u0, db, n_sub, t, gro, gco, 0xFFFFFFFFu,
+          rowk, colk, last, u0, db, n_sub, n_cols, t, gro, gco, 0xFFFFFFFFu,
           [GMAX](uint32_t key, int delta) {
             // local keys order by 1 - rho (min); the global ones by 3 - that = rho + 2 (max)
             const double v = 3.0 - (double)__uint_as_float(key & ~LMAX);
@@ -774,19 +777,32 @@ __device__ int smallest_flat_at_or_after(const SJState& st, const double* invn, 
   return -1;
 }
 
-__global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64_t* I, int64_t ldp) {
+__global__ __launch_bounds__(256) void merge_kernel(SJState st) {
+  extern __shared__ double sh_w[];  // samples [x0, x0 + 256 + m - 1) of the chunk: the block's own windows
   const ChunkPos c = decode_chunk(st, blockIdx.x);
   const SeriesPlan& sp = st.plan[c.s];
+  if (sp.p0 == nullptr) return;  // this series' profile is not wanted
   const int64_t x = c.x0 + threadIdx.x;
-  if (x < 0 || x >= sp.n_sub) return;
   const int m = st.m;
-  const int excl = st.excl;
-  const int64_t n_sub = sp.n_sub;
   const int g = st.groups.g[c.gi];
+  const double* r = sp.r0 + (int64_t)g * sp.ldr;
+  for (int q = threadIdx.x; q < 256 + m - 1; q += 256) {
+    const int64_t t = c.x0 + q;
+    sh_w[q] = (t >= 0 && t < sp.n) ? r[t] : 0.0;
+  }
+  __syncthreads();
+  if (x < 0 || x >= sp.n_sub) return;
+  // partners are windows of the column series cs (this series in a self-join)
+  const int pexcl = sp.pexcl;
+  const int64_t n_cols = sp.n_cols;
+  const SeriesPlan& cp = st.plan[sp.cs];
   const int64_t sbase = (int64_t)c.gi * st.gstride + sp.stat_base + PADL;
+  const int64_t cbase = (int64_t)c.gi * st.gstride + sp.cstat_base + PADL;
   const double* invn = st.invn + sbase;
   const double* mu = st.mu + sbase;
-  const double* r = st.R + (int64_t)g * st.ldr + sp.col;
+  const double* cinvn = st.invn + cbase;
+  const double* cmu = st.mu + cbase;
+  const double* rc = sp.cr0 + (int64_t)g * sp.cldr;
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
   const unsigned long long rk = st.rowkey[sbase + x], ck = st.colkey[sbase + x];
   int64_t partner = -1;
@@ -794,16 +810,16 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64
   else if (rk != 0ull) partner = x + (int64_t)(GMAX - (rk & GMAX));
 
   const double sqrt_m = sqrt((double)m);
-  const int64_t sg = (int64_t)c.s * st.groups.count + c.gi;
+  const int64_t sg = (int64_t)sp.cs * st.groups.count + c.gi;
   const int32_t ff = st.flat_first[sg], fl = st.flat_last[sg];
-  const int32_t* fblk = st.flat_blk + (int64_t)c.gi * st.blk_stride + sp.blk_base;
+  const int32_t* fblk = st.flat_blk + (int64_t)c.gi * st.blk_stride + cp.blk_base;
   const bool xflat = invn[x] == 0.0;
 
-  // smallest admissible flat partner (|j - x| >= excl), -1 if none
+  // smallest admissible flat partner (|j - x| >= pexcl), -1 if none
   int64_t jf = -1;
   if (ff != INT_MAX) {
-    if ((int64_t)ff <= x - excl) jf = ff;
-    else jf = smallest_flat_at_or_after(st, invn, fblk, x + excl, fl);
+    if ((int64_t)ff <= x - pexcl) jf = ff;
+    else jf = smallest_flat_at_or_after(st, cinvn, fblk, x + pexcl, fl);
   }
 
   double best;
@@ -813,31 +829,33 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64
       best = 0.0;
       arg = jf;
     } else {
-      arg = (x >= excl) ? 0 : ((x + excl < n_sub) ? x + excl : -1);
+      arg = (x >= pexcl) ? 0 : ((x + pexcl < n_cols) ? x + pexcl : -1);
       best = (arg >= 0) ? sqrt_m : INFINITY;
     }
   } else {
     best = INFINITY;
     arg = -1;
     if (partner >= 0) {
-      if (invn[partner] == 0.0) {
+      if (cinvn[partner] == 0.0) {
         best = sqrt_m;
       } else {
         // exact distance from explicit differences of the normalised windows
-        const double ax = invn[x] * sqrt_m, ap = invn[partner] * sqrt_m;
-        const double mx = mu[x], mp = mu[partner];
-        // four independent partial sums keep several gathers of the partner in flight
+        const double ax = invn[x] * sqrt_m, ap = cinvn[partner] * sqrt_m;
+        const double mx = mu[x], mp = cmu[partner];
+        // the window itself comes from LDS, the partner's is gathered; four
+        // independent partial sums keep several gathers in flight
+        const double* wx = sh_w + threadIdx.x;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         int q = 0;
         for (; q + 4 <= m; q += 4) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const double e = (r[x + q + u] - mx) * ax - (r[partner + q + u] - mp) * ap;
+            const double e = (wx[q + u] - mx) * ax - (rc[partner + q + u] - mp) * ap;
             acc[u] = fma(e, e, acc[u]);
           }
         }
         for (; q < m; ++q) {
-          const double e = (r[x + q] - mx) * ax - (r[partner + q] - mp) * ap;
+          const double e = (wx[q] - mx) * ax - (rc[partner + q] - mp) * ap;
           acc[0] = fma(e, e, acc[0]);
         }
         best = sqrt((acc[0] + acc[1]) + (acc[2] + acc[3]));
@@ -849,8 +867,8 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st, double* P, int64
       arg = jf;
     }
   }
-  P[(int64_t)g * ldp + sp.col + x] = best;
-  I[(int64_t)g * ldp + sp.col + x] = arg;
+  sp.p0[(int64_t)g * sp.ldp + x] = best;
+  sp.i0[(int64_t)g * sp.ldp + x] = arg;
 }
 
 // ------------------------------------------------------------------ host
@@ -863,11 +881,15 @@ struct PlanInfo {
 
 // C > 0: diagonal kernels (bands of 64 C diagonals x strips of `strip` rows);
 // C = 0: MFMA tiles (row panels of MFMA_TILE rows x segments of MFMA_SEG column tiles).
+// ab = false: every series is joined with itself from diagonal excl on.
+// ab = true: the two series of an AB-join (0 = A, 1 = B): A's units cover the
+// diagonals j - i >= 0 of A x B, B's units the diagonals >= 1 of B x A, so
+// every pair is met once and there is no trivial-match zone.
 static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_t excl, int kact, int C, int strip,
-                     PlanInfo& pl, bool validate) {
+                     PlanInfo& pl, bool validate, bool ab = false) {
   const int cs = C > 0 ? C - 1 : 7;  // de-interleave stride of the column statistics
-  pl.sp.resize(n_series);
-  int64_t stat = 0, unit = 0, chunk = 0, blk = 0, max_nsub = 1;
+  pl.sp.assign(n_series, SeriesPlan{});
+  int64_t stat = 0, chunk = 0, blk = 0, max_nsub = 1;
   for (int64_t s = 0; s < n_series; ++s) {
     SeriesPlan& p = pl.sp[s];
     p.col = offsets[s];
@@ -881,11 +903,28 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.stat_base = stat;
     p.lpad = ((p.n_sub + PADL + PADR + cs - 1) / cs) * cs;
     stat += p.lpad;
-    const int64_t nd = p.n_sub - excl;  // diagonals with admissible pairs
+    p.chunk_base = chunk;
+    chunk += ((p.lpad + 255) / 256) * kact;
+    p.blk_base = blk;
+    blk += (p.n_sub + 255) / 256;
+    p.cs = ab ? (int32_t)(1 - s) : (int32_t)s;
+    p.d0 = ab ? (int32_t)s : excl;
+    p.pexcl = ab ? 0 : excl;
+  }
+  int64_t unit = 0;
+  for (int64_t s = 0; s < n_series; ++s) {
+    SeriesPlan& p = pl.sp[s];
+    const SeriesPlan& q = pl.sp[p.cs];
+    p.n_cols = q.n_sub;
+    p.cn = q.n;
+    p.cstat_base = q.stat_base;
+    p.clpad = q.lpad;
+    const int64_t nd = p.n_cols - p.d0;  // diagonals with pairs
     if (C > 0) {
       const int64_t D = 64 * (int64_t)C;
+      const int64_t rows = std::min<int64_t>(p.n_sub + 63, p.n_cols - p.d0);  // steps of the first band
       p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
-      p.ns = nd > 0 ? (int32_t)((nd + strip - 1) / strip) : 0;
+      p.ns = nd > 0 ? (int32_t)((rows + strip - 1) / strip) : 0;
     } else {
       const int64_t jt_last = (p.n_sub - 1) / MFMA_TILE;
       const int64_t nt0 = jt_last - (int64_t)excl / MFMA_TILE + 1;  // tiles of row panel 0
@@ -894,10 +933,6 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     }
     p.unit_base = unit;
     unit += (int64_t)p.nb * p.ns * kact;
-    p.chunk_base = chunk;
-    chunk += ((p.lpad + 255) / 256) * kact;
-    p.blk_base = blk;
-    blk += (p.n_sub + 255) / 256;
   }
   pl.gstride = stat;
   pl.total_units = unit;
@@ -1142,15 +1177,35 @@ static int validate_selfjoin(const double* R, int64_t ldr, int64_t n_series, con
   return SKMP_OK;
 }
 
-// Everything after validation, with an explicit launch configuration.
-static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
-                        int32_t excl, int32_t prec, const GroupList& gl, double* P, int64_t* I, int64_t ldp,
-                        void* workspace, size_t ws_bytes, hipStream_t st, const Fp64Variant& var, int strip) {
+// Where a series' sketch rows are read and its profile rows written.
+struct JoinIO {
+  const double* r0;
+  int64_t ldr;
+  double* p0;  // NULL: not written
+  int64_t* i0;
+  int64_t ldp;
+};
+
+// Everything after validation, with an explicit launch configuration: the
+// self-join of every series (ab = false) or the AB-join of series 0 and 1.
+static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const JoinIO* io, int32_t m, int32_t excl,
+                    int32_t prec, const GroupList& gl, void* workspace, size_t ws_bytes, hipStream_t st,
+                    const Fp64Variant& var, int strip) {
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   const int kact = gl.count;
   PlanInfo pl;
-  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true);
+  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true, ab);
   if (rc) return rc;
+  for (int64_t q = 0; q < n_series; ++q) {
+    SeriesPlan& p = pl.sp[q];
+    p.r0 = io[q].r0;
+    p.ldr = io[q].ldr;
+    p.p0 = io[q].p0;
+    p.i0 = io[q].i0;
+    p.ldp = io[q].ldp;
+    p.cr0 = io[p.cs].r0;
+    p.cldr = io[p.cs].ldr;
+  }
   Carve cv(workspace, ws_bytes);
   SJBuffers b;
   carve_sj(cv, pl, n_series, kact, prec, b);
@@ -1161,8 +1216,6 @@ static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const in
   if (int rc = upload_async(b.plan, pl.sp.data(), sizeof(SeriesPlan) * n_series, st)) return rc;
 
   SJState s;
-  s.R = R;
-  s.ldr = ldr;
   s.plan = b.plan;
   s.n_series = (int32_t)n_series;
   s.m = m;
@@ -1223,10 +1276,19 @@ static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const in
   SKMP_CHECK_HIP(hipGetLastError());
   {
     StageTimer tm(SKMP_TIMER_MERGE, st);
-    hipLaunchKernelGGL(merge_kernel, cg, fb, 0, st, s, P, I, ldp);
+    hipLaunchKernelGGL(merge_kernel, cg, fb, sizeof(double) * (256 + m - 1), st, s);
   }
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
+}
+
+static int run_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                        int32_t excl, int32_t prec, const GroupList& gl, double* P, int64_t* I, int64_t ldp,
+                        void* workspace, size_t ws_bytes, hipStream_t st, const Fp64Variant& var, int strip) {
+  (void)k;
+  std::vector<JoinIO> io((size_t)n_series);
+  for (int64_t q = 0; q < n_series; ++q) io[q] = JoinIO{R + offsets[q], ldr, P + offsets[q], I + offsets[q], ldp};
+  return run_join(n_series, offsets, false, io.data(), m, excl, prec, gl, workspace, ws_bytes, st, var, strip);
 }
 
 extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k,
@@ -1243,6 +1305,41 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
   const Fp64Variant* vs = variants_of(prec, &nv);
   return run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes,
                       static_cast<hipStream_t>(stream), vs[vidx], strip);
+}
+
+// ------------------------------------------------------------- AB-join
+extern "C" size_t mp_abjoin_workspace(int64_t na, int64_t nb, int32_t k, int32_t m, int32_t prec) {
+  if (na < 1 || nb < 1 || (prec != SKMP_FP64 && prec != SKMP_FP32)) return 0;
+  const int64_t offs[3] = {0, na, na + nb};
+  return mp_selfjoin_workspace(2, offs, k, m, prec);
+}
+
+extern "C" int mp_abjoin(const double* RA, int64_t lda, int64_t na, const double* RB, int64_t ldb, int64_t nb,
+                         int32_t k, int32_t m, int32_t prec, int32_t refresh, uint64_t group_mask, double* PA,
+                         int64_t* IA, int64_t ldpa, double* PB, int64_t* IB, int64_t ldpb, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(RA && RB && PA && IA, "null pointer argument");
+  SKMP_REQUIRE((PB == nullptr) == (IB == nullptr), "PB and IB are given together or not at all");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(m >= 4 && m <= 2048, "m must lie in [4, 2048]");
+  SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "the AB-join runs in FP64 or FP32 (with FP64 refresh)");
+  SKMP_REQUIRE(refresh == 0 || (refresh >= 64 && refresh <= (1 << 20)), "refresh must be 0 or in [64, 2^20]");
+  SKMP_REQUIRE(na >= m && nb >= m, "both series need at least m samples");
+  SKMP_REQUIRE(na < (int64_t)INT_MAX - 2 * PADR && nb < (int64_t)INT_MAX - 2 * PADR, "series too long");
+  SKMP_REQUIRE(lda >= na && ldb >= nb && ldpa >= na && (PB == nullptr || ldpb >= nb),
+               "row strides must be >= the series lengths");
+  if (k < 64) group_mask &= (1ull << k) - 1;
+  GroupList gl;
+  if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
+  const int64_t offs[3] = {0, na, na + nb};
+  int vidx = 0, strip = DEFAULT_STRIP;
+  select_config(prec, refresh, tune_key(prec, m, 2, offs), &vidx, &strip);
+  int nv = 0;
+  const Fp64Variant* vs = variants_of(prec, &nv);
+  const JoinIO io[2] = {JoinIO{RA, lda, PA, IA, ldpa}, JoinIO{RB, ldb, PB, IB, ldpb}};
+  return run_join(2, offs, true, io, m, 0, prec, gl, workspace, ws_bytes, static_cast<hipStream_t>(stream), vs[vidx],
+                  strip);
 }
 
 extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets,

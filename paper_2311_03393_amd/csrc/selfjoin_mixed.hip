@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
     const int64_t sbase = (int64_t)up.gi * st.gstride + up.sp.stat_base + PADL;
     const double* __restrict__ mu = st.mu + sbase;
     const double* __restrict__ invn = st.invn + sbase;
-    const double* __restrict__ r = st.R + (int64_t)st.groups.g[up.gi] * st.ldr + up.sp.col;
+    const double* __restrict__ r = up.sp.r0 + (int64_t)st.groups.g[up.gi] * up.sp.ldr;
     unsigned long long* gro = st.rowkey + sbase;
     unsigned long long* gco = st.colkey + sbase;
 

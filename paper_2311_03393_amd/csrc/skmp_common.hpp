@@ -60,17 +60,38 @@ struct Carve {
 
 // -------------------------------------------------------------- plan
 // One entry per series, device resident (built on the host, copied once per call).
+//
+// A series' work units pair its windows (the rows) with the windows of a
+// column series: itself in a self-join; in an AB-join the other series, the
+// two passes covering diagonals j - i >= 0 (rows of A, columns of B) and
+// j - i >= 1 (rows of B, columns of A).  The column series is also the one
+// the series' nearest neighbours belong to.
 struct SeriesPlan {
-  int64_t col;         // first column of the series in T / R / P / I
+  int64_t col;         // first column of the series in the caller's concatenated layout
   int64_t n;           // samples
   int64_t n_sub;       // n - m + 1
   int64_t stat_base;   // index of x = -PADL of this series inside one group's stats row
-  int64_t unit_base;   // first self-join work unit of this series
+  int64_t unit_base;   // first work unit of this series
   int64_t chunk_base;  // first 256-element chunk of this series (elementwise kernels)
   int64_t blk_base;    // first 256-window block (flat-index summaries)
   int64_t lpad;        // padded windows per group: round_up(n_sub + PADL + PADR, cstride)
   int32_t nb;          // diagonal bands
   int32_t ns;          // strips per band (grid, some empty)
+  const double* r0;    // sketch row g of the series at r0 + g * ldr
+  int64_t ldr;
+  double* p0;          // profile row g at p0 + g * ldp (NULL: not written)
+  int64_t* i0;         // index row g at i0 + g * ldp
+  int64_t ldp;
+  const double* cr0;   // the column series: sketch rows, samples, windows, stats base, padded length
+  int64_t cldr;
+  int64_t cn;
+  int64_t n_cols;
+  int64_t cstat_base;
+  int64_t clpad;
+  int32_t cs;          // index of the column series
+  int32_t d0;          // first diagonal of the units (excl in a self-join; 0 / 1 in an AB-join)
+  int32_t pexcl;       // trivial-match zone against the partner series (0 between different series)
+  int32_t pad0;
 };
 
 struct GroupList {
@@ -78,10 +99,8 @@ struct GroupList {
   int8_t g[64];
 };
 
-// Shared by the self-join kernels (both precisions).
+// Shared by the join kernels (all precisions).
 struct SJState {
-  const double* R;
-  int64_t ldr;
   const SeriesPlan* plan;
   int32_t n_series;
   int32_t m;
@@ -131,6 +150,34 @@ __device__ __forceinline__ int64_t uni(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+  return reinterpret_cast<T*>(uni((int64_t)reinterpret_cast<intptr_t>(p)));
+}
+
+// Plan entry s (s uniform) with every field the join kernels read forced uniform.
+__device__ __forceinline__ SeriesPlan load_plan(const SJState& st, int s) {
+  SeriesPlan sp = st.plan[s];
+  sp.unit_base = uni(sp.unit_base);
+  sp.nb = uni(sp.nb);
+  sp.ns = uni(sp.ns);
+  sp.n_sub = uni(sp.n_sub);
+  sp.stat_base = uni(sp.stat_base);
+  sp.lpad = uni(sp.lpad);
+  sp.col = uni(sp.col);
+  sp.n = uni(sp.n);
+  sp.r0 = uni(sp.r0);
+  sp.ldr = uni(sp.ldr);
+  sp.cr0 = uni(sp.cr0);
+  sp.cldr = uni(sp.cldr);
+  sp.cn = uni(sp.cn);
+  sp.n_cols = uni(sp.n_cols);
+  sp.cstat_base = uni(sp.cstat_base);
+  sp.clpad = uni(sp.clpad);
+  sp.d0 = uni(sp.d0);
+  return sp;
+}
+
 // Decoded self-join work unit: series s, group slot gi and the two unit
 // coordinates (diagonal kernels: strip sigma, band b; MFMA kernel: segment,
 // row panel), with the series fields forced uniform.
@@ -142,15 +189,7 @@ struct UnitPos {
 __device__ __forceinline__ UnitPos decode_unit(const SJState& st, unsigned int unit) {
   UnitPos u;
   u.s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
-  u.sp = st.plan[u.s];
-  u.sp.unit_base = uni(u.sp.unit_base);
-  u.sp.nb = uni(u.sp.nb);
-  u.sp.ns = uni(u.sp.ns);
-  u.sp.n_sub = uni(u.sp.n_sub);
-  u.sp.stat_base = uni(u.sp.stat_base);
-  u.sp.lpad = uni(u.sp.lpad);
-  u.sp.col = uni(u.sp.col);
-  u.sp.n = uni(u.sp.n);
+  u.sp = load_plan(st, u.s);
   const int64_t local = (int64_t)unit - u.sp.unit_base;
   const int64_t per_group = (int64_t)u.sp.nb * u.sp.ns;
   u.gi = (int)(local / per_group);

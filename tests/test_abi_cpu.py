@@ -135,3 +135,26 @@ def test_autotune_rejects_bad_arguments_before_launch(L):
     assert L.mp_selfjoin_autotune(*args(0, 0)) == -1   # reps
     assert L.mp_selfjoin_autotune(*args(0, 2, k=0)) == -1
     assert L.skmp_last_error()
+
+
+def test_abjoin_workspace_and_argument_checks(L):
+    assert L.mp_abjoin_workspace(1000, 3000, 4, 64, 0) > 0
+    assert L.mp_abjoin_workspace(1000, 3000, 4, 64, 1) > 0
+    assert L.mp_abjoin_workspace(1000, 3000, 4, 64, 2) == 0   # MFMA precisions: no AB-join
+    fake = ctypes.c_void_p(16)
+    M = (1 << 64) - 1
+
+    def call(na=300, nb=500, k=2, m=16, prec=0, refresh=0, PB=fake, IB=fake, lda=300, ldpa=300, ws=1 << 30):
+        return L.mp_abjoin(fake, lda, na, fake, 500, nb, k, m, prec, refresh, M, fake, fake, ldpa, PB, IB, 500,
+                           fake, ws, None)
+    assert call(prec=2) == -1           # BF16x3
+    assert call(prec=3) == -1           # FP16x3
+    assert call(na=10) == -1            # A shorter than m
+    assert call(nb=8) == -1             # B shorter than m
+    assert call(k=0) == -1
+    assert call(m=3) == -1
+    assert call(PB=None) == -1          # PB without IB
+    assert call(lda=100) == -1          # stride below the length
+    assert call(refresh=10) == -1
+    assert call(ws=16) == -2            # workspace too small
+    assert L.skmp_last_error()
