@@ -33,10 +33,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-ops/s
-# (FP64 FMA is full rate; FP32 without packed math issues at the same rate)
+# MI355X VALU issue: 256 CUs x 4 SIMDs at 2.4 GHz.  FP64 arithmetic, integer
+# and min/max instructions retire 16 lanes per clock per SIMD (3.93e13
+# lane-ops/s; FP64 vector 78.6 TFLOP/s); FP32 FMA / MUL / ADD retire 32 lanes
+# per clock per SIMD without packed math (7.86e13; FP32 vector 157.3 TFLOP/s).
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
-OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MAX (row, column)
+VALU_FP32_FAST_PEAK = 2 * VALU_LANE_OPS_PEAK
+OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MIN/MAX (row, column)
+# cells/s at which each path's per-cell mix saturates the VALU:
+#   FP64: 6 single-rate ops -> 6 / 3.93e13 s per lane-cell;
+#   FP32: 4 double-rate FP32 ops + 2 single-rate minima -> 4 / 7.86e13 + 2 / 3.93e13.
+CELL_PEAK = {"fp64": VALU_LANE_OPS_PEAK / 6.0,
+             "fp32": 1.0 / (4.0 / VALU_FP32_FAST_PEAK + 2.0 / VALU_LANE_OPS_PEAK)}
+CELL_PEAK_BASIS = {
+    "fp64": "VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 FP64 lane-ops/s; a cell = 2 FMA + 2 MUL + "
+            "2 MIN, all single rate -> 6.55e12 cells/s",
+    "fp32": "VALU issue on gfx950: FP32 FMA/MUL at 32 lanes/clk/SIMD (7.86e13/s, FP32 vector 157.3 TFLOP/s), "
+            "integer minima at 16 (3.93e13/s); a cell = 2 FMA + 2 MUL (FP32) + 2 MIN (u32) = 4 issue slots -> "
+            "9.83e12 cells/s, i.e. 5.90e13 of the cell's lane-ops/s",
+}
 MFMA_16BIT_PEAK = 2.5e15  # dense BF16 / FP16 matrix-core peak of MI355X, FLOP/s
 NAMED = {"c0": ("fp64", 0), "c1": ("fp32", 256), "c2": ("bf16x3", 0), "c3": ("fp32", 256), "c4": ("fp16x3", 0)}
 DESCR = {
@@ -70,6 +85,9 @@ def _parse():
                     help="run one plain device copy of MB MiB before the steps (reference for HBM byte counters)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the FP64 / FP32 launch configuration first (on up to 64 series of a batch)")
+    ap.add_argument("--join", default="self", choices=["self", "ab"],
+                    help="ab: AB-join of the second half of a single-series workload (test) against its first "
+                         "half (train), as in the train/test procedure")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -147,12 +165,113 @@ def _progress(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def _bench_ab(args, prec: str, refresh: int) -> int:
+    """AB-join throughput: the second half of a single-series workload (test)
+    against its first half (train).  One step sketches both halves, joins the
+    test half against the train half and takes the test half's top-10
+    discords.  Cells = k * na' * nb' (every pair of the rectangle)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2311_03393_amd as skmp
+    if args.workload == "c3":
+        print("the AB-join measurement takes a single-series workload (c0, c1, c2, c4)", file=sys.stderr)
+        return 2
+    if prec not in ("fp64", "fp32"):
+        prec, refresh = "fp32", 0
+    dev = torch.device("cuda:0")
+    w = datagen.make(args.workload)
+    k, m = w.k, w.m
+    n = w.T.shape[1]
+    half = n // 2
+    T = torch.from_numpy(w.T).to(dev)
+    Ta, Tb = T[:, half:].contiguous(), T[:, :half].contiguous()
+    del T
+    na, nb = n - half, half
+    na_sub, nb_sub = na - m + 1, nb - m + 1
+    cells = float(k) * na_sub * nb_sub
+    Ra = torch.empty((k, na), dtype=torch.float64, device=dev)
+    Rb = torch.empty((k, nb), dtype=torch.float64, device=dev)
+    sa = torch.empty((1, w.T.shape[0], 2), dtype=torch.float64, device=dev)
+    sb = torch.empty_like(sa)
+    PA = torch.empty((k, na), dtype=torch.float64, device=dev)
+    IA = torch.empty((k, na), dtype=torch.int64, device=dev)
+    out = (torch.empty((1, 10), dtype=torch.int64, device=dev), torch.empty((1, 10), dtype=torch.int32, device=dev),
+           torch.empty((1, 10), dtype=torch.float64, device=dev), torch.empty((1,), dtype=torch.int32, device=dev))
+    results, profiles, picks = {}, {}, {}
+
+    def measure(pr: str, rf: int, steps: int, warmup: int):
+        ws = torch.empty(max(skmp.mp_abjoin_workspace(na, nb, k, m, pr), 256), dtype=torch.uint8, device=dev)
+
+        def step():
+            skmp.sketch_build(Ta, [0, na], k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=Ra, stats=sa)
+            skmp.sketch_build(Tb, [0, nb], k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=Rb, stats=sb)
+            skmp.mp_abjoin(Ra, Rb, k, m, prec=pr, refresh=rf, PA=PA, IA=IA, workspace=ws)
+            skmp.top_discords(PA, [0, na], k, m, 10, out=out)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        _progress(f"ab {pr}: {warmup} warmup step(s) done")
+        skmp.timing_enable(True)
+        for st in skmp.TIMERS:
+            skmp.timing_read(st, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        skmp.timing_enable(False)
+        stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
+        ms = (t1 - t0) * 1e3 / steps
+        _progress(f"ab {pr}: {steps} timed step(s), {ms:.3f} ms each")
+        tiles_ms, tiles_n = stage["tiles"]
+        tile_s = tiles_ms / max(tiles_n, 1) * 1e-3
+        profiles[pr] = PA[:, :na_sub].clone()
+        picks[pr] = out[0].cpu().clone()
+        return {"precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
+                "tile_kernel_ms": tile_s * 1e3, "tile_launches": tiles_n,
+                "tile_frac_of_valu_issue": cells / tile_s / CELL_PEAK[pr],
+                "stages_ms_per_step": {st: v[0] / max(steps, 1) for st, v in stage.items()},
+                "top10": [int(x) for x in out[0][0].cpu()]}
+
+    head = measure(prec, refresh, args.steps, args.warmup)
+    results[prec + (f"_refresh{refresh}" if refresh else "")] = head
+    if prec != "fp64":
+        results["fp64"] = measure("fp64", 0, max(3, args.steps // 2), 1)
+        ref, got = profiles["fp64"], profiles[prec]
+        head["vs_fp64"] = {"max_abs_dP": float((got - ref).abs().max()), "tolerance_dP": 1e-3 * 2 * m ** 0.5,
+                           "top10_equal": bool(torch.equal(picks[prec], picks["fp64"]))}
+    tile_s = head["tile_kernel_ms"] * 1e-3
+    achieved = OPS_PER_CELL * cells / tile_s
+    peak = OPS_PER_CELL * CELL_PEAK[prec]
+    result = {
+        "metric": "AB-join matrix-profile cells/sec (k*na'*nb' per s)",
+        "value": head["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32"}[prec], "data": "synthetic",
+        "config": {"workload": DESCR[args.workload] + ": test = second half, train = first half",
+                   "precision": prec, "refresh": refresh, "na": na, "nb": nb, "cells_per_step": cells,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "Tops/s", "frac": achieved / peak, "traffic": None, "basis": CELL_PEAK_BASIS[prec],
+                     "kernel": KERNELS[prec], "per_launch": {"cells": cells, "ops_per_cell": OPS_PER_CELL,
+                                                             "avg_ms": head["tile_kernel_ms"],
+                                                             "launches": head["tile_launches"]}},
+        "paths": results,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the sketched self-join of one workload is measured on a single "
-              "MI355X (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "MI355X (sharding across GPUs is not built)", file=sys.stderr)
         return 2
     import numpy as np
     import torch
@@ -163,6 +282,8 @@ def main() -> int:
     named_prec, named_refresh = NAMED[args.workload]
     prec = args.prec or named_prec
     refresh = args.refresh if args.refresh is not None else (named_refresh if prec == named_prec else 0)
+    if args.join == "ab":
+        return _bench_ab(args, prec, refresh)
 
     dev = torch.device("cuda:0")
     if args.workload == "c3":
@@ -256,7 +377,7 @@ def main() -> int:
         return {
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
-            "tile_frac_of_valu_issue": OPS_PER_CELL * valid / tile_avg_s / VALU_LANE_OPS_PEAK,
+            "tile_frac_of_valu_issue": (valid / tile_avg_s / CELL_PEAK[pr] if pr in CELL_PEAK else None),
             "tile_frac_of_mfma_peak": (6.0 * m * valid / tile_avg_s / MFMA_16BIT_PEAK
                                        if pr in ("bf16x3", "fp16x3") else None),
             "stages_ms_per_step": {st: v[0] / max(steps, 1) for st, v in stage.items()},
@@ -332,23 +453,22 @@ def main() -> int:
             "per_launch": {"cells": valid, "flops_per_cell": 6 * m, "avg_ms": head["tile_kernel_ms"],
                            "launches": head["tile_launches"]},
             "basis": "dense 16-bit MFMA peak 2.5 PFLOP/s; 3 products x 2m flops per valid half-matrix cell",
-            "valu_equivalent_frac": OPS_PER_CELL * valid / tile_avg_s / VALU_LANE_OPS_PEAK,
         }
     else:
         achieved = OPS_PER_CELL * valid / tile_avg_s
+        peak = OPS_PER_CELL * CELL_PEAK[prec]
         roofline = {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": VALU_LANE_OPS_PEAK / 1e12,
+            "peak": peak / 1e12,
             "unit": "Tops/s",
-            "frac": achieved / VALU_LANE_OPS_PEAK,
+            "frac": achieved / peak,
             "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
             "traffic_detail": tr,
             "kernel": KERNELS[prec],
             "per_launch": {"cells": valid, "ops_per_cell": OPS_PER_CELL, "avg_ms": head["tile_kernel_ms"],
                            "launches": head["tile_launches"]},
-            "basis": "VALU issue: 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s; 6 lane-ops (2 FMA, 2 MUL, "
-                     "2 MAX) per valid half-matrix cell",
+            "basis": CELL_PEAK_BASIS[prec] + "; 6 lane-ops per valid half-matrix cell",
         }
     # the sketch stage is HBM-bound: T is read twice (statistics, projection), R written once
     sk_ms = head["stages_ms_per_step"]["sketch"]

@@ -242,19 +242,28 @@ def mp_selfjoin(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refre
     return P, I
 
 
+def mp_abjoin_workspace(na: int, nb: int, k: int, m: int, prec: str = "fp64") -> int:
+    return int(lib().mp_abjoin_workspace(na, nb, k, m, PRECISIONS[prec]))
+
+
 def mp_abjoin(RA, RB, k: int, m: int, prec: str = "fp64", refresh: int = 0, group_mask: Optional[int] = None,
-              both: bool = False, workspace=None):
+              both: bool = False, PA=None, IA=None, PB=None, IB=None, workspace=None):
     """AB-join: nearest subsequence of RB for every subsequence of RA (and, with
     both=True, the converse).  Returns (PA, IA) or (PA, IA, PB, IB); PA/IA are
     k x na with the last m - 1 columns unused, IA indexes windows of RB."""
     torch = _torch()
     na, nb = int(RA.shape[1]), int(RB.shape[1])
-    PA = torch.full((k, na), float("nan"), dtype=torch.float64, device=RA.device)
-    IA = torch.full((k, na), -2, dtype=torch.int64, device=RA.device)
-    PB = IB = None
-    if both:
+    if PA is None:
+        PA = torch.full((k, na), float("nan"), dtype=torch.float64, device=RA.device)
+    if IA is None:
+        IA = torch.full((k, na), -2, dtype=torch.int64, device=RA.device)
+    assert _ld(PA) == _ld(IA)
+    if both and PB is None:
         PB = torch.full((k, nb), float("nan"), dtype=torch.float64, device=RA.device)
+    if both and IB is None:
         IB = torch.full((k, nb), -2, dtype=torch.int64, device=RA.device)
+    if both:
+        assert _ld(PB) == _ld(IB)
     if workspace is None:
         workspace = _workspace(torch, lib().mp_abjoin_workspace(na, nb, k, m, PRECISIONS[prec]), RA.device)
     mask = (1 << 64) - 1 if group_mask is None else int(group_mask)
