@@ -19,7 +19,11 @@ blocking, fusion or reordering beyond what the definition states:
   self-join variant of Section III-B), with a trivial-match exclusion zone;
 * the discord time detection over the k sketched series (Algorithm 2) and
   the ordered non-overlapping discord list (Sections IV-B, IV-C);
-* the add/delete-dimension update (Section III-C).
+* the add/delete-dimension update (Section III-C);
+* the AB-join between a test and a train series and the discord dimension
+  detection (Algorithm 3), which scores each dimension of the discord's group
+  by the AB-join of the test subsequence against that dimension's train
+  series.
 
 Readings where the paper is silent (each one is listed in the design doc):
 
@@ -304,6 +308,38 @@ def ab_join(ra: np.ndarray, rb: np.ndarray, m: int, rows=None) -> Tuple[np.ndarr
         jj = int(np.argmin(dd))          # first (smallest j) minimum
         P[i], I[i] = float(dd[jj]), jj
     return P, I
+
+
+def dimension_detection(T_train: np.ndarray, T_test, i_star: int, dims: Sequence[int], m: int,
+                        excl: int = 0) -> Tuple[np.ndarray, np.ndarray, int]:
+    """Algorithm 3: for every dimension j of ``dims`` (the group J_g* of the
+    discord), the z-normalised distance from the test subsequence starting at
+    ``i_star`` in dimension j to its nearest subsequence of the train series in
+    dimension j (the AB-join of that one subsequence, Def. 6), and the first
+    dimension with the strictly largest score (s_bsf starts at 0; if no score
+    exceeds 0 the first dimension is returned).
+
+    Dimensions are z-normalised first (Algorithm 1's normalisation).  With
+    ``T_test is None`` the test series is the train series itself (the
+    self-join setting): subsequences within ``excl`` of ``i_star`` are trivial
+    matches.  Returns (scores, neighbour index per dimension, position of j* in
+    ``dims``).
+    """
+    Tb_train, _, _ = znorm_dims(T_train)
+    Tb_test = Tb_train if T_test is None else znorm_dims(T_test)[0]
+    scores = np.zeros(len(dims))
+    nn = np.zeros(len(dims), dtype=np.int64)
+    for q, j in enumerate(dims):
+        if T_test is None:
+            P, I = matrix_profile(Tb_train[j], m, excl, rows=[i_star])
+        else:
+            P, I = ab_join(Tb_test[j], Tb_train[j], m, rows=[i_star])
+        scores[q], nn[q] = P[i_star], I[i_star]
+    s_bsf, best = 0.0, 0
+    for q in range(len(dims)):
+        if scores[q] > s_bsf:
+            s_bsf, best = float(scores[q]), q
+    return scores, nn, best
 
 
 # ------------------------------------------------------------------ discords

@@ -309,6 +309,36 @@ def test_ab_join_planted_copy_and_self(c_oracle):
     assert np.max(np.abs(d - P)) < 1e-12
 
 
+# ------------------------------------------------- dimension detection
+def test_dimension_detection_finds_the_planted_dimension(c_oracle):
+    """A discord planted in one dimension of the test series is attributed to it,
+    and each score is the AB-join distance of the test subsequence in that
+    dimension (affine-invariant: raw or normalised dimensions give the same)."""
+    rng = np.random.default_rng(31)
+    d, n, m = 7, 1200, 32
+    T_train = datagen.tiny_series(41, d, n)
+    T_test = datagen.tiny_series(42, d, 900)
+    i_star, j0 = 400, 5
+    loc = T_test[j0, i_star:i_star + m].std()
+    T_test[j0, i_star:i_star + m] += 6 * loc * np.sin(np.linspace(0, 9 * np.pi, m) ** 1.3)
+    dims = [0, 2, 3, 5, 6]
+    scores, nn, best = O.dimension_detection(T_train, T_test, i_star, dims, m)
+    assert dims[best] == j0
+    for q, j in enumerate(dims):
+        P, I = c_oracle.ab_profile(T_test[j], T_train[j], m, rows=[i_star])
+        assert abs(P[0] - scores[q]) < 1e-9 and I[0] == nn[q]
+    # strict ">" from 0: the first of equal scores wins
+    same = np.stack([T_train[1]] * 3)
+    s2, _, b2 = O.dimension_detection(same, np.stack([T_test[1]] * 3), i_star, [0, 1, 2], m)
+    assert s2[0] == s2[1] == s2[2] and b2 == 0
+    # self-join setting: the exclusion zone around i_star applies
+    s3, nn3, _ = O.dimension_detection(T_test, None, i_star, dims, m, excl=m // 4)
+    assert np.all(np.abs(nn3 - i_star) >= m // 4)
+    for q, j in enumerate(dims):
+        P, I = c_oracle.profile(T_test[j], m, m // 4, rows=[i_star])
+        assert abs(P[0] - s3[q]) < 1e-9 and I[0] == nn3[q]
+
+
 # ---------------------------------------------------------------- discords
 def test_time_detection_strict_greater_keeps_first_group():
     P = np.array([[0.1, 0.9, 0.2],
