@@ -227,6 +227,42 @@ int mp_abjoin(const double* RA, int64_t lda, int64_t na, const double* RB, int64
               int32_t m, int32_t prec, int32_t refresh, uint64_t group_mask, double* PA, int64_t* IA, int64_t ldpa,
               double* PB, int64_t* IB, int64_t ldpb, void* workspace, size_t ws_bytes, void* stream);
 
+/* Workspace bytes needed by dim_detect (0 for invalid sizes). */
+size_t dim_detect_workspace(int64_t n_train, int32_t n_dims, int32_t m);
+
+/*
+ * Discord dimension detection (Algorithm 3): for every dimension j listed in
+ * dims (the group J_g* of a discord found on the sketch, Algorithm 2), the
+ * z-normalised distance (Def. 3) from the test subsequence starting at i_star
+ * in dimension j to its nearest subsequence of the train series in dimension
+ * j (the AB-join of that one subsequence, Def. 6), and the position in dims of
+ * the first dimension with the strictly largest score (0 when no score exceeds
+ * 0).  Dimensions are compared as Algorithm 1 normalises them: a dimension with
+ * sigma_j = 0 in its statistics is constant (all its subsequences are flat),
+ * otherwise a subsequence is flat when its sigma is <= 1e-10 max|T_j - mu_j|.
+ *   T_train, T_test  device, d x n_train / d x n_test, row strides ld_train,
+ *            ld_test, dtype SKMP_F64 or SKMP_F32 (the same for both).
+ *   stats_train, stats_test  device, d x 2 doubles (mu, sigma) of each
+ *            dimension over its series (sketch_build's dim_stats of a
+ *            one-series call).
+ *   dims     host, n_dims row indices in [0, d) (1 <= n_dims <= 65535).
+ *   i_star   start of the test subsequence, 0 <= i_star <= n_test - m.
+ *   m        4 <= m <= 2048, n_train, n_test >= m.
+ *   excl     0: train and test are different series (no trivial-match zone);
+ *            > 0: the self-join setting -- T_test, stats_test, ld_test and
+ *            n_test must equal the train ones, and train subsequences t with
+ *            |t - i_star| < excl are excluded.
+ *   scores, nn  device out, n_dims: the distance and the nearest train
+ *            subsequence's index (+inf and -1 when every one is excluded).
+ *   best     device out, one int32: the position of j* in dims.
+ * Distances are FP64 from explicit differences of the normalised subsequences.
+ * Asynchronous on `stream`.
+ */
+int dim_detect(const void* T_train, int64_t ld_train, int64_t n_train, const double* stats_train, const void* T_test,
+               int64_t ld_test, int64_t n_test, const double* stats_test, int32_t dtype, int64_t d,
+               const int64_t* dims, int32_t n_dims, int64_t i_star, int32_t m, int32_t excl, double* scores,
+               int64_t* nn, int32_t* best, void* workspace, size_t ws_bytes, void* stream);
+
 /*
  * The process's tuning table as text, one line per shape class:
  * "prec mlog nlog variant strip ms".  skmp_tuning_export writes at most len
@@ -265,7 +301,8 @@ int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* 
 #define SKMP_TIMER_TILES 2      /* the self-join tile kernel (FP64 or mixed) */
 #define SKMP_TIMER_MERGE 3      /* key merge + FP64 polish */
 #define SKMP_TIMER_DISCORDS 4   /* top_discords */
-#define SKMP_TIMER_COUNT 5
+#define SKMP_TIMER_DIMDETECT 5  /* dim_detect */
+#define SKMP_TIMER_COUNT 6
 int skmp_timing_enable(int on);
 int skmp_timing_read(int32_t which, int32_t reset, double* total_ms, int64_t* launches);
 

@@ -36,10 +36,11 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 # every symbol include/sketchmp.h declares
 EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
-            "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "skmp_tuning_export",
+            "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "dim_detect_workspace", "dim_detect",
+            "skmp_tuning_export",
             "skmp_tuning_import", "skmp_tuning_clear",
             "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
-TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4}
+TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4, "dimdetect": 5}
 
 
 class SketchMPError(RuntimeError):
@@ -82,6 +83,10 @@ def lib():
         L.mp_abjoin_workspace.restype = _sz
         L.mp_abjoin.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i32, _i32, _i32, _i32, _u64, _vp, _vp, _i64, _vp,
                                 _vp, _i64, _vp, _sz, _vp]
+        L.dim_detect_workspace.argtypes = [_i64, _i32, _i32]
+        L.dim_detect_workspace.restype = _sz
+        L.dim_detect.argtypes = [_vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _i32, _i64, _i64p, _i32, _i64, _i32,
+                                 _i32, _vp, _vp, _vp, _vp, _sz, _vp]
         L.top_discords_workspace.argtypes = [_i64, _i64p, _i32, _i32]
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
@@ -272,6 +277,39 @@ def mp_abjoin(RA, RB, k: int, m: int, prec: str = "fp64", refresh: int = 0, grou
                            IB.data_ptr() if both else None, _ld(PB) if both else 0, workspace.data_ptr(),
                            workspace.numel(), _stream(torch)))
     return (PA, IA, PB, IB) if both else (PA, IA)
+
+
+def group_dims(kind: str, k: int, seed: int, g: int, dim_ids) -> np.ndarray:
+    """Rows of the dimensions that sketch group g mixes (J_g: non-zero coefficients)."""
+    S = sketch_coeffs(kind, k, seed, dim_ids)
+    return np.nonzero(S[g])[0].astype(np.int64)
+
+
+def dim_detect(T_train, stats_train, dims, i_star: int, m: int, T_test=None, stats_test=None, excl: int = 0):
+    """Discord dimension detection (Algorithm 3).  T_* are d x n device tensors
+    of one series each, stats_* their (mu, sigma) per dimension (d x 2, as
+    sketch_build returns for a one-series call); without T_test the test series
+    is the train series (excl > 0 then excludes trivial matches of i_star).
+    Returns (scores, nn, position of j* in dims) as device tensors."""
+    torch = _torch()
+    same = T_test is None
+    if same:
+        T_test, stats_test = T_train, stats_train
+    assert T_train.dtype == T_test.dtype and T_train.stride(1) == 1 and T_test.stride(1) == 1
+    dtype = {torch.float64: F64, torch.float32: F32}[T_train.dtype]
+    st_tr = stats_train.reshape(-1, 2).contiguous()
+    st_te = st_tr if same else stats_test.reshape(-1, 2).contiguous()
+    dims = _i64arr(dims)
+    n_tr, n_te = int(T_train.shape[1]), int(T_test.shape[1])
+    scores = torch.empty(dims.size, dtype=torch.float64, device=T_train.device)
+    nn = torch.empty(dims.size, dtype=torch.int64, device=T_train.device)
+    best = torch.empty(1, dtype=torch.int32, device=T_train.device)
+    ws = _workspace(torch, lib().dim_detect_workspace(n_tr, dims.size, m), T_train.device)
+    _check(lib().dim_detect(T_train.data_ptr(), _ld(T_train), n_tr, st_tr.data_ptr(), T_test.data_ptr(), _ld(T_test),
+                            n_te, st_te.data_ptr(), dtype, int(T_train.shape[0]), _ptr64(dims), dims.size, i_star, m,
+                            excl, scores.data_ptr(), nn.data_ptr(), best.data_ptr(), ws.data_ptr(), ws.numel(),
+                            _stream(torch)))
+    return scores, nn, best
 
 
 def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0,

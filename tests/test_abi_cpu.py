@@ -158,3 +158,27 @@ def test_abjoin_workspace_and_argument_checks(L):
     assert call(refresh=10) == -1
     assert call(ws=16) == -2            # workspace too small
     assert L.skmp_last_error()
+
+
+def test_dim_detect_argument_checks(L):
+    assert L.dim_detect_workspace(5000, 8, 64) > 0
+    assert L.dim_detect_workspace(10, 8, 64) == 0
+    fake = ctypes.c_void_p(16)
+    other = ctypes.c_void_p(32)
+    dims = np.array([0, 3, 5], dtype=np.int64)
+    dp = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def call(Tte=fake, ste=fake, n_tr=1000, n_te=1000, d=6, i_star=10, m=32, excl=0, dtype=0, nd=3, ws=1 << 30):
+        return L.dim_detect(fake, 1000, n_tr, fake, Tte, 1000, n_te, ste, dtype, d, dp, nd, i_star, m, excl, fake,
+                            fake, fake, fake, ws, None)
+    assert call(m=3) == -1                  # m < 4
+    assert call(n_tr=20) == -1              # train shorter than m
+    assert call(i_star=1000 - 31) == -1     # the subsequence runs past the test series
+    assert call(i_star=-1) == -1
+    assert call(d=5) == -1                  # dimension 5 out of range
+    assert call(excl=8, Tte=other) == -1    # self-join setting needs the same series
+    assert call(excl=8, ste=other) == -1
+    assert call(dtype=3) == -1
+    assert call(nd=0) == -1
+    assert call(ws=16) == -2                # workspace too small
+    assert L.skmp_last_error()
