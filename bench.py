@@ -88,6 +88,7 @@ def _parse():
     ap.add_argument("--join", default="self", choices=["self", "ab"],
                     help="ab: AB-join of the second half of a single-series workload (test) against its first "
                          "half (train), as in the train/test procedure")
+    ap.add_argument("--no-dims", action="store_true", help="skip the dimension-detection measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -321,7 +322,7 @@ def main() -> int:
     for a, ns in zip(offsets[:-1], n_subs):
         wmask_h[int(a):int(a) + int(ns)] = True
     wmask = torch.from_numpy(wmask_h).to(dev)
-    profiles, picks = {}, {}
+    profiles, picks, groups = {}, {}, {}
 
     def measure(pr: str, rf: int, steps: int, warmup: int):
         ws = torch.empty(skmp.mp_selfjoin_workspace(offsets, k, m, pr), dtype=torch.uint8, device=dev)
@@ -374,6 +375,7 @@ def main() -> int:
         tile_avg_s = tiles_ms / max(tiles_n, 1) * 1e-3
         profiles[pr] = P[:, wmask].clone()
         picks[pr] = out[0].cpu().clone()
+        groups[pr] = out[1].cpu().clone()
         return {
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
@@ -433,6 +435,34 @@ def main() -> int:
             del got, both, err, sq
         del ref
     profiles.clear()
+
+    # discord dimension detection (Algorithm 3) for the named path's top discord:
+    # all dimensions of its group, self-join setting, FP64
+    dimdet = None
+    if n_series == 1 and not args.no_dims:
+        i_star, g_star = int(picks[prec][0, 0]), int(groups[prec][0, 0])
+        if i_star >= 0 and g_star >= 0:
+            dims = skmp.group_dims(w.kind, k, w.sketch_seed, g_star, w.dim_ids)
+            skmp.dim_detect(T, stats[0], dims, i_star, m, excl=w.excl)   # warm-up
+            torch.cuda.synchronize()
+            skmp.timing_enable(True)
+            skmp.timing_read("dimdetect", reset=True)
+            reps = 5
+            for _ in range(reps):
+                sc, nn_, best = skmp.dim_detect(T, stats[0], dims, i_star, m, excl=w.excl)
+            torch.cuda.synchronize()
+            skmp.timing_enable(False)
+            dd_ms, dd_n = skmp.timing_read("dimdetect", reset=True)
+            per = dd_ms / max(dd_n, 1)
+            n_sub0 = int(lens[0]) - m + 1
+            ops = float(len(dims)) * n_sub0 * 7.0 * m   # mean, variance and distance passes, FP64
+            dimdet = {"i_star": i_star, "group": g_star, "n_dims": int(len(dims)),
+                      "j_star": int(dims[int(best.item())]), "ms": per,
+                      "roofline": {"bound": "alu", "achieved": ops / (per * 1e-3) / 1e12,
+                                   "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
+                                   "frac": ops / (per * 1e-3) / VALU_LANE_OPS_PEAK,
+                                   "basis": "7 m single-rate FP64 lane-ops per (dimension, train subsequence): "
+                                            "mean, variance, explicit-difference distance"}}
 
     tile_avg_s = head["tile_kernel_ms"] * 1e-3
     tr = _traffic(KERNELS[prec], args.workload)
@@ -500,6 +530,7 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "sketch": sketch,
+        "dim_detect": dimdet,
         "paths": paths,
     }
     if not args.no_cpu_baseline:
