@@ -89,6 +89,10 @@ def _parse():
                     help="ab: AB-join of the second half of a single-series workload (test) against its first "
                          "half (train), as in the train/test procedure")
     ap.add_argument("--no-dims", action="store_true", help="skip the dimension-detection measurement")
+    ap.add_argument("--experiment", default=None, choices=["random-walks"],
+                    help="random-walks: the sketched vs exact discord experiment of Section IV-A")
+    ap.add_argument("--trials", type=int, default=20)
+    ap.add_argument("--dims-list", default="250,500,1000,2500,5000,7500,10000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -164,6 +168,91 @@ def _cpu_baseline(R_host_series, w, target_s: float):
 
 def _progress(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _experiment_random_walks(args) -> int:
+    """Section IV-A on the GPU: random walks of length 10,000 with d dimensions,
+    m = 100, k = ceil(sqrt(d)) (at most 64, the library's group limit), count
+    sketch (the paper's), `trials` seeded repetitions per d.  Per trial:
+      sketched: sketch_build -> mp_selfjoin over the k groups -> top discord
+                (Algorithm 2) -> dim_detect over the discord's group
+                (Algorithm 3), self-join setting with the m/4 exclusion zone;
+      exact:    every dimension's own self-join profile (exact_profiles: the
+                d dimensions as one batch) and its top discord.
+    Success: the sketched discord's exact score (its dimension's profile at its
+    start) ranks within the top 0.01 % of all d x n' exact scores (ties counted
+    in its favour); reported for (j*, i*) of Algorithms 2-3 and after the
+    refinement (the top discord of dimension j*'s own self-join).  Speedup:
+    exact time / sketched time, both end to end on the GPU in the same
+    precision; the ranking always uses FP64 exact scores."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2311_03393_amd as skmp
+    dev = torch.device("cuda:0")
+    n, m = 10000, 100
+    excl = m // 4
+    prec = args.prec or "fp64"
+    refresh = args.refresh if args.refresh is not None else 0
+    ds = [int(x) for x in args.dims_list.split(",")]
+    rows = []
+    for d in ds:
+        k = min(int(math.ceil(math.sqrt(d))), 64)
+        succ, succ_ref, t_sk, t_ref, t_ex, ranks, ranks_ref = 0, 0, [], [], [], [], []
+        for trial in range(args.trials):
+            seed = 7919 * d + trial
+            g = torch.Generator(device=dev)
+            g.manual_seed(seed)
+            T = torch.randn((d, n), generator=g, dtype=torch.float64, device=dev).cumsum_(dim=1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R, stats = skmp.sketch_build(T, [0, n], k, "count", seed)
+            P, _ = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec, refresh=refresh)
+            idx, grp, _, _ = skmp.top_discords(P, [0, n], k, m, 1)
+            i_star, g_star = int(idx[0, 0].item()), int(grp[0, 0].item())
+            dims = skmp.group_dims("count", k, seed, g_star, np.arange(d))
+            _, _, best = skmp.dim_detect(T, stats[0], dims, i_star, m, excl=excl)
+            j_star = int(dims[int(best.item())])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            i_ref, _ = skmp.refine_discord(T, j_star, m, excl, prec=prec, refresh=refresh)
+            torch.cuda.synchronize()
+            t1r = time.perf_counter()
+            Pe, _ = skmp.exact_profiles(T, m, excl, prec=prec, refresh=refresh)
+            offs = np.arange(d + 1, dtype=np.int64) * n
+            eidx, _, escore, _ = skmp.top_discords(Pe.reshape(1, d * n), offs, 1, m, 1)
+            _ = int(torch.argmax(escore[:, 0]).item())   # the exact multidimensional discord
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_sk.append(t1 - t0)
+            t_ref.append(t1r - t1)
+            t_ex.append(t2 - t1r)
+            if prec != "fp64":
+                Pe, _ = skmp.exact_profiles(T, m, excl, prec="fp64")
+            n_sub = n - m + 1
+            scores = Pe[:, :n_sub]
+            total = d * n_sub
+            rank = int((scores > scores[j_star, i_star]).sum().item()) + 1
+            rank_ref = int((scores > scores[j_star, i_ref]).sum().item()) + 1
+            ranks.append(rank / total)
+            ranks_ref.append(rank_ref / total)
+            succ += int(rank <= 1e-4 * total)
+            succ_ref += int(rank_ref <= 1e-4 * total)
+            del T, R, stats, P, Pe, scores
+        tsk, tref, tex = float(np.median(t_sk)), float(np.median(t_ref)), float(np.median(t_ex))
+        rows.append({"d": d, "k": k, "trials": args.trials, "success_rate": succ / args.trials,
+                     "success_rate_refined": succ_ref / args.trials,
+                     "median_rank_fraction": float(np.median(ranks)),
+                     "median_rank_fraction_refined": float(np.median(ranks_ref)),
+                     "t_sketched_ms": 1e3 * tsk, "t_refine_ms": 1e3 * tref, "t_exact_ms": 1e3 * tex,
+                     "speedup": tex / tsk, "speedup_with_refinement": tex / (tsk + tref)})
+        _progress(f"random walks d={d} k={k}: success {succ}/{args.trials}, refined {succ_ref}/{args.trials}, "
+                  f"speedup {rows[-1]['speedup']:.1f}x ({rows[-1]['speedup_with_refinement']:.1f}x refined)")
+    print(json.dumps({"experiment": "Section IV-A random walks: sketched vs exact discord", "n": n, "m": m,
+                      "excl": excl, "precision": prec, "sketch": "count", "rows": rows}), flush=True)
+    return 0
 
 
 def _bench_ab(args, prec: str, refresh: int) -> int:
@@ -285,6 +374,8 @@ def main() -> int:
     refresh = args.refresh if args.refresh is not None else (named_refresh if prec == named_prec else 0)
     if args.join == "ab":
         return _bench_ab(args, prec, refresh)
+    if args.experiment == "random-walks":
+        return _experiment_random_walks(args)
 
     dev = torch.device("cuda:0")
     if args.workload == "c3":

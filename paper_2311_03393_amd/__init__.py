@@ -279,6 +279,32 @@ def mp_abjoin(RA, RB, k: int, m: int, prec: str = "fp64", refresh: int = 0, grou
     return (PA, IA, PB, IB) if both else (PA, IA)
 
 
+def exact_profiles(T, m: int, excl: int, prec: str = "fp64", refresh: int = 0):
+    """The exact multidimensional baseline: the self-join profile of every
+    dimension of one series (T: d x n contiguous device tensor), i.e. the sketch
+    with k = d and the identity.  Runs as one batched launch per stage: the d
+    dimensions are d one-dimensional series of the batch, each z-normalised by
+    the sum sketch of one dimension.  Returns (P, I) as d x n tensors."""
+    torch = _torch()
+    assert T.is_contiguous() and T.dim() == 2
+    d, n = int(T.shape[0]), int(T.shape[1])
+    flat = T.reshape(1, d * n)
+    offsets = np.arange(d + 1, dtype=np.int64) * n
+    R, _ = sketch_build(flat, offsets, 1, "sum", 0)
+    P, I = mp_selfjoin(R, offsets, 1, m, excl, prec=prec, refresh=refresh)
+    return P.reshape(d, n), I.reshape(d, n)
+
+
+def refine_discord(T, j: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0):
+    """The optional refinement after Algorithm 3: the self-join of the whole
+    detected dimension j (z-normalised) and its top discord.  Returns
+    (start, score) as host values."""
+    P, _ = exact_profiles(T[j:j + 1].contiguous(), m, excl, prec=prec, refresh=refresh)
+    n = int(T.shape[1])
+    idx, _, score, nf = top_discords(P, [0, n], 1, m, 1)
+    return int(idx[0, 0].item()), float(score[0, 0].item())
+
+
 def group_dims(kind: str, k: int, seed: int, g: int, dim_ids) -> np.ndarray:
     """Rows of the dimensions that sketch group g mixes (J_g: non-zero coefficients)."""
     S = sketch_coeffs(kind, k, seed, dim_ids)

@@ -129,3 +129,29 @@ def test_two_phase_detection(workload, kind, k):
     torch.cuda.synchronize()
     ref = O.dimension_detection(w.T, None, i_star, [int(j) for j in dims], w.m, excl=w.excl)
     _check(s.cpu().numpy(), nn.cpu().numpy(), int(best.item()), ref, w.m, fp64_tol(w.m))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exact_multidimensional_baseline(prec, c_oracle):
+    """Every dimension's own self-join profile in one batched launch (k = d,
+    identity sketch) against the oracle's profile of each z-normalised dimension."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    from tests.helpers import check_neighbours, mixed_tol
+    dev = torch.device("cuda:0")
+    d, n, m, excl = 12, 1500, 32, 8
+    T = datagen.tiny_series(77, d, n)
+    T[4] = -0.5                       # constant dimension
+    T[7, 300:600] = 2.0               # flat windows
+    P, I = skmp.exact_profiles(torch.from_numpy(T).to(dev), m, excl, prec=prec,
+                               refresh=256 if prec == "fp32" else 0)
+    torch.cuda.synchronize()
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    Tb, _, _ = O.znorm_dims(T)
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
+    n_sub = n - m + 1
+    for j in range(d):
+        P_o, _ = c_oracle.profile(Tb[j], m, excl)
+        ok, err = profile_close(P[j, :n_sub], P_o, m, tol)
+        assert ok.all(), (j, err)
+        check_neighbours(c_oracle, Tb[j], m, excl, np.arange(n_sub), I[j, :n_sub], P_o, tol)
