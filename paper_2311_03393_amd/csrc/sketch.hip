@@ -10,9 +10,10 @@
 //              dimensions of its slice, normalises each value and accumulates
 //              k sketch rows in FP64:
 //              R[g][t] = sum_j S[g][j] * (T[j][t] - mu_j) / sigma_j.
-// The coefficient matrix S is drawn on the host (integer hashing and glibc
-// libm) and copied to the workspace; it is a pure function of (kind, k, seed,
-// dimension id), so an update regenerates exactly the columns it needs.
+// The coefficient matrix S is a pure function of (kind, k, seed, dimension
+// id), so an update regenerates exactly the columns it needs.  Count and sum
+// coefficients (integer hashing) are drawn on the device straight into the
+// projection's table; Gaussian ones on the host (glibc libm) and copied.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -49,26 +50,38 @@ static inline uint64_t mulmod61(uint64_t a, uint64_t x) {
   return s;
 }
 
+// Carter-Wegman parameters of the count sketch's hash pair: (a, b) for the
+// bucket h, (a2, b2) for the sign s, from SplitMix64(seed) outputs 1..4.
+static void count_params(uint64_t seed, uint64_t* a, uint64_t* b, uint64_t* a2, uint64_t* b2) {
+  *a = 1 + splitmix64_output(seed, 1) % (P61 - 1);
+  *b = splitmix64_output(seed, 2) % P61;
+  *a2 = 1 + splitmix64_output(seed, 3) % (P61 - 1);
+  *b2 = splitmix64_output(seed, 4) % P61;
+}
+
+static int check_ids(const int64_t* ids, int64_t d) {
+  for (int64_t j = 0; j < d; ++j) {
+    int64_t id = ids ? ids[j] : j;
+    SKMP_REQUIRE(id >= 0 && (uint64_t)id < P61, "dimension ids must lie in [0, 2^61 - 1)");
+  }
+  return SKMP_OK;
+}
+
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S) {
   SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
   SKMP_REQUIRE(d >= 1, "d must be >= 1");
   SKMP_REQUIRE(S != nullptr, "S is NULL");
   SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
   SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
-  for (int64_t j = 0; j < d; ++j) {
-    int64_t id = ids ? ids[j] : j;
-    SKMP_REQUIRE(id >= 0 && (uint64_t)id < P61, "dimension ids must lie in [0, 2^61 - 1)");
-  }
+  if (int rc = check_ids(ids, d)) return rc;
   std::memset(S, 0, sizeof(double) * (size_t)k * (size_t)d);
   if (kind == SKMP_SUM) {
     for (int64_t j = 0; j < d; ++j) S[j] = 1.0;
     return SKMP_OK;
   }
   if (kind == SKMP_COUNT) {
-    uint64_t a = 1 + splitmix64_output(seed, 1) % (P61 - 1);
-    uint64_t b = splitmix64_output(seed, 2) % P61;
-    uint64_t a2 = 1 + splitmix64_output(seed, 3) % (P61 - 1);
-    uint64_t b2 = splitmix64_output(seed, 4) % P61;
+    uint64_t a, b, a2, b2;
+    count_params(seed, &a, &b, &a2, &b2);
     for (int64_t j = 0; j < d; ++j) {
       uint64_t id = (uint64_t)(ids ? ids[j] : j);
       uint64_t hv = mulmod61(a, id) + b;
@@ -101,6 +114,38 @@ constexpr int STAT_THREADS = 256;
 __global__ void fill_u32(unsigned int* p, unsigned int v, int64_t count) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
+}
+
+// (a x) mod (2^61 - 1) from the 128-bit product: a x = hi 2^64 + lo and
+// 2^64 = 8 (mod 2^61 - 1); fully reduced, so it equals the host's value.
+__device__ __forceinline__ uint64_t mulmod61_dev(uint64_t a, uint64_t x) {
+  const uint64_t lo = a * x, hi = __umul64hi(a, x);
+  uint64_t s = (lo & P61) + (lo >> 61) + (hi << 3);
+  s = (s & P61) + (s >> 61);
+  if (s >= P61) s -= P61;
+  return s;
+}
+
+// Count or sum sketch coefficients straight into the projection's transposed
+// table St[j][g] (kb groups per row, zero past k): the hash pair of the host
+// generator (Section III-A), evaluated per dimension, so no table crosses PCIe.
+__global__ void count_coeffs_kernel(double* __restrict__ St, int64_t d, int kb, int k, int kind,
+                                    const int64_t* __restrict__ ids, uint64_t a, uint64_t b, uint64_t a2,
+                                    uint64_t b2) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  double* row = St + j * kb;
+  for (int g = 0; g < kb; ++g) row[g] = 0.0;
+  if (kind == SKMP_SUM) {
+    row[0] = 1.0;
+    return;
+  }
+  const uint64_t id = ids ? (uint64_t)ids[j] : (uint64_t)j;
+  uint64_t hv = mulmod61_dev(a, id) + b;
+  if (hv >= P61) hv -= P61;
+  uint64_t sv = mulmod61_dev(a2, id) + b2;
+  if (sv >= P61) sv -= P61;
+  row[hv % (uint64_t)k] = (sv & 1) ? -1.0 : 1.0;
 }
 
 struct StatPartial {
@@ -342,13 +387,16 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
                                                       const int64_t* __restrict__ offsets, int n_series,
                                                       const double* __restrict__ coef, const double* __restrict__ St,
                                                       int k, double* __restrict__ R, int64_t ldr, int mode,
-                                                      int64_t tiles_per_block) {
+                                                      int64_t tiles_per_block, double* __restrict__ dpart) {
   extern __shared__ double part[];  // (SL - 1) x KB x V x 64
   constexpr int TW = 64 * V;
   const int lane = threadIdx.x & 63;
   const int SL = blockDim.x >> 6;
   const int sl = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's slice of the dimensions
-  const int j0 = (int)(d * sl / SL), j1 = (int)(d * (sl + 1) / SL);
+  // the block's chunk of the dimensions (gridDim.y chunks; one unless d is
+  // large against the number of column tiles), split among its SL waves
+  const int64_t D0 = d * blockIdx.y / gridDim.y, D1 = d * (blockIdx.y + 1) / gridDim.y;
+  const int j0 = (int)(D0 + (D1 - D0) * sl / SL), j1 = (int)(D0 + (D1 - D0) * (sl + 1) / SL);
   const int64_t n_tiles = (N + TW - 1) / TW;
   const int64_t tile0 = (int64_t)blockIdx.x * tiles_per_block;
   const int64_t tile1 = min(tile0 + tiles_per_block, n_tiles);
@@ -394,16 +442,35 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
 #pragma unroll
           for (int v = 0; v < V; ++v) {
             if (t + v < N) {
-              double* dst = R + (int64_t)g * ldr + t + v;
-              if (mode == 0) *dst = acc[g][v];
-              else if (mode > 0) *dst += acc[g][v];
-              else *dst -= acc[g][v];
+              if (gridDim.y > 1) {  // one chunk's partial sum; project_sum adds the chunks
+                dpart[((int64_t)blockIdx.y * KB + g) * N + t + v] = acc[g][v];
+              } else {
+                double* dst = R + (int64_t)g * ldr + t + v;
+                if (mode == 0) *dst = acc[g][v];
+                else if (mode > 0) *dst += acc[g][v];
+                else *dst -= acc[g][v];
+              }
             }
           }
         }
       }
     }
   }
+}
+
+// R[g][t] (=, +=, -=) the sum of the chunks' partial sums, in chunk order.
+__global__ void project_sum(const double* __restrict__ dpart, int n_chunks, int kb, int k, int64_t N,
+                            double* __restrict__ R, int64_t ldr, int mode) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)k * N) return;
+  const int g = (int)(i / N);
+  const int64_t t = i - (int64_t)g * N;
+  double acc = 0.0;
+  for (int c = 0; c < n_chunks; ++c) acc += dpart[((int64_t)c * kb + g) * N + t];
+  double* dst = R + (int64_t)g * ldr + t;
+  if (mode == 0) *dst = acc;
+  else if (mode > 0) *dst += acc;
+  else *dst -= acc;
 }
 
 __global__ void prep_coef(const double* __restrict__ stats, int64_t pairs, double* __restrict__ coef) {
@@ -435,57 +502,90 @@ static int proj_vec(int kb, const void* T, int64_t ldt) {
   return v;
 }
 
+// Waves per block (slices of the dimensions) while the column tiles alone leave
+// the chip under-filled (4096 waves): each slice at least PROJ_PF rows, the
+// partial sums within the LDS budget.
+static int proj_slices(int64_t n_tiles, int64_t d, int kb, int v) {
+  int SL = 1;
+  while (SL < 4 && n_tiles * SL < 4096 && d >= 2 * SL * PROJ_PF &&
+         (size_t)(2 * SL - 1) * kb * v * 64 * sizeof(double) <= PROJ_LDS_BYTES)
+    SL *= 2;
+  return SL;
+}
+
+// Chunks of the dimensions across blocks when tiles x slices still leave the
+// chip under-filled and there are many dimensions (each chunk >= 32 rows per slice).
+static int64_t proj_chunks(int64_t n_tiles, int SL, int64_t d) {
+  if (n_tiles * SL >= 4096 || d < 2 * SL * 64) return 1;
+  const int64_t c = (4096 + n_tiles * SL - 1) / (n_tiles * SL);
+  return std::max<int64_t>(1, std::min<int64_t>(c, d / (SL * 32)));
+}
+
+// Workspace doubles for the chunks' partial sums (the most any column-group width needs).
+static size_t proj_part_elems(int64_t d, int64_t N, int k) {
+  const int kb = proj_kb(k);
+  size_t best = 0;
+  for (int v : {1, 2, 4}) {
+    if ((kb > 16 && v > 1) || (kb == 16 && v > 2)) continue;  // widths proj_vec never picks for this kb
+    const int64_t n_tiles = (N + 64 * v - 1) / (64 * v);
+    const int64_t nc = proj_chunks(n_tiles, proj_slices(n_tiles, d, kb, v), d);
+    if (nc > 1) best = std::max(best, (size_t)nc * kb * (size_t)N);
+  }
+  return best;
+}
+
 template <typename TIn, int KB, int V>
 static void launch_project_v(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                              const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
-                             hipStream_t st) {
+                             double* dpart, size_t dpart_elems, hipStream_t st) {
   constexpr int TW = 64 * V;
   const int64_t n_tiles = (N + TW - 1) / TW;
-  // slices of the dimensions while the tiles alone leave the chip under-filled
-  // (4096 waves), each slice at least PROJ_PF rows, partial sums within the LDS budget
-  int SL = 1;
-  while (SL < 4 && n_tiles * SL < 4096 && d >= 2 * SL * PROJ_PF &&
-         (size_t)(2 * SL - 1) * KB * V * 64 * sizeof(double) <= PROJ_LDS_BYTES)
-    SL *= 2;
+  const int SL = proj_slices(n_tiles, d, KB, V);
+  int64_t nc = proj_chunks(n_tiles, SL, d);
+  nc = std::min<int64_t>(nc, dpart ? (int64_t)(dpart_elems / ((size_t)KB * (size_t)N)) : 1);
+  nc = std::max<int64_t>(nc, 1);
   // at most two blocks per resident slot (8192 waves); more tiles go to each block
-  const int64_t max_blocks = std::max<int64_t>(1, 16384 / SL);
+  const int64_t max_blocks = std::max<int64_t>(1, 16384 / (SL * nc));
   const int64_t tpb = (n_tiles + max_blocks - 1) / max_blocks;
   const int64_t blocks = (n_tiles + tpb - 1) / tpb;
   const size_t lds = (size_t)(SL - 1) * KB * V * 64 * sizeof(double);
-  hipLaunchKernelGGL((project_kernel<TIn, KB, V>), dim3((unsigned)blocks), dim3(64 * SL), lds, st, T, ldt, d, N,
-                     offsets, n_series, coef, St, k, R, ldr, mode, tpb);
+  hipLaunchKernelGGL((project_kernel<TIn, KB, V>), dim3((unsigned)blocks, (unsigned)nc), dim3(64 * SL), lds, st, T,
+                     ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, tpb, dpart);
+  if (nc > 1)
+    hipLaunchKernelGGL(project_sum, dim3((unsigned)(((int64_t)k * N + 255) / 256)), dim3(256), 0, st, dpart, (int)nc,
+                       KB, k, N, R, ldr, mode);
 }
 
 template <typename TIn, int KB>
 static void launch_project_kb(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                               const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
-                              hipStream_t st) {
+                              double* dpart, size_t dpart_elems, hipStream_t st) {
   const int v = proj_vec<TIn>(KB, T, ldt);
   constexpr int VMAX = sizeof(TIn) == 8 ? (KB <= 16 ? 2 : 1) : (KB <= 8 ? 4 : KB <= 16 ? 2 : 1);
   if constexpr (VMAX >= 4) {
-    if (v == 4) return launch_project_v<TIn, KB, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    if (v == 4) return launch_project_v<TIn, KB, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
   }
   if constexpr (VMAX >= 2) {
-    if (v == 2) return launch_project_v<TIn, KB, 2>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    if (v == 2) return launch_project_v<TIn, KB, 2>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
   }
-  launch_project_v<TIn, KB, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+  launch_project_v<TIn, KB, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
 }
 
 // coef: workspace of n_series * d * 2 doubles; St: transpose_coeffs(S) on the device
 template <typename TIn>
 static void launch_project(const void* Tv, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                            const double* stats, double* coef, const double* St, int k, double* R, int64_t ldr,
-                           int mode, hipStream_t st) {
+                           int mode, double* dpart, size_t dpart_elems, hipStream_t st) {
   const int64_t pairs = (int64_t)n_series * d;
   hipLaunchKernelGGL(prep_coef, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, stats, pairs, coef);
   const TIn* T = static_cast<const TIn*>(Tv);
   switch (proj_kb(k)) {
-    case 1: return launch_project_kb<TIn, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
-    case 4: return launch_project_kb<TIn, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
-    case 8: return launch_project_kb<TIn, 8>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
-    case 16: return launch_project_kb<TIn, 16>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
-    case 32: return launch_project_kb<TIn, 32>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
-    default: return launch_project_kb<TIn, 64>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, st);
+    case 1: return launch_project_kb<TIn, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    case 4: return launch_project_kb<TIn, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    case 8: return launch_project_kb<TIn, 8>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    case 16: return launch_project_kb<TIn, 16>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    case 32: return launch_project_kb<TIn, 32>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    default: return launch_project_kb<TIn, 64>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
   }
 }
 
@@ -603,7 +703,9 @@ extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int6
   tb.put<int64_t>(nullptr, n_series + 1);
   tb.put<int64_t>(nullptr, n_series + 1);
   tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)d);
+  cv.take<int64_t>((size_t)d);  // dimension ids when the coefficients are drawn on the device
   cv.take<double>((size_t)n_series * (size_t)d * 2);
+  cv.take<double>(proj_part_elems(d, offsets[n_series], k));
   stats_workspace(d, cpre[n_series], cv, nullptr);
   return cv.used + 256;
 }
@@ -623,18 +725,32 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   const int64_t N = offsets[n_series];
   SKMP_REQUIRE(ldt >= N && ldr >= N, "row strides must be >= the total number of samples");
   SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
-  std::vector<double> S((size_t)k * (size_t)d);
-  int rc = launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S.data());
-  if (rc) return rc;
+  // count and sum coefficients are drawn on the device (integer hashing only);
+  // Gaussian ones on the host (glibc libm), shipped as a table
+  const bool device_coeffs = (kind == SKMP_COUNT || kind == SKMP_SUM);
+  SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
+  SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
+  int rc = SKMP_OK;
+  std::vector<double> St;
+  if (device_coeffs) {
+    if ((rc = check_ids(dim_ids, d))) return rc;
+  } else {
+    std::vector<double> S((size_t)k * (size_t)d);
+    if ((rc = launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S.data()))) return rc;
+    St = transpose_coeffs(S, k, d);
+  }
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);
   Carve cv(workspace, ws_bytes);
   TableBlob tb(cv);
   StatsBuffers sb;
   sb.offsets_dev = tb.put(offsets, n_series + 1);
   sb.cprefix_dev = tb.put(cpre.data(), n_series + 1);
-  const std::vector<double> St = transpose_coeffs(S, k, d);
-  double* S_dev = tb.put(St.data(), St.size());
+  const int kb = proj_kb(k);
+  double* S_dev = device_coeffs ? cv.take<double>((size_t)kb * (size_t)d) : tb.put(St.data(), St.size());
+  const int64_t* ids_dev = (device_coeffs && dim_ids) ? tb.put(dim_ids, (size_t)d) : nullptr;
   double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
+  const size_t dpart_elems = proj_part_elems(d, N, k);
+  double* dpart = cv.take<double>(dpart_elems);
   stats_workspace(d, cpre[n_series], cv, &sb);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
@@ -643,12 +759,20 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (int rc2 = tb.upload(st)) return rc2;
   StageTimer tm(SKMP_TIMER_SKETCH, st);
+  if (device_coeffs) {
+    uint64_t a = 0, b = 0, a2 = 0, b2 = 0;
+    count_params(seed, &a, &b, &a2, &b2);
+    hipLaunchKernelGGL(count_coeffs_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, S_dev, d, kb, k,
+                       kind, ids_dev, a, b, a2, b2);
+  }
   rc = run_dimstats(T, dtype, ldt, d, n_series, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
   if (dtype == SKMP_F64)
-    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, st);
+    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, dpart,
+                           dpart_elems, st);
   else
-    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, st);
+    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, dpart,
+                          dpart_elems, st);
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }
@@ -664,6 +788,7 @@ extern "C" size_t sketch_update_workspace(int64_t n, int64_t d_add, int64_t d_re
   tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)std::max<int64_t>(d_add, 1));
   tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)std::max<int64_t>(d_rem, 1));
   cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
+  cv.take<double>(proj_part_elems(std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1), n, k));
   stats_workspace(std::max<int64_t>(d_add, 1), cpre[1], cv, nullptr);
   return cv.used + 256;
 }
@@ -715,6 +840,8 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
   double* Sa_dev = tb.put(Sat.data(), Sat.size());
   double* Sr_dev = tb.put(Srt.data(), Srt.size());
   double* coef = cv.take<double>((size_t)std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1) * 2);
+  const size_t dpart_elems = proj_part_elems(std::max<int64_t>(std::max<int64_t>(d_add, d_rem), 1), n, k);
+  double* dpart = cv.take<double>(dpart_elems);
   stats_workspace(std::max<int64_t>(d_add, 1), cpre[1], cv, &sb);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
@@ -727,18 +854,22 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
     rc = run_dimstats(T_add, dtype, ldt, d_add, 1, cpre, sb, add_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
     if (rc) return rc;
     if (dtype == SKMP_F64)
-      launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1, st);
+      launch_project<double>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1,
+                             dpart, dpart_elems, st);
     else
-      launch_project<float>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1, st);
+      launch_project<float>(T_add, ldt, d_add, n, sb.offsets_dev, 1, add_stats, coef, Sa_dev, k, R, ldr, +1,
+                            dpart, dpart_elems, st);
     for (int g = 0; g < k; ++g)
       for (int64_t j = 0; j < d_add; ++j)
         if (Sa[(size_t)g * d_add + j] != 0.0) mask |= 1ull << g;
   }
   if (d_rem) {
     if (dtype == SKMP_F64)
-      launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1, st);
+      launch_project<double>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1,
+                             dpart, dpart_elems, st);
     else
-      launch_project<float>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1, st);
+      launch_project<float>(T_rem, ldt, d_rem, n, sb.offsets_dev, 1, rem_stats, coef, Sr_dev, k, R, ldr, -1,
+                            dpart, dpart_elems, st);
     for (int g = 0; g < k; ++g)
       for (int64_t j = 0; j < d_rem; ++j)
         if (Sr[(size_t)g * d_rem + j] != 0.0) mask |= 1ull << g;

@@ -87,6 +87,8 @@ PROJ_CASES = [
     ("f64", 17, [1000, 23], 40, 0),            # 32 padded groups
     ("f64", 33, [515], 70, 0),                 # 64 padded groups
     ("f64", 1, [3000], 5, 1),                  # k = 1, unaligned rows
+    ("f64", 64, [2000], 3000, 0),              # many dimensions: chunks of them across blocks
+    ("f32", 20, [900, 1100], 2600, 0),         # the same with FP32 input and two series
 ]
 
 
@@ -113,6 +115,38 @@ def test_sketch_projection_layouts(dev, case):
         scale = max(1.0, float(np.max(np.abs(R_o))))
         assert np.max(np.abs(R[:, a:b] - R_o)) <= 1e-12 * scale, (case, s)
         assert np.allclose(stats[s, :, 1], sd_o, rtol=1e-12, atol=0)
+
+
+def test_count_sketch_many_dimensions(dev):
+    """d = 4000 dimensions of 3000 samples, count sketch k = 64: coefficients drawn on
+    the device, the dimensions split into chunks across blocks."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, n, k = 4000, 3000, 64
+    T = np.random.default_rng(5).standard_normal((d, n)).cumsum(axis=1)
+    R, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, "count", 77)
+    torch.cuda.synchronize()
+    R_o, _, _, _ = O.build(T, "count", k, 77)
+    assert np.max(np.abs(R.cpu().numpy() - R_o)) <= 1e-12 * np.max(np.abs(R_o))
+
+
+@pytest.mark.parametrize("kind,k", [("count", 7), ("count", 64), ("sum", 1)])
+def test_device_drawn_coefficients_large_ids(dev, kind, k):
+    """Count and sum coefficients are drawn on the device: large dimension ids
+    (up to 2^61 - 2) hash exactly as in the oracle."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, n = 40, 700
+    ids = np.array([0, 1, 2 ** 61 - 2, 2 ** 40 + 3, 999999937] + list(range(1000, 1000 + d - 5)), dtype=np.int64)
+    T = datagen.tiny_series(83, d, n)
+    R, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, kind, 2024, dim_ids=ids)
+    torch.cuda.synchronize()
+    R_o, _, _, _ = O.build(T, kind, k, 2024, ids)
+    assert np.max(np.abs(R.cpu().numpy() - R_o)) <= 1e-12 * max(1.0, np.max(np.abs(R_o)))
+    R2, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, kind, 2024)   # ids 0 .. d - 1
+    torch.cuda.synchronize()
+    R2_o, _, _, _ = O.build(T, kind, k, 2024, np.arange(d))
+    assert np.max(np.abs(R2.cpu().numpy() - R2_o)) <= 1e-12 * max(1.0, np.max(np.abs(R2_o)))
 
 
 @pytest.mark.parametrize("n", [4096, 4097])
