@@ -19,7 +19,13 @@ over the K timed steps; ``paths`` repeats the measurement for the FP64 path
 (and any other precision asked for) on the same input, with each path's error
 against the FP64 path.  ``roofline`` covers the named path's tile kernel,
 timed with HIP events on the library's stream; ``cpu_baseline`` times the CPU
-oracle on a bounded sample of rows.
+oracle on a bounded sample of rows; ``dim_detect`` times the dimension
+detection (Algorithm 3) of the named path's top discord.
+
+Other modes (not the headline): ``--join ab`` measures the AB-join of a
+single-series workload's second half against its first half;
+``--experiment random-walks`` runs the random-walk experiment of Section IV-A
+(sketched vs exact discord: success rate and speedup per d).
 """
 from __future__ import annotations
 
