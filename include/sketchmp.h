@@ -74,7 +74,7 @@ extern "C" {
 #define SKMP_FP16X3 3 /* Hankel tiles on MFMA, FP16 hi+lo split products, FP32 accumulation */
 /* Every precision reports the exact FP64 distance of the neighbour it finds. */
 
-/* flags for sketch_build / sketch_update_dims */
+/* flags for sketch_build / sketch_update_dims / sketch_append */
 #define SKMP_FLAG_CHECK_FINITE 1u /* synchronise and reject NaN/Inf input */
 
 /* Message describing the last failure on this thread ("" if none). */
@@ -262,6 +262,101 @@ int dim_detect(const void* T_train, int64_t ld_train, int64_t n_train, const dou
                int64_t ld_test, int64_t n_test, const double* stats_test, int32_t dtype, int64_t d,
                const int64_t* dims, int32_t n_dims, int64_t i_star, int32_t m, int32_t excl, double* scores,
                int64_t* nn, int32_t* best, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------- streaming
+ * The streaming extension of Section III-B: the projection of Algorithm 1 is
+ * run only on newly arrived samples and the self-join is updated, not redone;
+ * and the point update of Section III-C.  A stream keeps, per series, a
+ * sketch buffer R and profile buffers P, I with room to grow (columns
+ * [start, start + capacity) of row strides ldr / ldp), and the per-dimension
+ * statistics (mu, sigma) its sketch was built with: they stay frozen, so a
+ * sample's sketched value never changes once written. */
+
+/* Workspace bytes needed by sketch_append (new_offsets host, as in sketch_append). */
+size_t sketch_append_workspace(int64_t d, int64_t n_series, const int64_t* new_offsets, int32_t k);
+
+/*
+ * Sketch newly arrived samples (Algorithm 1's projection, Section III-B's
+ * streaming extension) with frozen statistics:
+ *   R[g][dst_cols[s] + t] = sum_j S[g][j] (T_new[j][new_offsets[s] + t] - mu_sj) / sigma_sj
+ * for t < new_offsets[s+1] - new_offsets[s]; sigma_sj = 0 contributes 0.
+ *   T_new    device, d x N_new (N_new = new_offsets[n_series]), row stride
+ *            ldt >= N_new, dtype SKMP_F64 or SKMP_F32: the new samples of every
+ *            series, back to back.
+ *   new_offsets host, n_series + 1, non-decreasing from 0 (a series may have
+ *            no new samples).
+ *   dst_cols host, n_series: the column of R that receives series s's first
+ *            new sample (for a stream, start_s + samples already sketched);
+ *            ascending and disjoint, dst_cols[s] + count_s <= ldr.
+ *   dim_ids, k, kind, seed  as given to sketch_build.
+ *   dim_stats device, n_series x d x 2 doubles: the (mu, sigma) the series'
+ *            sketch was built with (sketch_build's dim_stats).
+ *   flags    SKMP_FLAG_CHECK_FINITE rejects NaN/Inf among the new samples.
+ * Only the new columns of R are written.  Asynchronous on `stream`.
+ */
+int sketch_append(const void* T_new, int32_t dtype, int64_t d, int64_t ldt, int64_t n_series,
+                  const int64_t* new_offsets, const int64_t* dst_cols, const int64_t* dim_ids, int32_t k,
+                  int32_t kind, uint64_t seed, const double* dim_stats, uint32_t flags, double* R, int64_t ldr,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by sketch_point_update (0 for n_upd < 1). */
+size_t sketch_point_update_workspace(int64_t n_upd, int32_t k);
+
+/*
+ * Point updates of a sketch (Section III-C): raising sample `col` of
+ * dimension j of series s by delta raises R^(g) at that column by
+ * S[g][j] * delta / sigma_sj for every group g (nothing when sigma_sj = 0).
+ * Updates apply in the order given (several may hit one column).
+ *   R        device, k x n_cols, row stride ldr >= n_cols.
+ *   d, dim_ids  the sketch's dimensions (dim_ids host, NULL: 0..d-1).
+ *   dim_stats device, n_series x d x 2 (mu, sigma), as in sketch_append.
+ *   upd_series host, n_upd series indices (NULL: all 0); upd_dim host, rows
+ *            in [0, d); upd_col host, columns of R in [0, n_cols); upd_delta
+ *            host, finite changes of the raw samples.
+ *   changed_groups host out (may be NULL): bit g set iff some update has a
+ *            nonzero coefficient in group g; those groups' profiles must be
+ *            recomputed (mp_selfjoin with that group mask): the detection
+ *            itself is unchanged.
+ * Asynchronous on `stream`.
+ */
+int sketch_point_update(double* R, int64_t ldr, int64_t n_cols, int32_t k, int32_t kind, uint64_t seed, int64_t d,
+                        const int64_t* dim_ids, int64_t n_series, const double* dim_stats, int64_t n_upd,
+                        const int64_t* upd_series, const int64_t* upd_dim, const int64_t* upd_col,
+                        const double* upd_delta, uint64_t* changed_groups, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* Workspace bytes needed by mp_selfjoin_append (n_new host, n_series entries;
+ * 0 for a precision other than SKMP_FP64 / SKMP_FP32). */
+size_t mp_selfjoin_append_workspace(int64_t n_series, const int64_t* n_new, int32_t k, int32_t m, int32_t prec);
+
+/*
+ * Streaming self-join update (the streaming matrix profile of Section
+ * III-B's streaming extension).  Series s occupies columns
+ * [starts[s], starts[s] + n_new[s]) of R, P and I.  On entry P, I hold, for
+ * its first n_old[s] - m + 1 subsequences, the self-join profile of its first
+ * n_old[s] samples (from mp_selfjoin or an earlier append with the same m,
+ * excl and precision); on return they hold the profile of all n_new[s]
+ * samples, as mp_selfjoin of the whole series would.  Only pairs with a
+ * subsequence that ends in the new samples are computed: about
+ * (n_new - n_old + 64 C) (n_new - m + 1) distance cells per group, C = 6
+ * (FP64) or 8 (FP32) diagonals per lane for appends of fewer than 2048
+ * subsequences, the batch join's C above that.
+ *   starts   host, n_series: ascending, disjoint, starts[s] + n_new[s] <= ldr, ldp.
+ *   n_old, n_new host, n_series: 0 <= n_old <= n_new, n_new >= m; n_old < m
+ *            joins the series afresh; n_old = n_new leaves it untouched.
+ *   k, m, excl, refresh, group_mask  as in mp_selfjoin.
+ *   prec     SKMP_FP64 | SKMP_FP32; others give SKMP_EINVAL.
+ * A stored entry is replaced only by a strictly nearer new neighbour, or an
+ * equally near one with a smaller index.  The flat-subsequence threshold
+ * (1e-10 max|R^(g)|) is taken over the samples present at each call, so a
+ * subsequence whose sigma falls between two calls' thresholds keeps the
+ * status it had when its entry was last written.
+ * Asynchronous on `stream`.
+ */
+int mp_selfjoin_append(const double* R, int64_t ldr, int64_t n_series, const int64_t* starts, const int64_t* n_old,
+                       const int64_t* n_new, int32_t k, int32_t m, int32_t excl, int32_t prec, int32_t refresh,
+                       uint64_t group_mask, double* P, int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes,
+                       void* stream);
 
 /*
  * The process's tuning table as text, one line per shape class:

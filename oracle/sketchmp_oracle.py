@@ -385,3 +385,66 @@ def top_discords(P_groups: np.ndarray, m: int, top_k: int, halfwidth: int = 0) -
         lo, hi = max(0, i - h + 1), min(n_sub, i + h)
         alive[lo:hi] = False
     return out
+
+
+# ------------------------------------------------------------------ streaming
+def sketch_append(T_new: np.ndarray, S: np.ndarray, mu, sigma) -> np.ndarray:
+    """Section III-B's streaming extension: the projection of Algorithm 1
+    applied to newly arrived samples only.  Each dimension is normalised with
+    the (mu, sigma) the sketch was built with (frozen, so earlier sketched
+    values never change); sigma_j = 0 marks a constant dimension, which
+    contributes 0."""
+    T_new = np.asarray(T_new, dtype=np.float64)
+    Tb = np.zeros_like(T_new)
+    for j in range(T_new.shape[0]):
+        if sigma[j] > 0.0:
+            Tb[j] = (T_new[j] - mu[j]) / sigma[j]
+    return sketch(Tb, S)
+
+
+def point_update(R: np.ndarray, S: np.ndarray, sigma, updates) -> np.ndarray:
+    """Section III-C point update: when sample t of dimension j rises by
+    delta, R^(g)_t rises by S_gj times the change of the normalised sample,
+    delta / sigma_j (nothing for a constant dimension).  ``updates`` is a list
+    of (j, t, delta), applied in order."""
+    R = np.array(R, dtype=np.float64, copy=True)
+    for j, t, delta in updates:
+        if sigma[j] > 0.0:
+            for g in range(S.shape[0]):
+                if S[g, j] != 0.0:
+                    R[g, t] += S[g, j] * (delta / sigma[j])
+    return R
+
+
+def matrix_profile_streaming(r: np.ndarray, m: int, excl: int, n_start: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Self-join profile maintained while samples arrive (the streaming matrix
+    profile that Section III-B's streaming extension calls for): start from
+    the profile of r[:n_start] (Def. 6), then for each arriving sample the one
+    new subsequence j is compared (Def. 3, pair by pair) with every earlier
+    admissible subsequence i: P[j] is the smallest of those distances (first
+    index on ties), and P[i] takes d(i, j) when strictly smaller.  Ties keep
+    the earlier, smaller index, as the batch definition does.  Returns the
+    profile after the last sample; by construction it must equal
+    matrix_profile(r, m, excl)."""
+    r = np.asarray(r, dtype=np.float64)
+    n = r.size
+    n0 = max(n_start, m - 1)
+    if n0 >= m:
+        P, I = matrix_profile(r[:n0], m, excl)
+        P, I = list(P), list(I)
+    else:
+        P, I = [], []
+    for t in range(n0, n):
+        j = t - m + 1                     # the subsequence completed by sample t
+        pj, ij = math.inf, -1
+        for i in range(j):
+            if j - i < excl:
+                continue
+            dij = dist(r[i:i + m], r[j:j + m])
+            if dij < pj:
+                pj, ij = dij, i
+            if dij < P[i]:
+                P[i], I[i] = dij, j
+        P.append(pj)
+        I.append(ij)
+    return np.asarray(P, dtype=np.float64), np.asarray(I, dtype=np.int64)

@@ -12,6 +12,11 @@ Functions mirror the C-ABI in ``include/sketchmp.h``:
 * ``mp_selfjoin``         self-join matrix profile of each sketched series
 * ``top_discords``        Algorithm 2 plus the ordered discord list
 * ``sketch_coeffs``       the coefficient matrix S (host computation)
+* ``mp_abjoin``           AB-join between a test and a train series (Algorithm 2)
+* ``dim_detect``          discord dimension detection (Algorithm 3)
+* ``sketch_append``, ``sketch_point_update``, ``mp_selfjoin_append``
+                          the streaming extension (Section III-B) and point
+                          updates (Section III-C)
 """
 from __future__ import annotations
 
@@ -37,7 +42,8 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOT
 EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
             "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "dim_detect_workspace", "dim_detect",
-            "skmp_tuning_export",
+            "sketch_append_workspace", "sketch_append", "sketch_point_update_workspace", "sketch_point_update",
+            "mp_selfjoin_append_workspace", "mp_selfjoin_append", "skmp_tuning_export",
             "skmp_tuning_import", "skmp_tuning_clear",
             "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4, "dimdetect": 5}
@@ -87,6 +93,18 @@ def lib():
         L.dim_detect_workspace.restype = _sz
         L.dim_detect.argtypes = [_vp, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _i32, _i64, _i64p, _i32, _i64, _i32,
                                  _i32, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.sketch_append_workspace.argtypes = [_i64, _i64, _i64p, _i32]
+        L.sketch_append_workspace.restype = _sz
+        L.sketch_append.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64p, _i64p, _i64p, _i32, _i32, _u64, _vp, _u32,
+                                    _vp, _i64, _vp, _sz, _vp]
+        L.sketch_point_update_workspace.argtypes = [_i64, _i32]
+        L.sketch_point_update_workspace.restype = _sz
+        L.sketch_point_update.argtypes = [_vp, _i64, _i64, _i32, _i32, _u64, _i64, _i64p, _i64, _vp, _i64, _i64p,
+                                          _i64p, _i64p, _dp, _u64p, _vp, _sz, _vp]
+        L.mp_selfjoin_append_workspace.argtypes = [_i64, _i64p, _i32, _i32, _i32]
+        L.mp_selfjoin_append_workspace.restype = _sz
+        L.mp_selfjoin_append.argtypes = [_vp, _i64, _i64, _i64p, _i64p, _i64p, _i32, _i32, _i32, _i32, _i32, _u64,
+                                         _vp, _vp, _i64, _vp, _sz, _vp]
         L.top_discords_workspace.argtypes = [_i64, _i64p, _i32, _i32]
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
@@ -336,6 +354,79 @@ def dim_detect(T_train, stats_train, dims, i_star: int, m: int, T_test=None, sta
                             excl, scores.data_ptr(), nn.data_ptr(), best.data_ptr(), ws.data_ptr(), ws.numel(),
                             _stream(torch)))
     return scores, nn, best
+
+
+def sketch_append(T_new, new_offsets, dst_cols, R, stats, k: int, kind: str, seed: int, dim_ids=None,
+                  check_finite: bool = False):
+    """Sketch newly arrived samples into R with the frozen statistics the
+    sketch was built with (Algorithm 1's projection, Section III-B's streaming
+    extension).  T_new: d x N_new device tensor, the new samples of every
+    series back to back (new_offsets, n_series + 1); series s's go to columns
+    dst_cols[s], ... of R; stats: n_series x d x 2 (sketch_build's).  Returns R."""
+    torch = _torch()
+    assert T_new.is_cuda and T_new.dim() == 2 and T_new.stride(1) == 1
+    dtype = {torch.float64: F64, torch.float32: F32}[T_new.dtype]
+    d = int(T_new.shape[0])
+    offs = _i64arr(new_offsets)
+    dst = _i64arr(dst_cols)
+    n_series = offs.size - 1
+    assert dst.size == n_series
+    ids = None if dim_ids is None else _i64arr(dim_ids)
+    ws = _workspace(torch, lib().sketch_append_workspace(d, n_series, _ptr64(offs), k), R.device)
+    _check(lib().sketch_append(T_new.data_ptr(), dtype, d, _ld(T_new), n_series, _ptr64(offs), _ptr64(dst),
+                               None if ids is None else _ptr64(ids), k, KINDS[kind], seed, stats.data_ptr(),
+                               FLAG_CHECK_FINITE if check_finite else 0, R.data_ptr(), _ld(R), ws.data_ptr(),
+                               ws.numel(), _stream(torch)))
+    return R
+
+
+def sketch_point_update(R, stats, k: int, kind: str, seed: int, dims, cols, deltas, series=None, dim_ids=None,
+                        n_cols: Optional[int] = None) -> int:
+    """Point updates (Section III-C): sample cols[u] of dimension dims[u] (of
+    series series[u]) rose by deltas[u]; R changes in place.  stats: n_series x
+    d x 2.  Returns the mask of the groups that changed."""
+    torch = _torch()
+    st = stats.reshape(-1, stats.shape[-2], 2) if stats.dim() == 3 else stats.reshape(1, -1, 2)
+    n_series, d = int(st.shape[0]), int(st.shape[1])
+    dims_a, cols_a = _i64arr(dims), _i64arr(cols)
+    deltas_a = np.ascontiguousarray(np.asarray(deltas, dtype=np.float64))
+    ser = None if series is None else _i64arr(series)
+    ids = None if dim_ids is None else _i64arr(dim_ids)
+    n_upd = int(dims_a.size)
+    assert cols_a.size == n_upd and deltas_a.size == n_upd and (ser is None or ser.size == n_upd)
+    nc = int(R.shape[1]) if n_cols is None else int(n_cols)
+    mask = ctypes.c_uint64(0)
+    ws = _workspace(torch, max(lib().sketch_point_update_workspace(n_upd, k), 256), R.device)
+    _check(lib().sketch_point_update(R.data_ptr(), _ld(R), nc, k, KINDS[kind], seed, d,
+                                     None if ids is None else _ptr64(ids), n_series, st.data_ptr(), n_upd,
+                                     None if ser is None else _ptr64(ser), _ptr64(dims_a), _ptr64(cols_a),
+                                     deltas_a.ctypes.data_as(_dp), ctypes.byref(mask), ws.data_ptr(), ws.numel(),
+                                     _stream(torch)))
+    return int(mask.value)
+
+
+def mp_selfjoin_append_workspace(n_new, k: int, m: int, prec: str = "fp64") -> int:
+    nn = _i64arr(n_new)
+    return int(lib().mp_selfjoin_append_workspace(nn.size, _ptr64(nn), k, m, PRECISIONS[prec]))
+
+
+def mp_selfjoin_append(R, P, I, starts, n_old, n_new, k: int, m: int, excl: int, prec: str = "fp64",
+                       refresh: int = 0, group_mask: Optional[int] = None, workspace=None):
+    """Streaming self-join update: series s (columns starts[s] ... of R, P, I)
+    grew from n_old[s] to n_new[s] samples; P, I, holding the profile of the
+    first n_old[s] samples, are updated in place to that of all n_new[s]."""
+    torch = _torch()
+    st, no, nn = _i64arr(starts), _i64arr(n_old), _i64arr(n_new)
+    n_series = st.size
+    assert no.size == n_series and nn.size == n_series and _ld(P) == _ld(I)
+    if workspace is None:
+        workspace = _workspace(torch, lib().mp_selfjoin_append_workspace(n_series, _ptr64(nn), k, m,
+                                                                         PRECISIONS[prec]), R.device)
+    mask = (1 << 64) - 1 if group_mask is None else int(group_mask)
+    _check(lib().mp_selfjoin_append(R.data_ptr(), _ld(R), n_series, _ptr64(st), _ptr64(no), _ptr64(nn), k, m, excl,
+                                    PRECISIONS[prec], refresh, mask, P.data_ptr(), I.data_ptr(), _ld(P),
+                                    workspace.data_ptr(), workspace.numel(), _stream(torch)))
+    return P, I
 
 
 def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp64", refresh: int = 0,

@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
     // last lane has passed the last row of its longest diagonal (in a self-join
     // that is the first diagonal's n_sub - db rows; rows past n_sub are padding)
     const int Ub = min(n_sub + 63, n_cols - db);
-    const int u_begin = sigma * st.strip;
+    const int u_begin = max(0, sp.c0 - db) + sigma * st.strip;
     if (u_begin >= Ub) continue;
     const int u_end = min(u_begin + st.strip, Ub);
 
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     // last lane has passed the last row of its longest diagonal (in a self-join
     // that is the first diagonal's n_sub - db rows; rows past n_sub are padding)
     const int Ub = min(n_sub + 63, n_cols - db);
-    const int u_begin = sigma * st.strip;
+    const int u_begin = max(0, sp.c0 - db) + sigma * st.strip;
     if (u_begin >= Ub) continue;
     const int u_end = min(u_begin + st.strip, Ub);
     const int64_t gbase = (int64_t)gi * st.gstride + sp.stat_base;    // rows
@@ -867,8 +867,19 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
       arg = jf;
     }
   }
-  sp.p0[(int64_t)g * sp.ldp + x] = best;
-  sp.i0[(int64_t)g * sp.ldp + x] = arg;
+  double* pdst = sp.p0 + (int64_t)g * sp.ldp + x;
+  int64_t* idst = sp.i0 + (int64_t)g * sp.ldp + x;
+  if (x < sp.keep) {
+    // an append: the stored entry covers every partner before the new
+    // samples; the new candidate replaces it only if strictly nearer, or
+    // equally near with a smaller index (flat windows: the smallest flat
+    // partner, as in a join of the whole series)
+    const double pold = *pdst;
+    const int64_t iold = *idst;
+    if (!(best < pold || (best == pold && arg >= 0 && (iold < 0 || arg < iold)))) return;
+  }
+  *pdst = best;
+  *idst = arg;
 }
 
 // ------------------------------------------------------------------ host
@@ -885,8 +896,15 @@ struct PlanInfo {
 // ab = true: the two series of an AB-join (0 = A, 1 = B): A's units cover the
 // diagonals j - i >= 0 of A x B, B's units the diagonals >= 1 of B x A, so
 // every pair is met once and there is no trivial-match zone.
+// keep (diagonal kernels only; NULL: none): per series, the windows whose
+// profile entries already cover every partner below that index (an append).
+// Only pairs with a column at or after keep are new; a band reaches such a
+// column first at step keep - db - 64 (C - 1) (lane t, diagonal q of the band
+// at step u is on column u + db + t (C - 1) + q), so its walk starts there
+// and the few older cells it passes again are merged harmlessly.  A series
+// with keep = its window count has nothing new: no units, no merge.
 static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_t excl, int kact, int C, int strip,
-                     PlanInfo& pl, bool validate, bool ab = false) {
+                     PlanInfo& pl, bool validate, bool ab = false, const int64_t* keep = nullptr) {
   const int cs = C > 0 ? C - 1 : 7;  // de-interleave stride of the column statistics
   pl.sp.assign(n_series, SeriesPlan{});
   int64_t stat = 0, chunk = 0, blk = 0, max_nsub = 1;
@@ -910,6 +928,8 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     p.cs = ab ? (int32_t)(1 - s) : (int32_t)s;
     p.d0 = ab ? (int32_t)s : excl;
     p.pexcl = ab ? 0 : excl;
+    p.keep = (keep && C > 0) ? std::min<int64_t>(std::max<int64_t>(keep[s], 0), p.n - m + 1) : 0;
+    p.c0 = p.keep > 0 ? (int32_t)std::max<int64_t>(p.keep - 64 * (int64_t)(C - 1), 0) : 0;
   }
   int64_t unit = 0;
   for (int64_t s = 0; s < n_series; ++s) {
@@ -922,9 +942,11 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
     const int64_t nd = p.n_cols - p.d0;  // diagonals with pairs
     if (C > 0) {
       const int64_t D = 64 * (int64_t)C;
-      const int64_t rows = std::min<int64_t>(p.n_sub + 63, p.n_cols - p.d0);  // steps of the first band
-      p.nb = nd > 0 ? (int32_t)((nd + D - 1) / D) : 0;
-      p.ns = nd > 0 ? (int32_t)((rows + strip - 1) / strip) : 0;
+      // steps of the first band (no later band walks more)
+      const int64_t rows = std::min<int64_t>(p.n_sub + 63, p.n_cols - p.d0) - std::max<int64_t>(p.c0 - p.d0, 0);
+      const bool fresh = p.keep < p.n - m + 1;  // false: an append with no new window
+      p.nb = (nd > 0 && fresh && rows > 0) ? (int32_t)((nd + D - 1) / D) : 0;
+      p.ns = (nd > 0 && fresh && rows > 0) ? (int32_t)((rows + strip - 1) / strip) : 0;
     } else {
       const int64_t jt_last = (p.n_sub - 1) / MFMA_TILE;
       const int64_t nt0 = jt_last - (int64_t)excl / MFMA_TILE + 1;  // tiles of row panel 0
@@ -1051,6 +1073,9 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 constexpr int kDefaultFp64Variant = 0;
 constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (spills 12 VGPRs outside the inner loop; fastest measured)
 static const int kTuneStrips[] = {1024, 2048, 4096};
+// The narrowest bands (C = 6 in FP64, C = 8 in FP32), for short appends.
+constexpr int kNarrowFp64Variant = 5;
+constexpr int kNarrowFp32Variant = 4;
 
 struct TuneKey {
   int prec, mlog, nlog;
@@ -1188,13 +1213,14 @@ struct JoinIO {
 
 // Everything after validation, with an explicit launch configuration: the
 // self-join of every series (ab = false) or the AB-join of series 0 and 1.
+// keep: as in make_plan (an append), NULL otherwise.
 static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const JoinIO* io, int32_t m, int32_t excl,
                     int32_t prec, const GroupList& gl, void* workspace, size_t ws_bytes, hipStream_t st,
-                    const Fp64Variant& var, int strip) {
+                    const Fp64Variant& var, int strip, const int64_t* keep = nullptr) {
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   const int kact = gl.count;
   PlanInfo pl;
-  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true, ab);
+  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true, ab, keep);
   if (rc) return rc;
   for (int64_t q = 0; q < n_series; ++q) {
     SeriesPlan& p = pl.sp[q];
@@ -1340,6 +1366,82 @@ extern "C" int mp_abjoin(const double* RA, int64_t lda, int64_t na, const double
   const JoinIO io[2] = {JoinIO{RA, lda, PA, IA, ldpa}, JoinIO{RB, ldb, PB, IB, ldpb}};
   return run_join(2, offs, true, io, m, 0, prec, gl, workspace, ws_bytes, static_cast<hipStream_t>(stream), vs[vidx],
                   strip);
+}
+
+// ------------------------------------------------------------- streaming append
+// Series s occupies columns [starts[s], starts[s] + n_new[s]) of R, P and I;
+// the join sees the compact layout offs (series back to back) and reads and
+// writes through per-series pointers.
+static int append_layout(int64_t n_series, const int64_t* starts, const int64_t* n_old, const int64_t* n_new,
+                         int32_t m, int64_t ldr, int64_t ldp, std::vector<int64_t>& offs, std::vector<int64_t>& keep,
+                         int64_t* max_new_windows) {
+  SKMP_REQUIRE(starts && n_old && n_new, "null pointer argument");
+  offs.assign((size_t)n_series + 1, 0);
+  keep.assign((size_t)n_series, 0);
+  int64_t most = 0;
+  for (int64_t s = 0; s < n_series; ++s) {
+    SKMP_REQUIRE(n_new[s] >= m, "every series needs n_new >= m samples");
+    SKMP_REQUIRE(n_old[s] >= 0 && n_old[s] <= n_new[s], "n_old must lie in [0, n_new]");
+    SKMP_REQUIRE(n_new[s] < (int64_t)INT_MAX - 2 * PADR, "series too long");
+    SKMP_REQUIRE(starts[s] >= 0 && starts[s] + n_new[s] <= ldr && starts[s] + n_new[s] <= ldp,
+                 "a series runs past the row stride");
+    SKMP_REQUIRE(s == 0 || starts[s] >= starts[s - 1] + n_new[s - 1], "series must be ascending and disjoint");
+    offs[s + 1] = offs[s] + n_new[s];
+    keep[s] = n_old[s] >= m ? n_old[s] - m + 1 : 0;
+    most = std::max<int64_t>(most, (n_new[s] - m + 1) - keep[s]);
+  }
+  *max_new_windows = most;
+  return SKMP_OK;
+}
+
+// Appends of fewer new windows than this walk the narrowest compiled bands:
+// a band passes 64 (C - 1) old steps before its last lane reaches a new column.
+constexpr int64_t kAppendNarrowBelow = 2048;
+
+extern "C" size_t mp_selfjoin_append_workspace(int64_t n_series, const int64_t* n_new, int32_t k, int32_t m,
+                                               int32_t prec) {
+  if (n_series < 1 || !n_new || (prec != SKMP_FP64 && prec != SKMP_FP32)) return 0;
+  std::vector<int64_t> offs((size_t)n_series + 1, 0);
+  for (int64_t s = 0; s < n_series; ++s) {
+    if (n_new[s] < 1) return 0;
+    offs[s + 1] = offs[s] + n_new[s];
+  }
+  return mp_selfjoin_workspace(n_series, offs.data(), k, m, prec);
+}
+
+extern "C" int mp_selfjoin_append(const double* R, int64_t ldr, int64_t n_series, const int64_t* starts,
+                                  const int64_t* n_old, const int64_t* n_new, int32_t k, int32_t m, int32_t excl,
+                                  int32_t prec, int32_t refresh, uint64_t group_mask, double* P, int64_t* I,
+                                  int64_t ldp, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(R && P && I, "null pointer argument");
+  SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(m >= 4 && m <= 2048, "m must lie in [4, 2048]");
+  SKMP_REQUIRE(excl >= 1, "excl must be >= 1 (a subsequence is its own trivial match)");
+  SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "appends run in FP64 or FP32 (with FP64 refresh)");
+  SKMP_REQUIRE(refresh == 0 || (refresh >= 64 && refresh <= (1 << 20)), "refresh must be 0 or in [64, 2^20]");
+  std::vector<int64_t> offs, keep;
+  int64_t most = 0;
+  if (int rc = append_layout(n_series, starts, n_old, n_new, m, ldr, ldp, offs, keep, &most)) return rc;
+  if (k < 64) group_mask &= (1ull << k) - 1;
+  GroupList gl;
+  if (active_groups(k, group_mask, gl) == 0 || most == 0) return SKMP_OK;
+  int vidx = 0, strip = DEFAULT_STRIP;
+  select_config(prec, refresh, tune_key(prec, m, n_series, offs.data()), &vidx, &strip);
+  int nv = 0;
+  const Fp64Variant* vs = variants_of(prec, &nv);
+  static const int env64 = env_int("SKMP_FP64_VARIANT", 0, kNumFp64Variants - 1);
+  static const int env32 = env_int("SKMP_FP32_VARIANT", 0, kNumFp32Variants - 1);
+  if (most < kAppendNarrowBelow && (prec == SKMP_FP32 ? env32 : env64) < 0)
+    vidx = (prec == SKMP_FP32) ? kNarrowFp32Variant : kNarrowFp64Variant;
+  std::vector<JoinIO> io((size_t)n_series);
+  for (int64_t q = 0; q < n_series; ++q) {
+    const bool fresh = n_new[q] > n_old[q];
+    io[q] = JoinIO{R + starts[q], ldr, fresh ? P + starts[q] : nullptr, I + starts[q], ldp};
+  }
+  return run_join(n_series, offs.data(), false, io.data(), m, excl, prec, gl, workspace, ws_bytes,
+                  static_cast<hipStream_t>(stream), vs[vidx], strip, keep.data());
 }
 
 extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets,

@@ -19,6 +19,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -387,7 +388,8 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
                                                       const int64_t* __restrict__ offsets, int n_series,
                                                       const double* __restrict__ coef, const double* __restrict__ St,
                                                       int k, double* __restrict__ R, int64_t ldr, int mode,
-                                                      int64_t tiles_per_block, double* __restrict__ dpart) {
+                                                      int64_t tiles_per_block, double* __restrict__ dpart,
+                                                      const int64_t* __restrict__ oshift) {
   extern __shared__ double part[];  // (SL - 1) x KB x V x 64
   constexpr int TW = 64 * V;
   const int lane = threadIdx.x & 63;
@@ -409,12 +411,13 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
       s_end = offsets[s + 1];
     }
     const int64_t t = c0 + (int64_t)lane * V;
+    const bool full = c0 + TW <= s_end;  // a full tile inside series s (s_end <= N)
     double acc[KB][V];
 #pragma unroll
     for (int g = 0; g < KB; ++g)
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[g][v] = 0.0;
-    if (c0 + TW <= s_end)  // a full tile inside series s (s_end <= N)
+    if (full)
       rows_uniform<TIn, KB, V>(T, ldt, j0, j1, t, coef + (int64_t)s * d * 2, St, acc);
     else
       rows_general<TIn, KB, V>(T, ldt, d, j0, j1, t, N, offsets, n_series, coef, St, acc);
@@ -436,6 +439,13 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
       __syncthreads();  // part is rewritten by the next tile
     }
     if (sl == 0) {
+      // output columns: t + v, moved by the series' shift when one is given
+      int64_t oc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        oc[v] = t + v;
+        if (oshift && t + v < N) oc[v] += full ? oshift[s] : oshift[series_of_lane(offsets, n_series, t + v)];
+      }
 #pragma unroll
       for (int g = 0; g < KB; ++g) {
         if (g < k) {
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
               if (gridDim.y > 1) {  // one chunk's partial sum; project_sum adds the chunks
                 dpart[((int64_t)blockIdx.y * KB + g) * N + t + v] = acc[g][v];
               } else {
-                double* dst = R + (int64_t)g * ldr + t + v;
+                double* dst = R + (int64_t)g * ldr + oc[v];
                 if (mode == 0) *dst = acc[g][v];
                 else if (mode > 0) *dst += acc[g][v];
                 else *dst -= acc[g][v];
@@ -460,14 +470,15 @@ __global__ __launch_bounds__(256) void project_kernel(const TIn* __restrict__ T,
 
 // R[g][t] (=, +=, -=) the sum of the chunks' partial sums, in chunk order.
 __global__ void project_sum(const double* __restrict__ dpart, int n_chunks, int kb, int k, int64_t N,
-                            double* __restrict__ R, int64_t ldr, int mode) {
+                            double* __restrict__ R, int64_t ldr, int mode, const int64_t* __restrict__ offsets,
+                            int n_series, const int64_t* __restrict__ oshift) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)k * N) return;
   const int g = (int)(i / N);
   const int64_t t = i - (int64_t)g * N;
   double acc = 0.0;
   for (int c = 0; c < n_chunks; ++c) acc += dpart[((int64_t)c * kb + g) * N + t];
-  double* dst = R + (int64_t)g * ldr + t;
+  double* dst = R + (int64_t)g * ldr + t + (oshift ? oshift[series_of_lane(offsets, n_series, t)] : 0);
   if (mode == 0) *dst = acc;
   else if (mode > 0) *dst += acc;
   else *dst -= acc;
@@ -537,7 +548,7 @@ static size_t proj_part_elems(int64_t d, int64_t N, int k) {
 template <typename TIn, int KB, int V>
 static void launch_project_v(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                              const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
-                             double* dpart, size_t dpart_elems, hipStream_t st) {
+                             double* dpart, size_t dpart_elems, const int64_t* oshift, hipStream_t st) {
   constexpr int TW = 64 * V;
   const int64_t n_tiles = (N + TW - 1) / TW;
   const int SL = proj_slices(n_tiles, d, KB, V);
@@ -550,42 +561,44 @@ static void launch_project_v(const TIn* T, int64_t ldt, int64_t d, int64_t N, co
   const int64_t blocks = (n_tiles + tpb - 1) / tpb;
   const size_t lds = (size_t)(SL - 1) * KB * V * 64 * sizeof(double);
   hipLaunchKernelGGL((project_kernel<TIn, KB, V>), dim3((unsigned)blocks, (unsigned)nc), dim3(64 * SL), lds, st, T,
-                     ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, tpb, dpart);
+                     ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, tpb, dpart, oshift);
   if (nc > 1)
     hipLaunchKernelGGL(project_sum, dim3((unsigned)(((int64_t)k * N + 255) / 256)), dim3(256), 0, st, dpart, (int)nc,
-                       KB, k, N, R, ldr, mode);
+                       KB, k, N, R, ldr, mode, offsets, n_series, oshift);
 }
 
 template <typename TIn, int KB>
 static void launch_project_kb(const TIn* T, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                               const double* coef, const double* St, int k, double* R, int64_t ldr, int mode,
-                              double* dpart, size_t dpart_elems, hipStream_t st) {
+                              double* dpart, size_t dpart_elems, const int64_t* oshift, hipStream_t st) {
   const int v = proj_vec<TIn>(KB, T, ldt);
   constexpr int VMAX = sizeof(TIn) == 8 ? (KB <= 16 ? 2 : 1) : (KB <= 8 ? 4 : KB <= 16 ? 2 : 1);
   if constexpr (VMAX >= 4) {
-    if (v == 4) return launch_project_v<TIn, KB, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    if (v == 4) return launch_project_v<TIn, KB, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
   }
   if constexpr (VMAX >= 2) {
-    if (v == 2) return launch_project_v<TIn, KB, 2>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    if (v == 2) return launch_project_v<TIn, KB, 2>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
   }
-  launch_project_v<TIn, KB, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+  launch_project_v<TIn, KB, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
 }
 
-// coef: workspace of n_series * d * 2 doubles; St: transpose_coeffs(S) on the device
+// coef: workspace of n_series * d * 2 doubles; St: transpose_coeffs(S) on the device;
+// oshift (device, n_series; NULL: none): column t of series s is written to R column t + oshift[s]
 template <typename TIn>
 static void launch_project(const void* Tv, int64_t ldt, int64_t d, int64_t N, const int64_t* offsets, int n_series,
                            const double* stats, double* coef, const double* St, int k, double* R, int64_t ldr,
-                           int mode, double* dpart, size_t dpart_elems, hipStream_t st) {
+                           int mode, double* dpart, size_t dpart_elems, hipStream_t st,
+                           const int64_t* oshift = nullptr) {
   const int64_t pairs = (int64_t)n_series * d;
   hipLaunchKernelGGL(prep_coef, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, stats, pairs, coef);
   const TIn* T = static_cast<const TIn*>(Tv);
   switch (proj_kb(k)) {
-    case 1: return launch_project_kb<TIn, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
-    case 4: return launch_project_kb<TIn, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
-    case 8: return launch_project_kb<TIn, 8>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
-    case 16: return launch_project_kb<TIn, 16>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
-    case 32: return launch_project_kb<TIn, 32>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
-    default: return launch_project_kb<TIn, 64>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, st);
+    case 1: return launch_project_kb<TIn, 1>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
+    case 4: return launch_project_kb<TIn, 4>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
+    case 8: return launch_project_kb<TIn, 8>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
+    case 16: return launch_project_kb<TIn, 16>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
+    case 32: return launch_project_kb<TIn, 32>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
+    default: return launch_project_kb<TIn, 64>(T, ldt, d, N, offsets, n_series, coef, St, k, R, ldr, mode, dpart, dpart_elems, oshift, st);
   }
 }
 
@@ -671,6 +684,37 @@ static int run_dimstats(const void* T, int32_t dtype, int64_t ldt, int64_t d, in
     }
   }
   return SKMP_OK;
+}
+
+// Point updates (Section III-C): raising sample t of dimension j of series s
+// by delta raises R^(g)_t by S_gj * delta / sigma_sj (sigma = 0: a constant
+// dimension, no change).  The host sorts the updates by column, keeping their
+// order within a column; thread (segment, g) applies one column's updates in
+// that order, so the result is that of applying them one by one.
+struct PointUpd {
+  int64_t col;    // column of R
+  int64_t stat;   // row of the (series, dimension) statistics table
+  double delta;   // change of the raw sample
+  int64_t crow;   // row of the coefficient table (k values)
+};
+
+__global__ void point_update_kernel(double* __restrict__ R, int64_t ldr, int k, int64_t n_seg,
+                                    const int64_t* __restrict__ seg, const PointUpd* __restrict__ upd,
+                                    const double* __restrict__ coef, const double* __restrict__ stats) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_seg * k) return;
+  const int64_t sgm = i / k;
+  const int g = (int)(i - sgm * k);
+  const int64_t u0 = seg[sgm], u1 = seg[sgm + 1];
+  double* dst = R + (int64_t)g * ldr + upd[u0].col;
+  double r = *dst;
+  for (int64_t u = u0; u < u1; ++u) {
+    const PointUpd p = upd[u];
+    const double sd = stats[2 * p.stat + 1];
+    const double c = coef[p.crow * k + g];
+    if (sd > 0.0 && c != 0.0) r += c * (p.delta / sd);
+  }
+  *dst = r;
 }
 
 static std::vector<int64_t> chunk_prefix(int64_t n_series, const int64_t* offsets) {
@@ -874,6 +918,189 @@ extern "C" int sketch_update_dims(double* R, int64_t ldr, int64_t n, int32_t k, 
       for (int64_t j = 0; j < d_rem; ++j)
         if (Sr[(size_t)g * d_rem + j] != 0.0) mask |= 1ull << g;
   }
+  SKMP_CHECK_HIP(hipGetLastError());
+  if (changed_groups) *changed_groups = mask;
+  return SKMP_OK;
+}
+
+// ------------------------------------------------------------- streaming
+extern "C" size_t sketch_append_workspace(int64_t d, int64_t n_series, const int64_t* new_offsets, int32_t k) {
+  if (d < 1 || n_series < 1 || !new_offsets || k < 1) return 0;
+  const int64_t N = new_offsets[n_series];
+  if (N < 0) return 0;
+  std::vector<int64_t> cpre = chunk_prefix(n_series, new_offsets);
+  Carve cv(nullptr, 0);
+  TableBlob tb(cv);
+  tb.put<int64_t>(nullptr, n_series + 1);
+  tb.put<int64_t>(nullptr, n_series + 1);
+  tb.put<int64_t>(nullptr, n_series);
+  tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)d);
+  cv.take<int64_t>((size_t)d);
+  cv.take<double>((size_t)n_series * (size_t)d * 2);  // coefficients of the normalisation
+  cv.take<double>((size_t)n_series * (size_t)d * 2);  // statistics of the finiteness check
+  cv.take<double>(proj_part_elems(d, std::max<int64_t>(N, 1), k));
+  stats_workspace(d, std::max<int64_t>(cpre[n_series], 1), cv, nullptr);
+  return cv.used + 256;
+}
+
+extern "C" int sketch_append(const void* T_new, int32_t dtype, int64_t d, int64_t ldt, int64_t n_series,
+                             const int64_t* new_offsets, const int64_t* dst_cols, const int64_t* dim_ids, int32_t k,
+                             int32_t kind, uint64_t seed, const double* dim_stats, uint32_t flags, double* R,
+                             int64_t ldr, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  SKMP_REQUIRE(T_new && R && dim_stats && new_offsets && dst_cols, "null pointer argument");
+  SKMP_REQUIRE(dtype == SKMP_F64 || dtype == SKMP_F32, "dtype must be SKMP_F64 or SKMP_F32");
+  SKMP_REQUIRE(d >= 1, "d must be >= 1");
+  SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
+  SKMP_REQUIRE(new_offsets[0] == 0, "new_offsets[0] must be 0");
+  for (int64_t s = 0; s < n_series; ++s)
+    SKMP_REQUIRE(new_offsets[s + 1] >= new_offsets[s], "new_offsets must be non-decreasing");
+  const int64_t N = new_offsets[n_series];
+  SKMP_REQUIRE(ldt >= N, "ldt must be >= the number of new samples");
+  for (int64_t s = 0; s < n_series; ++s) {
+    const int64_t cnt = new_offsets[s + 1] - new_offsets[s];
+    SKMP_REQUIRE(dst_cols[s] >= 0 && dst_cols[s] + cnt <= ldr, "a series' new columns run past ldr");
+    SKMP_REQUIRE(s == 0 || dst_cols[s] >= dst_cols[s - 1] + (new_offsets[s] - new_offsets[s - 1]),
+                 "destination columns must be ascending and disjoint");
+  }
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
+  SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
+  if (N == 0) return SKMP_OK;
+  const bool device_coeffs = (kind == SKMP_COUNT || kind == SKMP_SUM);
+  int rc = SKMP_OK;
+  std::vector<double> St;
+  if (device_coeffs) {
+    if ((rc = check_ids(dim_ids, d))) return rc;
+  } else {
+    std::vector<double> S((size_t)k * (size_t)d);
+    if ((rc = launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S.data()))) return rc;
+    St = transpose_coeffs(S, k, d);
+  }
+  std::vector<int64_t> cpre = chunk_prefix(n_series, new_offsets);
+  std::vector<int64_t> shift((size_t)n_series);
+  for (int64_t s = 0; s < n_series; ++s) shift[s] = dst_cols[s] - new_offsets[s];
+  Carve cv(workspace, ws_bytes);
+  TableBlob tb(cv);
+  StatsBuffers sb;
+  sb.offsets_dev = tb.put(new_offsets, n_series + 1);
+  sb.cprefix_dev = tb.put(cpre.data(), n_series + 1);
+  const int64_t* shift_dev = tb.put(shift.data(), (size_t)n_series);
+  const int kb = proj_kb(k);
+  double* S_dev = device_coeffs ? cv.take<double>((size_t)kb * (size_t)d) : tb.put(St.data(), St.size());
+  const int64_t* ids_dev = (device_coeffs && dim_ids) ? tb.put(dim_ids, (size_t)d) : nullptr;
+  double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
+  double* check_stats = cv.take<double>((size_t)n_series * (size_t)d * 2);
+  const size_t dpart_elems = proj_part_elems(d, N, k);
+  double* dpart = cv.take<double>(dpart_elems);
+  stats_workspace(d, std::max<int64_t>(cpre[n_series], 1), cv, &sb);
+  if (!workspace || !cv.fits()) {
+    set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
+    return SKMP_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc2 = tb.upload(st)) return rc2;
+  StageTimer tm(SKMP_TIMER_SKETCH, st);
+  if (device_coeffs) {
+    uint64_t a = 0, b = 0, a2 = 0, b2 = 0;
+    count_params(seed, &a, &b, &a2, &b2);
+    hipLaunchKernelGGL(count_coeffs_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, S_dev, d, kb, k,
+                       kind, ids_dev, a, b, a2, b2);
+  }
+  if (flags & SKMP_FLAG_CHECK_FINITE) {
+    // the statistics pass doubles as the finiteness check; its values are not used
+    rc = run_dimstats(T_new, dtype, ldt, d, n_series, cpre, sb, check_stats, true, st);
+    if (rc) return rc;
+  }
+  if (dtype == SKMP_F64)
+    launch_project<double>(T_new, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0,
+                           dpart, dpart_elems, st, shift_dev);
+  else
+    launch_project<float>(T_new, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0,
+                          dpart, dpart_elems, st, shift_dev);
+  SKMP_CHECK_HIP(hipGetLastError());
+  return SKMP_OK;
+}
+
+extern "C" size_t sketch_point_update_workspace(int64_t n_upd, int32_t k) {
+  if (n_upd < 1 || k < 1 || k > 64) return 0;
+  Carve cv(nullptr, 0);
+  TableBlob tb(cv);
+  tb.put<int64_t>(nullptr, (size_t)n_upd + 1);
+  tb.put<PointUpd>(nullptr, (size_t)n_upd);
+  tb.put<double>(nullptr, (size_t)n_upd * (size_t)k);
+  return cv.used + 256;
+}
+
+extern "C" int sketch_point_update(double* R, int64_t ldr, int64_t n_cols, int32_t k, int32_t kind, uint64_t seed,
+                                   int64_t d, const int64_t* dim_ids, int64_t n_series, const double* dim_stats,
+                                   int64_t n_upd, const int64_t* upd_series, const int64_t* upd_dim,
+                                   const int64_t* upd_col, const double* upd_delta, uint64_t* changed_groups,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (changed_groups) *changed_groups = 0;
+  SKMP_REQUIRE(R && dim_stats, "null pointer argument");
+  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
+  SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
+  SKMP_REQUIRE(d >= 1 && n_series >= 1, "d and n_series must be >= 1");
+  SKMP_REQUIRE(n_cols >= 1 && ldr >= n_cols, "bad column count or stride");
+  SKMP_REQUIRE(n_upd >= 0, "negative update count");
+  if (n_upd == 0) return SKMP_OK;
+  SKMP_REQUIRE(upd_dim && upd_col && upd_delta, "null update array");
+  if (int rc = check_ids(dim_ids, d)) return rc;
+  for (int64_t u = 0; u < n_upd; ++u) {
+    SKMP_REQUIRE(upd_dim[u] >= 0 && upd_dim[u] < d, "update dimension out of range");
+    SKMP_REQUIRE(upd_col[u] >= 0 && upd_col[u] < n_cols, "update column out of range");
+    SKMP_REQUIRE(!upd_series || (upd_series[u] >= 0 && upd_series[u] < n_series), "update series out of range");
+    SKMP_REQUIRE(std::isfinite(upd_delta[u]), "update deltas must be finite");
+  }
+  // coefficient rows of the dimensions the updates touch
+  std::vector<int64_t> dims(upd_dim, upd_dim + n_upd);
+  std::sort(dims.begin(), dims.end());
+  dims.erase(std::unique(dims.begin(), dims.end()), dims.end());
+  std::vector<int64_t> ids(dims.size());
+  for (size_t q = 0; q < dims.size(); ++q) ids[q] = dim_ids ? dim_ids[dims[q]] : dims[q];
+  const int64_t nd = (int64_t)dims.size();
+  std::vector<double> S((size_t)k * (size_t)nd);
+  if (int rc = launch_sketch_coeffs_host(kind, k, seed, ids.data(), nd, S.data())) return rc;
+  std::vector<double> coef((size_t)nd * (size_t)k);  // row q: the k coefficients of dims[q]
+  uint64_t mask = 0;
+  for (int64_t q = 0; q < nd; ++q)
+    for (int g = 0; g < k; ++g) {
+      coef[(size_t)q * k + g] = S[(size_t)g * nd + q];
+      if (S[(size_t)g * nd + q] != 0.0) mask |= 1ull << g;
+    }
+  // updates sorted by column, stable, and the column segments
+  std::vector<int64_t> order((size_t)n_upd);
+  for (int64_t u = 0; u < n_upd; ++u) order[u] = u;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return upd_col[a] < upd_col[b]; });
+  std::vector<PointUpd> upd((size_t)n_upd);
+  std::vector<int64_t> seg;
+  seg.reserve((size_t)n_upd + 1);
+  for (int64_t q = 0; q < n_upd; ++q) {
+    const int64_t u = order[q];
+    const int64_t s = upd_series ? upd_series[u] : 0;
+    const int64_t crow = std::lower_bound(dims.begin(), dims.end(), upd_dim[u]) - dims.begin();
+    upd[q] = PointUpd{upd_col[u], s * d + upd_dim[u], upd_delta[u], crow};
+    if (q == 0 || upd_col[u] != upd[q - 1].col) seg.push_back(q);
+  }
+  seg.push_back(n_upd);
+  const int64_t n_seg = (int64_t)seg.size() - 1;
+  Carve cv(workspace, ws_bytes);
+  TableBlob tb(cv);
+  const int64_t* seg_dev = tb.put(seg.data(), seg.size());
+  const PointUpd* upd_dev = tb.put(upd.data(), upd.size());
+  const double* coef_dev = tb.put(coef.data(), coef.size());
+  if (!workspace || !cv.fits()) {
+    set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
+    return SKMP_ENOMEM;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc2 = tb.upload(st)) return rc2;
+  const int64_t threads = n_seg * k;
+  hipLaunchKernelGGL(point_update_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, R, ldr, k, n_seg,
+                     seg_dev, upd_dev, coef_dev, dim_stats);
   SKMP_CHECK_HIP(hipGetLastError());
   if (changed_groups) *changed_groups = mask;
   return SKMP_OK;

@@ -82,6 +82,7 @@ struct SeriesPlan {
   double* p0;          // profile row g at p0 + g * ldp (NULL: not written)
   int64_t* i0;         // index row g at i0 + g * ldp
   int64_t ldp;
+  int64_t keep;        // windows [0, keep) already hold a profile in p0 / i0 that is merged, not overwritten
   const double* cr0;   // the column series: sketch rows, samples, windows, stats base, padded length
   int64_t cldr;
   int64_t cn;
@@ -91,7 +92,8 @@ struct SeriesPlan {
   int32_t cs;          // index of the column series
   int32_t d0;          // first diagonal of the units (excl in a self-join; 0 / 1 in an AB-join)
   int32_t pexcl;       // trivial-match zone against the partner series (0 between different series)
-  int32_t pad0;
+  int32_t c0;          // a band's walk starts at step max(0, c0 - first diagonal): 0, or the first step
+                       // that can reach a column >= keep (an append)
 };
 
 struct GroupList {
@@ -175,6 +177,7 @@ __device__ __forceinline__ SeriesPlan load_plan(const SJState& st, int s) {
   sp.cstat_base = uni(sp.cstat_base);
   sp.clpad = uni(sp.clpad);
   sp.d0 = uni(sp.d0);
+  sp.c0 = uni(sp.c0);
   return sp;
 }
 

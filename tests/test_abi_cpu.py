@@ -182,3 +182,69 @@ def test_dim_detect_argument_checks(L):
     assert call(nd=0) == -1
     assert call(ws=16) == -2                # workspace too small
     assert L.skmp_last_error()
+
+
+def test_streaming_argument_checks(L):
+    i64p = ctypes.POINTER(ctypes.c_int64)
+
+    def arr(*xs):
+        a = np.array(xs, dtype=np.int64)
+        return a, a.ctypes.data_as(i64p)
+
+    nn, nnp = arr(1000, 3000)
+    assert L.mp_selfjoin_append_workspace(2, nnp, 4, 64, 0) > 0
+    assert L.mp_selfjoin_append_workspace(2, nnp, 4, 64, 1) > 0
+    assert L.mp_selfjoin_append_workspace(2, nnp, 4, 64, 2) == 0   # MFMA precisions: no append
+    fake = ctypes.c_void_p(16)
+    M = (1 << 64) - 1
+
+    def append(starts=(0, 4000), n_old=(900, 2500), n_new=(1000, 3000), k=2, m=64, excl=16, prec=0, ld=8000,
+               ws=1 << 30):
+        s, sp = arr(*starts)
+        o, op = arr(*n_old)
+        n, np_ = arr(*n_new)
+        return L.mp_selfjoin_append(fake, ld, len(starts), sp, op, np_, k, m, excl, prec, 0, M, fake, fake, ld, fake,
+                                    ws, None)
+    assert append(prec=2) == -1                      # BF16x3
+    assert append(n_old=(1100, 2500)) == -1          # n_old > n_new
+    assert append(n_old=(-1, 2500)) == -1
+    assert append(n_new=(50, 3000)) == -1            # shorter than m
+    assert append(starts=(0, 500)) == -1             # overlapping series
+    assert append(ld=5000) == -1                     # runs past the stride
+    assert append(excl=0) == -1
+    assert append(ws=16) == -2                       # workspace too small
+    assert append(n_old=(1000, 3000)) == 0           # nothing new: no launch at all
+    assert L.skmp_last_error() == b""
+
+    no, nop = arr(0, 300, 300)
+    dst, dstp = arr(1000, 5000, 5000)
+    assert L.sketch_append_workspace(6, 2, nop, 4) > 0
+    bad, badp = arr(1000, 1100)                      # series 1 would overwrite series 0's columns
+    assert L.sketch_append(fake, 0, 6, 300, 2, nop, badp, None, 4, 1, 7, fake, 0, fake, 8000, fake, 1 << 30,
+                           None) == -1
+    far, farp = arr(7800, 8100)                      # series 0 runs past ldr
+    assert L.sketch_append(fake, 0, 6, 300, 2, nop, farp, None, 4, 1, 7, fake, 0, fake, 8000, fake, 1 << 30,
+                           None) == -1
+    assert L.sketch_append(fake, 0, 6, 300, 2, nop, dstp, None, 2, 0, 7, fake, 0, fake, 8000, fake, 1 << 30,
+                           None) == -1              # sum sketch with k = 2
+
+    dims, dimsp = arr(0, 5)
+    cols, colsp = arr(3, 99)
+    dl = np.array([1.0, -2.0])
+    dlp = dl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.sketch_point_update_workspace(2, 4) > 0
+    assert L.sketch_point_update_workspace(0, 4) == 0
+    bd, bdp = arr(0, 6)                              # dimension 6 of 6
+    assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 2, None, bdp, colsp, dlp, None, fake,
+                                 1 << 30, None) == -1
+    bc, bcp = arr(3, 100)                            # column 100 of 100
+    assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 2, None, dimsp, bcp, dlp, None, fake,
+                                 1 << 30, None) == -1
+    inf = np.array([1.0, np.inf])
+    assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 2, None, dimsp, colsp,
+                                 inf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, fake, 1 << 30,
+                                 None) == -1
+    assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 2, None, dimsp, colsp, dlp, None, fake,
+                                 16, None) == -2     # workspace too small
+    assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 0, None, None, None, None, None, None,
+                                 0, None) == 0       # no updates: nothing to do, nothing launched

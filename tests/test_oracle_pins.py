@@ -374,3 +374,77 @@ def test_planted_discord_is_recovered_on_c0(c_oracle):
     (_, _, o, _), = w.planted
     assert abs(top[0][0] - o) <= w.m // 2
     assert len(top) == 10 and all(top[q][2] >= top[q + 1][2] for q in range(9))
+
+
+# ---------------------------------------------------------------- streaming
+def _frozen_normalise(T, mu, sd):
+    """Each row normalised with given statistics (sigma = 0: zeros), in numpy."""
+    safe = np.where(sd > 0, sd, 1.0)
+    return np.where((sd > 0)[:, None], (T - mu[:, None]) / safe[:, None], 0.0)
+
+
+@pytest.mark.parametrize("n,m,excl,n0,flat", [
+    (160, 8, 2, 0, None),           # from the first sample on
+    (220, 16, 4, 150, (180, 205)),  # flat block among the new samples
+    (200, 12, 40, 60, (20, 45)),    # flat block among the old samples, wide exclusion zone
+    (60, 12, 40, 30, None),         # rows without an admissible partner before and after
+])
+def test_streaming_profile_equals_batch(n, m, excl, n0, flat, c_oracle):
+    """Growing the profile sample by sample (pairwise Def. 3 distances) ends
+    at the batch profile of the whole series (Def. 6), computed by the C
+    brute force; rows with no admissible partner stay +inf / -1."""
+    r = datagen.tiny_series(20 + n, 1, n)[0]
+    if flat is not None:
+        r[flat[0]:flat[1]] = 1.25
+    Ps, Is = O.matrix_profile_streaming(r, m, excl, n0)
+    P, I = c_oracle.profile(r, m, excl)
+    assert np.array_equal(np.isinf(Ps), np.isinf(P))
+    fin = np.isfinite(P)
+    assert np.max(np.abs(Ps[fin] - P[fin]), initial=0.0) < 1e-12
+    assert np.array_equal(Is, I)
+    if n == 60:
+        assert np.isinf(Ps[20]) and Is[20] == -1
+
+
+def test_sketch_append_continues_the_frozen_projection():
+    """New samples sketched with the build's statistics equal the matching
+    columns of S times the frozen normalisation of the whole series (numpy
+    matmul); appending in pieces equals appending at once."""
+    T = datagen.tiny_series(21, 7, 500)
+    T[3] = 2.0                                   # a constant dimension
+    n0 = 300
+    for kind, k in (("count", 3), ("gauss", 4), ("sum", 1)):
+        R0, S, mu, sd = O.build(T[:, :n0], kind, k, seed=5)
+        assert sd[3] == 0.0
+        Rn = O.sketch_append(T[:, n0:], S, mu, sd)
+        full = np.matmul(S, _frozen_normalise(T, mu, sd))
+        assert np.max(np.abs(R0 - full[:, :n0])) < 1e-12
+        assert np.max(np.abs(Rn - full[:, n0:])) < 1e-12
+        Ra = O.sketch_append(T[:, n0:401], S, mu, sd)
+        Rb = O.sketch_append(T[:, 401:], S, mu, sd)
+        assert np.array_equal(np.concatenate([Ra, Rb], axis=1), Rn)
+
+
+def test_point_update_equals_resketch_of_changed_samples():
+    """Point updates (Section III-C) equal the frozen sketch of the changed
+    series; a constant dimension's update changes nothing; a count sketch
+    changes only the updated dimensions' groups, at the updated columns."""
+    T = datagen.tiny_series(22, 6, 200)
+    T[2] = -1.0
+    updates = [(0, 5, 0.7), (4, 5, -1.3), (0, 5, 2.0), (2, 10, 5.0), (5, 199, 0.1), (1, 0, -0.25)]
+    for kind, k in (("count", 3), ("gauss", 4), ("sum", 1)):
+        R, S, mu, sd = O.build(T, kind, k, seed=3)
+        Ru = O.point_update(R, S, sd, updates)
+        T2 = T.copy()
+        for j, t, dl in updates:
+            T2[j, t] += dl
+        ref = np.matmul(S, _frozen_normalise(T2, mu, sd))
+        assert np.max(np.abs(Ru - ref)) < 1e-12
+        cols = sorted({t for j, t, _ in updates if j != 2})
+        other = np.setdiff1d(np.arange(200), cols)
+        assert np.array_equal(Ru[:, other], R[:, other])
+        assert np.array_equal(Ru[:, 10], R[:, 10])           # only the constant dimension touched column 10
+        if kind == "count":
+            groups = {int(np.nonzero(S[:, j])[0][0]) for j, _, _ in updates if j != 2}
+            for g in set(range(k)) - groups:
+                assert np.array_equal(Ru[g], R[g])
