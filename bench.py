@@ -95,6 +95,10 @@ def _parse():
                     help="ab: AB-join of the second half of a single-series workload (test) against its first "
                          "half (train), as in the train/test procedure")
     ap.add_argument("--no-dims", action="store_true", help="skip the dimension-detection measurement")
+    ap.add_argument("--stream", action="store_true",
+                    help="measure the streaming path: appends of new samples (sketch + self-join update)")
+    ap.add_argument("--batch-list", default="1,16,256,2048",
+                    help="--stream: samples per append (the first of these is the line's value)")
     ap.add_argument("--experiment", default=None, choices=["random-walks"],
                     help="random-walks: the sketched vs exact discord experiment of Section IV-A")
     ap.add_argument("--trials", type=int, default=20)
@@ -362,6 +366,134 @@ def _bench_ab(args, prec: str, refresh: int) -> int:
     return 0
 
 
+def _bench_stream(args, prec: str, refresh: int) -> int:
+    """Streaming (Section III-B's streaming extension): the first 80 % of a
+    single-series workload is sketched and joined once; the rest arrives in
+    appends of `a` samples, each sketched with the frozen statistics and
+    merged into the profile by mp_selfjoin_append.  Per batch size: the
+    latency of one append (synchronised), the pipelined time per append, the
+    stage split, and the cost of recomputing the whole series instead."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2311_03393_amd as skmp
+    if args.workload == "c3":
+        print("the streaming measurement takes a single-series workload (c0, c1, c2, c4)", file=sys.stderr)
+        return 2
+    if prec not in ("fp64", "fp32"):
+        prec, refresh = "fp32", 0
+    dev = torch.device("cuda:0")
+    w = datagen.make(args.workload)
+    k, m, excl = w.k, w.m, w.excl
+    d, n = w.T.shape
+    n0 = (n * 4) // 5
+    T = torch.from_numpy(w.T).to(dev)
+    R = torch.empty((k, n), dtype=torch.float64, device=dev)
+    P = torch.full((k, n), float("nan"), dtype=torch.float64, device=dev)
+    I = torch.full((k, n), -2, dtype=torch.int64, device=dev)
+    _, stats = skmp.sketch_build(T[:, :n0], [0, n0], k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=R[:, :n0])
+    skmp.mp_selfjoin(R[:, :n0], [0, n0], k, m, excl, prec=prec, refresh=refresh, P=P, I=I)
+    torch.cuda.synchronize()
+    P0, I0 = P.clone(), I.clone()
+    ws_j = torch.empty(max(skmp.mp_selfjoin_append_workspace([n], k, m, prec), 256), dtype=torch.uint8, device=dev)
+
+    # the alternative: sketch and join the whole series again
+    Rf = torch.empty((k, n), dtype=torch.float64, device=dev)
+    sf = torch.empty((1, d, 2), dtype=torch.float64, device=dev)
+    Pf = torch.empty((k, n), dtype=torch.float64, device=dev)
+    If = torch.empty((k, n), dtype=torch.int64, device=dev)
+    ws_f = torch.empty(max(skmp.mp_selfjoin_workspace([0, n], k, m, prec), 256), dtype=torch.uint8, device=dev)
+
+    def full():
+        skmp.sketch_build(T, [0, n], k, w.kind, w.sketch_seed, dim_ids=w.dim_ids, R=Rf, stats=sf)
+        skmp.mp_selfjoin(Rf, [0, n], k, m, excl, prec=prec, refresh=refresh, P=Pf, I=If, workspace=ws_f)
+
+    full()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        full()
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) * 1e3 / 3
+    _progress(f"stream {prec}: full recompute {full_ms:.3f} ms")
+
+    def append(cur: int, a: int):
+        skmp.sketch_append(T[:, cur:cur + a], [0, a], [cur], R, stats, k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
+        skmp.mp_selfjoin_append(R, P, I, [0], [cur], [cur + a], k, m, excl, prec=prec, refresh=refresh,
+                                workspace=ws_j)
+
+    def restore():
+        P.copy_(P0)
+        I.copy_(I0)
+
+    batches = {}
+    for a in [int(x) for x in args.batch_list.split(",") if x]:
+        reps = max(1, min(args.steps, (n - n0) // a))
+        restore()
+        append(n0, a)  # warm-up (plans, workspace)
+        torch.cuda.synchronize()
+        restore()
+        torch.cuda.synchronize()
+        lat = []
+        cur = n0
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            append(cur, a)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            cur += a
+        restore()
+        skmp.timing_enable(True)
+        for st in skmp.TIMERS:
+            skmp.timing_read(st, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cur = n0
+        for _ in range(reps):
+            append(cur, a)
+            cur += a
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        skmp.timing_enable(False)
+        stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
+        # the grown profile against a batch join of the same samples (same precision)
+        Pb, Ib = skmp.mp_selfjoin(R[:, :cur], [0, cur], k, m, excl, prec=prec, refresh=refresh)
+        torch.cuda.synchronize()
+        n_sub = cur - m + 1
+        dP = float((P[:, :n_sub] - Pb[:, :n_sub]).abs().max())
+        same_I = float((I[:, :n_sub] == Ib[:, :n_sub]).double().mean())
+        # pairs whose later subsequence is new: sum over new windows j of (j - excl + 1)
+        j0, j1 = n0 - m + 1, cur - m + 1
+        new_pairs = k * ((j1 - excl) * (j1 - excl + 1) - (j0 - excl) * (j0 - excl + 1)) / 2.0
+        tiles_ms, tiles_n = stage["tiles"]
+        _progress(f"stream {prec}: a={a}: {ms:.3f} ms per append (latency median {np.median(lat):.3f} ms)")
+        batches[str(a)] = {
+            "samples_per_append": a, "appends": reps, "ms_per_append": ms,
+            "latency_ms": {"median": float(np.median(lat)), "max": float(np.max(lat))},
+            "samples_per_s": a * reps / (ms * reps * 1e-3),
+            "new_pairs_per_append": new_pairs / reps, "new_pairs_per_s": new_pairs / (ms * reps * 1e-3),
+            "stages_ms_per_append": {st: v[0] / reps for st, v in stage.items() if v[1]},
+            "tile_kernel_ms": tiles_ms / max(tiles_n, 1),
+            "full_recompute_ms": full_ms, "speedup_vs_recompute": full_ms / ms,
+            "vs_batch_join": {"max_abs_dP": dP, "same_neighbour_frac": same_I},
+        }
+    restore()
+    first = batches[next(iter(batches))]
+    result = {
+        "metric": "streaming: appended samples per second (sketch + self-join update)",
+        "value": first["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": first["ms_per_append"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32"}[prec], "data": "synthetic",
+        "config": {"workload": DESCR[args.workload] + f": first {n0} samples joined once, the rest appended",
+                   "precision": prec, "refresh": refresh, "samples_per_append": first["samples_per_append"],
+                   "parallelism": "single GPU"},
+        "batches": batches,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -380,6 +512,8 @@ def main() -> int:
     refresh = args.refresh if args.refresh is not None else (named_refresh if prec == named_prec else 0)
     if args.join == "ab":
         return _bench_ab(args, prec, refresh)
+    if args.stream:
+        return _bench_stream(args, prec, refresh)
     if args.experiment == "random-walks":
         return _experiment_random_walks(args)
 

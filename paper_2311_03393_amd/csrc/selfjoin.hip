@@ -255,6 +255,26 @@ constexpr int seed_chunk() { return (128 / C) * C; }
 template <int C>
 constexpr int seed_stage_len() { return 64 + seed_chunk<C>() + 64 * C + seed_chunk<C>(); }
 
+// LDS of the FP32 tile kernel's workgroup: the row and column key partials
+// (NROW + NCOL keys) and the exact-seed stage share one buffer, since the
+// stage is only used at the start of a work unit, before the walk touches the
+// keys (refill_keys empties them again).  The workgroup then needs the larger
+// of the two (10.5 KB instead of 16.75 KB at C = 16), so LDS no longer caps the
+// occupancy below the 3 waves per SIMD the register budget allows.
+template <typename K, int NROW, int NCOL, int C>
+constexpr int tile_lds_bytes() {
+  return (int)sizeof(K) * (NROW + NCOL) > (int)sizeof(double) * seed_stage_len<C>()
+             ? (int)sizeof(K) * (NROW + NCOL)
+             : (int)sizeof(double) * seed_stage_len<C>();
+}
+
+template <typename K>
+__device__ __forceinline__ void refill_keys(K* keys, int count, K empty, int t) {
+  __syncthreads();  // every lane is done with the seed stage
+  for (int x = t; x < count; x += 64) keys[x] = empty;
+  __syncthreads();
+}
+
 template <int C>
 __device__ __forceinline__ void exact_seeds(double* stage, const double* __restrict__ r, const double* __restrict__ mu,
                                             const double* __restrict__ rc, const double* __restrict__ muc, int u,
@@ -413,13 +433,19 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
 // columns move down by TL and keep accumulating in the next block.  Every row
 // and column of a unit is thereby flushed once.  to_global(key, delta) forms
 // the global 64-bit key of a local key whose partner lies delta diagonals up.
-template <int C, int TL, typename K, typename G, typename V>
+// QB > 0: the local code is (63 - t) 2^QB + (2^QB - 1 - q) (lane t, its
+// diagonal q), so LMAX - code = t 2^QB + q; QB = 0: LMAX - code = t C + q.
+template <int C, int TL, int QB = 0, typename K, typename G, typename V>
 __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_rows, int n_cols, int t,
                                             unsigned long long* gro, unsigned long long* gco, K empty, G to_global,
                                             V valid) {
   constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
   constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
   constexpr uint32_t LMAX = (64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u);
+  auto diag = [](uint32_t local) -> int {
+    if constexpr (QB > 0) return (int)(local >> QB) * C + (int)(local & ((1u << QB) - 1));
+    else return (int)local;
+  };
   __syncthreads();
   K kr[RPL], kc[CPL];
 #pragma unroll
@@ -448,7 +474,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
     const int xl = t + 64 * q;
     const int x = u0 - 63 + xl;
     if (valid(kr[q]) && (last || xl < TL) && xl < NROW && x >= 0 && x < n_rows) {
-      const int delta = db + (int)(LMAX - (uint32_t)(kr[q] & LMAX));
+      const int delta = db + diag(LMAX - (uint32_t)(kr[q] & LMAX));
       atomicMax(gro + x, to_global(kr[q], delta));
     }
   }
@@ -457,7 +483,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
     const int xl = t + 64 * q;
     const int j = u0 + db + xl;
     if (valid(kc[q]) && (last || xl < TL) && xl < NCOL && j < n_cols) {
-      const int delta = db + (int)(LMAX - (uint32_t)(kc[q] & LMAX));
+      const int delta = db + diag(LMAX - (uint32_t)(kc[q] & LMAX));
       atomicMax(gco + j, to_global(kc[q], delta));
     }
   }
@@ -471,6 +497,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   constexpr int LBITS = (64 * C <= 512) ? 9 : ((64 * C <= 1024) ? 10 : 11);
   constexpr uint32_t LMAX = (1u << LBITS) - 1;
   static_assert(TL % C == 0, "tile length must be a multiple of C");
+  // separate key and seed buffers: measured faster for this kernel than the
+  // shared buffer of the FP32 kernel (whose higher occupancy does not pay here)
   __shared__ unsigned long long rowk[NROW];
   __shared__ unsigned long long colk[NCOL];
   __shared__ double sseed[seed_stage_len<C>()];
@@ -623,10 +651,18 @@ struct LaneStateF {
   uint32_t colacc[C];
 };
 
+// Bits of the diagonal q (of the lane's C) in the FP32 local codes: the key of
+// a cell carries 2^QB - 1 - q, a compile-time constant, and the lane's bits
+// (63 - t) 2^QB are ORed in once per step, when the row minimum and the
+// retiring column minimum go to LDS (every key they combine is the lane's own).
+template <int C>
+constexpr int fp32_qbits() { return C <= 2 ? 1 : (C <= 4 ? 2 : (C <= 8 ? 3 : 4)); }
+
 template <int C, int PD>
-__device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], const uint32_t (&code)[C],
+__device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], uint32_t lcode,
                                                uint32_t keep, int ngroups, int u0, int db, const StatRsrcF& R,
                                                uint32_t* rowk, uint32_t* colk, int t) {
+  constexpr uint32_t QM = (1u << fp32_qbits<C>()) - 1;
   for (int gidx = 0; gidx < ngroups; ++gidx) {
 #pragma unroll
     for (int p = 0; p < C; ++p) {
@@ -649,15 +685,15 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
         // 1 - rho (+ 2^-16 so FP32 rounding never makes it negative): a positive
         // float, resolved relative to itself, so close candidates stay apart
         const float kf = __builtin_fmaf(-a, cur.rinv, KEY_ONE);
-        const uint32_t key = (__float_as_uint(kf) & keep) | code[q];  // padded cells: NaN bits, above every key
+        const uint32_t key = (__float_as_uint(kf) & keep) | (QM - q);  // padded cells: NaN bits, above every key
         rowp = (q == 0) ? key : min(rowp, key);
         if (q == C - 1) ls.colacc[sl] = key;
         else ls.colacc[sl] = min(ls.colacc[sl], key);
         ls.Cq[q] = __builtin_fmaf(cur.rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = __builtin_fmaf(ls.cdf[sl], cur.rs.y, ls.Cq[q]);
       }
-      atomicMin(&rowk[us + 63 - t], rowp);
-      atomicMin(&colk[us + t * (C - 1)], ls.colacc[p]);
+      atomicMin(&rowk[us + 63 - t], rowp | lcode);
+      atomicMin(&colk[us + t * (C - 1)], ls.colacc[p] | lcode);
     }
   }
 }
@@ -670,17 +706,15 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   constexpr uint32_t LMAX = (1u << LBITS) - 1;
   static_assert(TL % C == 0, "tile length must be a multiple of C");
   static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
-  __shared__ uint32_t rowk[NROW];
-  __shared__ uint32_t colk[NCOL];
-  __shared__ double sseed[seed_stage_len<C>()];
+  __shared__ __align__(16) uint32_t lds[tile_lds_bytes<uint32_t, NROW, NCOL, C>() / 4];
+  uint32_t* rowk = lds;
+  uint32_t* colk = lds + NROW;
+  double* sseed = reinterpret_cast<double*>(lds);
   const int t = threadIdx.x;
-  for (int x = t; x < NROW; x += 64) rowk[x] = 0xFFFFFFFFu;
-  for (int x = t; x < NCOL; x += 64) colk[x] = 0xFFFFFFFFu;
-  __syncthreads();
   const uint32_t keep = ~LMAX;
-  uint32_t code[C];
-#pragma unroll
-  for (int q = 0; q < C; ++q) code[q] = LMAX - (uint32_t)(t * C + q);
+  constexpr int QB = fp32_qbits<C>();
+  static_assert((64u << QB) - 1 <= LMAX, "lane and diagonal bits fit the local code");
+  const uint32_t lcode = (uint32_t)(63 - t) << QB;
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
   const int m = st.m;
 
@@ -724,6 +758,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
 #pragma unroll
       for (int q = 0; q < C; ++q) ls.Cq[q] = (float)acc[q];
     }
+    refill_keys(lds, NROW + NCOL, 0xFFFFFFFFu, t);
     const StatRsrcF R = make_rsrc_f<C>(st, gbase, sp.lpad, cgbase, sp.clpad);
     {
       const int up = u_begin + db + PADL;
@@ -742,13 +777,13 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     for (int k = 0; k < PD; ++k) ring[k] = load_step_f<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
-      sjf_run_groups<C, PD>(ls, ring, code, keep, ngroups, u0, db, R, rowk, colk, t);
+      sjf_run_groups<C, PD>(ls, ring, lcode, keep, ngroups, u0, db, R, rowk, colk, t);
       const bool last = (u0 + TL >= u_end);
       if (last) {
 #pragma unroll
-        for (int q = 0; q < C - 1; ++q) atomicMin(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q]);
+        for (int q = 0; q < C - 1; ++q) atomicMin(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q] | lcode);
       }
-      flush_block<C, TL>(
+      flush_block<C, TL, QB>(
           rowk, colk, last, u0, db, n_sub, n_cols, t, gro, gco, 0xFFFFFFFFu,
           [GMAX](uint32_t key, int delta) {
             // local keys order by 1 - rho (min); the global ones by 3 - that = rho + 2 (max)
@@ -1071,7 +1106,7 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 // window count), or by the built-in defaults.  FP32 units restart from an
 // exact FP64 seed, so their strip is always the refresh period.
 constexpr int kDefaultFp64Variant = 0;
-constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (spills 12 VGPRs outside the inner loop; fastest measured)
+constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (165 VGPRs, 10.5 KB LDS; fastest measured)
 static const int kTuneStrips[] = {1024, 2048, 4096};
 // The narrowest bands (C = 6 in FP64, C = 8 in FP32), for short appends.
 constexpr int kNarrowFp64Variant = 5;

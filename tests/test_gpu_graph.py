@@ -137,3 +137,46 @@ def test_autotune_choice_is_used_and_exact(prec, c_oracle):
         assert ok.all(), err
         check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
     skmp.tuning_clear()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_compiled_variant_matches_oracle(prec, c_oracle):
+    """Each compiled tile-kernel variant (diagonals per lane, prefetch depth,
+    occupancy, column scheme), forced through the tuning table, gives the
+    oracle's profile: the key codes of every lane width decode to the right
+    diagonal."""
+    import math
+    import torch
+    import paper_2311_03393_amd as skmp
+    from oracle import sketchmp_oracle as O
+    from tests.helpers import check_neighbours, fp64_tol, mixed_tol, profile_close
+    dev = torch.device("cuda:0")
+    n, m, excl, k = 3100, 32, 8, 2
+    T = datagen.tiny_series(43, 5, n)
+    R_np, _, _, _ = O.build(T, "gauss", k, 43)
+    R = torch.from_numpy(R_np).to(dev)
+    n_sub = n - m + 1
+    mlog, nlog = math.ceil(math.log2(m)), math.ceil(math.log2(n_sub))
+    strip = 2048 if prec == "fp64" else 256
+    P_o = [c_oracle.profile(R_np[g], m, excl)[0] for g in range(k)]
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
+    tested = 0
+    try:
+        for v in range(64):
+            skmp.tuning_clear()
+            try:
+                skmp.tuning_import(f"{ {'fp64': 0, 'fp32': 1}[prec]} {mlog} {nlog} {v} {strip} 1.0")
+            except skmp.SketchMPError:
+                break                                   # past the last compiled variant
+            _say("variant", prec, v)
+            P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec)
+            torch.cuda.synchronize()
+            P, I = P.cpu().numpy(), I.cpu().numpy()
+            for g in range(k):
+                ok, err = profile_close(P[g, :n_sub], P_o[g], m, tol)
+                assert ok.all(), f"{prec} variant {v} group {g}: max err {err}"
+                check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o[g], tol)
+            tested += 1
+    finally:
+        skmp.tuning_clear()
+    assert tested >= 3
