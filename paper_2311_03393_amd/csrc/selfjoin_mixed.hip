@@ -147,6 +147,8 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
   using V = typename E::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ unsigned int s_unit;
+  // per row of the panel: -m (mu_i - c) and invn_i (kept in LDS, not in registers)
+  __shared__ float2 rowdat[MT];
   const int m = st.m;
   const int mp = mpad(m);
   const int bc = centring_block(m);
@@ -199,21 +201,19 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 
     build_vectors<PREC>(acp, stage, r, mu, I0, up.sp.n, n_sub, m, tid);
 
-    // per-row epilogue data: -m (mu_i - c) and invn_i for the lane's 16 rows
-    float ma[4][4], ri[4][4];
+    // per-row epilogue data of the panel (read back per row block in the
+    // epilogue; the column loop's first barrier orders these writes)
+    if (tid < MT) {
+      const int i = I0 + tid;
+      const double c = mu[min(I0 + (tid / bc) * bc + bc / 2, n_sub - 1)];
+      const bool ok = i < n_sub;
+      rowdat[tid] = make_float2(ok ? (float)(-(double)m * (mu[i] - c)) : 0.f, ok ? (float)invn[i] : 0.f);
+    }
     uint32_t rowacc[4][4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int il = 64 * wr + 16 * rb + 4 * lg + v;
-        const int i = I0 + il;
-        const double c = mu[min(I0 + (il / bc) * bc + bc / 2, n_sub - 1)];
-        const bool ok = i < n_sub;
-        ma[rb][v] = ok ? (float)(-(double)m * (mu[i] - c)) : 0.f;
-        ri[rb][v] = ok ? (float)invn[i] : 0.f;
-        rowacc[rb][v] = KEY_NONE;
-      }
+      for (int v = 0; v < 4; ++v) rowacc[rb][v] = KEY_NONE;
 
     for (int jt = jt0; jt <= jt1; ++jt) {
       const int J0 = jt * MT;
@@ -238,37 +238,34 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
         for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
       for (int c = 0; c < mp / 32; ++c) {
-        V ah[4], al[4], bh[4], bl[4];
+        V ah[4], al[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
           ah[rb] = *reinterpret_cast<const V*>(acp + abase[rb] + 32 * c);
           al[rb] = *reinterpret_cast<const V*>(acp + 8 * bs + abase[rb] + 32 * c);
         }
+        const int tfirst = 32 * c + 8 * lg;
+        const int nv = m - tfirst;  // K padding: only t < m contributes
+        // one column block's fragments at a time (fewer live registers)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          bh[cb] = *reinterpret_cast<const V*>(bcp + bbase[cb] + 32 * c);
-          bl[cb] = *reinterpret_cast<const V*>(bcp + 8 * bs + bbase[cb] + 32 * c);
-        }
-        const int tfirst = 32 * c + 8 * lg;
-        if (tfirst + 8 > m) {  // K padding: only t < m contributes
-          const int nv = max(0, m - tfirst);
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb)
+          V bh = *reinterpret_cast<const V*>(bcp + bbase[cb] + 32 * c);
+          V bl = *reinterpret_cast<const V*>(bcp + 8 * bs + bbase[cb] + 32 * c);
+          if (nv < 8) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
               if (e >= nv) {
-                bh[cb][e] = E::cvt(0.f);
-                bl[cb][e] = E::cvt(0.f);
+                bh[e] = E::cvt(0.f);
+                bl[e] = E::cvt(0.f);
               }
-        }
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb) {
-            acc[rb][cb] = E::mfma(ah[rb], bh[cb], acc[rb][cb]);
-            acc[rb][cb] = E::mfma(ah[rb], bl[cb], acc[rb][cb]);
-            acc[rb][cb] = E::mfma(al[rb], bh[cb], acc[rb][cb]);
           }
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) {
+            acc[rb][cb] = E::mfma(ah[rb], bh, acc[rb][cb]);
+            acc[rb][cb] = E::mfma(ah[rb], bl, acc[rb][cb]);
+            acc[rb][cb] = E::mfma(al[rb], bh, acc[rb][cb]);
+          }
+        }
       }
 
       // epilogue
@@ -278,13 +275,20 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) colp[cb] = KEY_NONE;
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < 4; ++rb) {
+        float ma[4], ri[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float2 rd = rowdat[64 * wr + 16 * rb + 4 * lg + v];
+          ma[v] = rd.x;
+          ri[v] = rd.y;
+        }
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float C = __builtin_fmaf(ma[rb][v], bj[cb], acc[rb][cb][v]);
-            const float kf = __builtin_fmaf(-(C * cj[cb]), ri[rb][v], KEY_ONE);  // 1 - rho + 2^-16
+            const float C = __builtin_fmaf(ma[v], bj[cb], acc[rb][cb][v]);
+            const float kf = __builtin_fmaf(-(C * cj[cb]), ri[v], KEY_ONE);  // 1 - rho + 2^-16
             uint32_t key = (__float_as_uint(kf) & ~CODE_MASK) | (uint32_t)(code_tile + 16 * (rb - cb) + v);
             if (masked) {
               const int i = I0 + 64 * wr + 16 * rb + 4 * lg + v;
@@ -294,6 +298,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
             rowacc[rb][v] = min(rowacc[rb][v], key);
             colp[cb] = min(colp[cb], key);
           }
+      }
       // column maxima: combine the four lane groups holding the same column
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
