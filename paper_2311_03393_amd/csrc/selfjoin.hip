@@ -433,8 +433,10 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
 // columns move down by TL and keep accumulating in the next block.  Every row
 // and column of a unit is thereby flushed once.  to_global(key, delta) forms
 // the global 64-bit key of a local key whose partner lies delta diagonals up.
-// QB > 0: the local code is (63 - t) 2^QB + (2^QB - 1 - q) (lane t, its
-// diagonal q), so LMAX - code = t 2^QB + q; QB = 0: LMAX - code = t C + q.
+// The local code in a key's low bits names the cell's diagonal within the
+// band: QB = 0: code = LMAX - (t C + q) (lane t, its diagonal q); QB > 0:
+// code = (63 - t) 2^QB + (2^QB - 1 - q), decoded from its two bit fields
+// (the field may be narrower than LMAX).
 template <int C, int TL, int QB = 0, typename K, typename G, typename V>
 __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_rows, int n_cols, int t,
                                             unsigned long long* gro, unsigned long long* gco, K empty, G to_global,
@@ -442,9 +444,13 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
   constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
   constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
   constexpr uint32_t LMAX = (64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u);
-  auto diag = [](uint32_t local) -> int {
-    if constexpr (QB > 0) return (int)(local >> QB) * C + (int)(local & ((1u << QB) - 1));
-    else return (int)local;
+  auto diag = [](uint32_t code) -> int {
+    if constexpr (QB > 0) {
+      constexpr uint32_t QM = (1u << QB) - 1;
+      return (63 - (int)(code >> QB)) * C + (int)(QM - (code & QM));
+    } else {
+      return (int)(LMAX - code);
+    }
   };
   __syncthreads();
   K kr[RPL], kc[CPL];
@@ -474,7 +480,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
     const int xl = t + 64 * q;
     const int x = u0 - 63 + xl;
     if (valid(kr[q]) && (last || xl < TL) && xl < NROW && x >= 0 && x < n_rows) {
-      const int delta = db + diag(LMAX - (uint32_t)(kr[q] & LMAX));
+      const int delta = db + diag((uint32_t)(kr[q] & LMAX));
       atomicMax(gro + x, to_global(kr[q], delta));
     }
   }
@@ -483,7 +489,7 @@ __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0,
     const int xl = t + 64 * q;
     const int j = u0 + db + xl;
     if (valid(kc[q]) && (last || xl < TL) && xl < NCOL && j < n_cols) {
-      const int delta = db + diag(LMAX - (uint32_t)(kc[q] & LMAX));
+      const int delta = db + diag((uint32_t)(kc[q] & LMAX));
       atomicMax(gco + j, to_global(kc[q], delta));
     }
   }
@@ -812,6 +818,96 @@ __device__ int smallest_flat_at_or_after(const SJState& st, const double* invn, 
   return -1;
 }
 
+// ------------------------------------------------- short appends, direct
+// An append of at most APPEND_DIRECT new windows per series does not walk
+// bands (a short walk is a chain of dependent per-step loads): every new pair
+// (i, j), j >= keep, j - i >= excl, is computed directly as an exact FP64 dot
+// product of the centred windows, C = sum_t (r[i+t] - mu_i)(r[j+t] - mu_j),
+// one thread per row i of a 256-window chunk, the new windows' samples staged
+// in LDS.  Row i's best new partner above goes to rowkey[i] (this thread is its
+// only writer); new window j's best partner below is reduced over the wave and
+// the block and goes to colkey[j] by atomic maximum.  Keys have the tile
+// kernels' global form (rho + 2 with GMAX - delta in the low bits), so the
+// merge and FP64 polish are shared.
+constexpr int APPEND_DIRECT = 32;  // the kernel's limit (LDS sizing)
+// Chosen for up to about 2000 / m new windows: its cost grows by ~3.4 us per
+// new window per 100 samples of m (8 groups of 50,000 windows), the band walk
+// of a short append costs ~85 us whatever the count (measured: break-even
+// near 20 new windows at m = 100).
+static inline int append_direct_max(int m) { return std::min(APPEND_DIRECT, std::max(1, 2000 / m)); }
+
+__global__ __launch_bounds__(256) void append_direct_kernel(SJState st) {
+  extern __shared__ double sh_a[];  // the chunk's rows: 256 + m - 1 samples, then the new windows' A + m - 1 (+ 3 zeros)
+  __shared__ unsigned long long ckey[APPEND_DIRECT];
+  const ChunkPos c = decode_chunk(st, blockIdx.x);
+  const SeriesPlan& sp = st.plan[c.s];
+  const int m = st.m;
+  const int64_t n_sub = sp.n_sub, keep = sp.keep;
+  const int A = (int)(n_sub - keep);
+  // rows that can pair with a new window: x <= n_sub - 1 - excl
+  if (sp.p0 == nullptr || A <= 0 || A > APPEND_DIRECT || c.x0 + 255 < 0 || c.x0 > n_sub - 1 - st.excl) return;
+  const int g = st.groups.g[c.gi];
+  const double* r = sp.r0 + (int64_t)g * sp.ldr;
+  double* sw = sh_a;
+  double* sq = sh_a + 256 + m - 1;
+  for (int q = threadIdx.x; q < 256 + m - 1; q += 256) {
+    const int64_t t = c.x0 + q;
+    sw[q] = (t >= 0 && t < sp.n) ? r[t] : 0.0;
+  }
+  for (int q = threadIdx.x; q < A + m - 1 + 3; q += 256) sq[q] = (q < A + m - 1) ? r[keep + q] : 0.0;
+  if (threadIdx.x < APPEND_DIRECT) ckey[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int64_t sbase = (int64_t)c.gi * st.gstride + sp.stat_base + PADL;
+  const unsigned long long GMAX = (1ull << st.key_bits) - 1;
+  const int64_t x = c.x0 + threadIdx.x;
+  const bool row_ok = x >= 0 && x < n_sub;
+  const double mx = row_ok ? st.mu[sbase + x] : 0.0;
+  const double ix = row_ok ? st.invn[sbase + x] : 0.0;
+  const double* w = sw + threadIdx.x;
+  double se = 0.0;  // sum_t (r[x+t] - mu_x)
+  if (row_ok)
+    for (int t = 0; t < m; ++t) se += w[t] - mx;
+  unsigned long long rk = 0ull;
+  const int lane = threadIdx.x & 63;
+  // four new windows per pass: each centred row sample feeds four products
+  for (int a0 = 0; a0 < A; a0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* q = sq + a0;  // q[k + t]: window a0 + k (staged up to index A + m - 2; k + t past it is unused)
+    if (row_ok) {
+      for (int t = 0; t < m; ++t) {
+        const double e = w[t] - mx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = fma(e, q[k + t], acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = a0 + k;
+      if (a >= A) break;  // uniform
+      const int64_t j = keep + a;
+      const int64_t delta = j - x;
+      unsigned long long key = 0ull;
+      if (row_ok && delta >= st.excl) {
+        const double mj = st.mu[sbase + j], ij = st.invn[sbase + j];
+        const double C = fma(-mj, se, acc[k]);
+        const double v = fma(C * ij, ix, 2.0);  // rho + 2
+        key = ((unsigned long long)__double_as_longlong(v) & ~GMAX) | (GMAX - (unsigned long long)delta);
+        rk = max(rk, key);
+      }
+      // column j: the best partner below over the wave, then the block
+      unsigned long long wk = key;
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)wk, off);
+        wk = max(wk, o);
+      }
+      if (lane == 0 && wk != 0ull) atomicMax(&ckey[a], wk);
+    }
+  }
+  if (row_ok) st.rowkey[sbase + x] = rk;
+  __syncthreads();
+  if ((int)threadIdx.x < A && ckey[threadIdx.x] != 0ull) atomicMax(st.colkey + sbase + keep + threadIdx.x, ckey[threadIdx.x]);
+}
+
 __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   extern __shared__ double sh_w[];  // samples [x0, x0 + 256 + m - 1) of the chunk: the block's own windows
   const ChunkPos c = decode_chunk(st, blockIdx.x);
@@ -870,7 +966,18 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   } else {
     best = INFINITY;
     arg = -1;
-    if (partner >= 0) {
+    // an append's old window whose new candidate, judged by its key, cannot
+    // beat the stored distance keeps it without a polish (the keys resolve
+    // 1 - rho to better than 3e-4 relative, or 2^-16 absolute)
+    bool worse = false;
+    if (partner >= 0 && x < sp.keep && cinvn[partner] != 0.0) {
+      const unsigned long long kk = (ck != 0ull && ck >= rk) ? ck : rk;
+      const double rho = __longlong_as_double((long long)(kk & ~GMAX)) - 2.0;
+      const double d2 = 2.0 * m * (1.0 - rho);
+      const double po = sp.p0[(int64_t)g * sp.ldp + x];
+      worse = d2 > po * po * (1.0 + 1e-3) + 2e-4 * m;
+    }
+    if (partner >= 0 && !worse) {
       if (cinvn[partner] == 0.0) {
         best = sqrt_m;
       } else {
@@ -1076,7 +1183,8 @@ static void launch_fp64(dim3 grid, hipStream_t st, const SJState& s) {
 static const Fp64Variant kFp64Variants[] = {
     SKMP_FP64_V(8, 1, 2, false), SKMP_FP64_V(8, 1, 2, true),  SKMP_FP64_V(8, 2, 2, true),
     SKMP_FP64_V(10, 1, 2, true), SKMP_FP64_V(12, 1, 2, true), SKMP_FP64_V(6, 1, 3, true),
-    SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true), SKMP_FP64_V(8, 1, 3, false),
+    SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true), SKMP_FP64_V(8, 1, 3, false), SKMP_FP64_V(2, 1, 4, false),
+    SKMP_FP64_V(4, 1, 3, false),
 };
 #undef SKMP_FP64_V
 constexpr int kNumFp64Variants = sizeof(kFp64Variants) / sizeof(kFp64Variants[0]);
@@ -1093,7 +1201,8 @@ static void launch_fp32(dim3 grid, hipStream_t st, const SJState& s) {
   }
 static const Fp64Variant kFp32Variants[] = {
     SKMP_FP32_V(8, 1, 2), SKMP_FP32_V(16, 1, 2), SKMP_FP32_V(8, 1, 3), SKMP_FP32_V(12, 1, 2), SKMP_FP32_V(8, 2, 3),
-    SKMP_FP32_V(16, 2, 2), SKMP_FP32_V(16, 1, 3), SKMP_FP32_V(16, 2, 3),
+    SKMP_FP32_V(16, 2, 2), SKMP_FP32_V(16, 1, 3), SKMP_FP32_V(16, 2, 3), SKMP_FP32_V(2, 2, 4),
+    SKMP_FP32_V(4, 2, 4),
 };
 #undef SKMP_FP32_V
 constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
@@ -1324,7 +1433,18 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   }
   SKMP_CHECK_HIP(hipGetLastError());
 
-  if (pl.total_units > 0) {
+  // a short append: every series has at most append_direct_max(m) new windows
+  // (SKMP_APPEND_DIRECT overrides the limit, 0 turns the direct kernel off)
+  static const int env_direct = env_int("SKMP_APPEND_DIRECT", 0, APPEND_DIRECT);
+  const int direct_max = env_direct >= 0 ? env_direct : append_direct_max(m);
+  bool direct = keep != nullptr && !mfma && direct_max > 0;
+  for (int64_t q = 0; direct && q < n_series; ++q)
+    if (pl.sp[q].n_sub - pl.sp[q].keep > direct_max) direct = false;
+  if (direct) {
+    StageTimer tm(SKMP_TIMER_TILES, st);
+    hipLaunchKernelGGL(append_direct_kernel, cg, fb, sizeof(double) * (256 + m - 1 + APPEND_DIRECT + m - 1 + 3), st,
+                       s);
+  } else if (pl.total_units > 0) {
     StageTimer tm(SKMP_TIMER_TILES, st);
     if (mfma) {
       rc = launch_sj_mfma(prec, s, pl.total_units, st);

@@ -294,3 +294,43 @@ def test_stream_end_to_end_discords(dev, c_oracle):
     A_o = np.max(np.where(np.isfinite(P_o), P_o, -np.inf), axis=0)
     assert len(gpu_list) == len(ora_list)
     discords_equivalent(gpu_list, ora_list, A_o, m, mixed_tol(m))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_short_appends_batched_direct_path(dev, c_oracle, prec):
+    """Short appends (a few new subsequences per series, computed without
+    band walks): three series in one call, one of them starting from fewer
+    than m samples, flat blocks arriving among the new samples; checked
+    against the oracle after every call."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    k, m, excl = 2, 24, 6
+    starts, caps = [0, 3000, 6000], [2600, 2600, 2600]
+    ld = 9000
+    R_np = np.zeros((k, ld))
+    for s in range(3):
+        R_np[:, starts[s]:starts[s] + caps[s]] = _sketched(90 + s, k, caps[s])
+    R_np[:, starts[1] + 2010:starts[1] + 2040] = -0.25       # flat block arriving in series 1
+    R = torch.from_numpy(R_np).to(dev)
+    P = torch.full((k, ld), float("nan"), dtype=torch.float64, device=dev)
+    I = torch.full((k, ld), -2, dtype=torch.int64, device=dev)
+    cur = [2000, 2000, 10]
+    for s in (0, 1):
+        a = starts[s]
+        skmp.mp_selfjoin(R[:, a:a + cur[s]], [0, cur[s]], k, m, excl, prec=prec, P=P[:, a:a + cur[s]],
+                         I=I[:, a:a + cur[s]])
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
+    # appends of at most 8 new subsequences per series use the direct kernel; the last mixes in a longer one
+    for step in ([1, 7, 20], [8, 0, 3], [5, 8, 1], [0, 1, 0], [2, 30, 40]):
+        new = [cur[s] + step[s] for s in range(3)]
+        _say("short append", prec, cur, new)
+        skmp.mp_selfjoin_append(R, P, I, starts, cur, new, k, m, excl, prec=prec)
+        torch.cuda.synchronize()
+        cur = new
+        Ph, Ih = P.cpu().numpy(), I.cpu().numpy()
+        for s in range(3):
+            if cur[s] < m:
+                continue
+            a = starts[s]
+            _check_profile(c_oracle, R_np[:, a:a + cur[s]], m, excl, Ph[:, a:a + cur[s]], Ih[:, a:a + cur[s]], tol,
+                           f"series {s} at {cur[s]} samples")
