@@ -334,3 +334,56 @@ def test_short_appends_batched_direct_path(dev, c_oracle, prec):
             a = starts[s]
             _check_profile(c_oracle, R_np[:, a:a + cur[s]], m, excl, Ph[:, a:a + cur[s]], Ih[:, a:a + cur[s]], tol,
                            f"series {s} at {cur[s]} samples")
+
+
+def test_sketch_append_nonfinite_check(dev):
+    """With the finiteness check, NaN or Inf among the new samples is rejected
+    (nothing is written); finite samples pass and are sketched."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, n0, a, k = 6, 800, 200, 3
+    T = datagen.tiny_series(95, d, n0 + a)
+    Tt = torch.from_numpy(T).to(dev)
+    R = torch.full((k, n0 + a), 5.0, dtype=torch.float64, device=dev)
+    _, stats = skmp.sketch_build(Tt[:, :n0].contiguous(), [0, n0], k, "count", 8, R=R[:, :n0])
+    bad = Tt[:, n0:].clone()
+    bad[2, 17] = float("nan")
+    with pytest.raises(skmp.SketchMPError) as e:
+        skmp.sketch_append(bad, [0, a], [n0], R, stats, k, "count", 8, check_finite=True)
+    assert e.value.code == -4
+    torch.cuda.synchronize()
+    assert torch.all(R[:, n0:] == 5.0)
+    skmp.sketch_append(Tt[:, n0:].contiguous(), [0, a], [n0], R, stats, k, "count", 8, check_finite=True)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()[0]
+    S = O.sketch_coeffs("count", k, np.arange(d), 8)
+    want = O.sketch_append(T[:, n0:], S, st[:, 0], st[:, 1])
+    assert np.max(np.abs(R[:, n0:].cpu().numpy() - want)) < 1e-12 * max(1.0, float(np.max(np.abs(want))))
+
+
+def test_point_update_several_series(dev):
+    """Point updates in a batch of two series use each series' own statistics."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, k, n = 5, 4, 600
+    T = np.concatenate([datagen.tiny_series(96, d, n), 3.0 * datagen.tiny_series(97, d, n)], axis=1)
+    Tt = torch.from_numpy(np.ascontiguousarray(T)).to(dev)
+    R, stats = skmp.sketch_build(Tt, [0, n, 2 * n], k, "gauss", 21)
+    torch.cuda.synchronize()
+    R0 = R.cpu().numpy().copy()
+    st = stats.cpu().numpy()
+    S = O.sketch_coeffs("gauss", k, np.arange(d), 21)
+    rng = np.random.default_rng(9)
+    ser = rng.integers(0, 2, 50)
+    dims = rng.integers(0, d, 50)
+    cols = rng.integers(0, n, 50) + ser * n
+    deltas = rng.standard_normal(50)
+    skmp.sketch_point_update(R, stats, k, "gauss", 21, dims, cols, deltas, series=ser)
+    torch.cuda.synchronize()
+    want = R0.copy()
+    for s in range(2):
+        sel = ser == s
+        upd = list(zip(dims[sel].tolist(), cols[sel].tolist(), deltas[sel].tolist()))
+        want = O.point_update(want, S, st[s, :, 1], upd)
+    got = R.cpu().numpy()
+    assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, float(np.max(np.abs(want))))
