@@ -100,22 +100,49 @@ __global__ __launch_bounds__(256) void scale_kernel(SJState st) {
   __shared__ double red[4];
   const int64_t c0 = (int64_t)blockIdx.x * SCALE_CHUNKS;
   const int64_t c1 = min(c0 + SCALE_CHUNKS, st.total_chunks);
+  // every chunk's sample first (independent loads in flight together), then
+  // the running maxima in chunk order
+  double v[SCALE_CHUNKS];
+  int64_t key[SCALE_CHUNKS];
+#pragma unroll
+  for (int k = 0; k < SCALE_CHUNKS; ++k) {
+    v[k] = 0.0;
+    key[k] = -1;
+    if (c0 + k < c1) {
+      const ChunkPos c = decode_chunk(st, c0 + k);
+      key[k] = (int64_t)c.s * st.groups.count + c.gi;
+      const SeriesPlan& sp = st.plan[c.s];
+      const int64_t t = c.x0 + threadIdx.x;
+      const double* r = sp.r0 + (int64_t)st.groups.g[c.gi] * sp.ldr;
+      if (t >= 0 && t < sp.n) v[k] = fabs(r[t]);
+    }
+  }
   double run = 0.0;
   int64_t cur = -1;
-  for (int64_t chunk = c0; chunk < c1; ++chunk) {
-    const ChunkPos c = decode_chunk(st, chunk);
-    const int64_t key = (int64_t)c.s * st.groups.count + c.gi;
-    if (key != cur) {
+#pragma unroll
+  for (int k = 0; k < SCALE_CHUNKS; ++k) {
+    if (key[k] < 0) break;  // uniform
+    if (key[k] != cur) {
       if (cur >= 0) scale_flush(run, reinterpret_cast<unsigned long long*>(st.scale) + cur, red);
-      cur = key;
+      cur = key[k];
       run = 0.0;
     }
-    const SeriesPlan& sp = st.plan[c.s];
-    const int64_t t = c.x0 + threadIdx.x;
-    const double* r = sp.r0 + (int64_t)st.groups.g[c.gi] * sp.ldr;
-    if (t >= 0 && t < sp.n) run = fmax(run, fabs(r[t]));
+    run = fmax(run, v[k]);
   }
   if (cur >= 0) scale_flush(run, reinterpret_cast<unsigned long long*>(st.scale) + cur, red);
+}
+
+// Sum of m consecutive samples in four interleaved partial sums (shorter
+// dependency chains); every window's sum is formed in this one order.
+__device__ __forceinline__ double window_sum(const double* w, int m) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = 0;
+  for (; q + 4 <= m; q += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] += w[q + u];
+  }
+  for (; q < m; ++q) a[0] += w[q];
+  return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
@@ -137,11 +164,7 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   // its own thread, so both uses of it carry the same bits
   double* smu = sh_r + span;
   double mu = 0.0;
-  if (x >= 0 && x < sp.n_sub) {
-    double s = 0.0;
-    for (int q = 0; q < m; ++q) s += w[q];
-    mu = s * inv_m;
-  }
+  if (x >= 0 && x < sp.n_sub) mu = window_sum(w, m) * inv_m;
   smu[threadIdx.x] = mu;
   __syncthreads();
   // the chunk grid rounds each group's padded range up to 256: stay inside it
@@ -168,11 +191,22 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     }
     return;
   }
-  double v = 0.0;
-  for (int q = 0; q < m; ++q) {
-    const double e = w[q] - mu;
-    v = fma(e, e, v);
+  double va[4] = {0.0, 0.0, 0.0, 0.0};
+  {
+    int q = 0;
+    for (; q + 4 <= m; q += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double e = w[q + u] - mu;
+        va[u] = fma(e, e, va[u]);
+      }
+    }
+    for (; q < m; ++q) {
+      const double e = w[q] - mu;
+      va[0] = fma(e, e, va[0]);
+    }
   }
+  const double v = (va[0] + va[1]) + (va[2] + va[3]);
   const double sd = sqrt(v * inv_m);
   const double scale = st.scale[(int64_t)c.s * st.groups.count + c.gi];
   const bool flat = sd <= FLAT_REL * scale;
@@ -182,9 +216,7 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     if (threadIdx.x + 1 < 256) {
       mu1 = smu[threadIdx.x + 1];
     } else {  // window x + 1 belongs to the next chunk: same sum, same order
-      double s1 = 0.0;
-      for (int q = 1; q <= m; ++q) s1 += w[q];
-      mu1 = s1 * inv_m;
+      mu1 = window_sum(w + 1, m) * inv_m;
     }
     df = 0.5 * (w[m] - w[0]);
     dg = (w[m] - mu1) + (w[0] - mu);
@@ -1184,7 +1216,7 @@ static const Fp64Variant kFp64Variants[] = {
     SKMP_FP64_V(8, 1, 2, false), SKMP_FP64_V(8, 1, 2, true),  SKMP_FP64_V(8, 2, 2, true),
     SKMP_FP64_V(10, 1, 2, true), SKMP_FP64_V(12, 1, 2, true), SKMP_FP64_V(6, 1, 3, true),
     SKMP_FP64_V(8, 1, 3, true),  SKMP_FP64_V(16, 1, 2, true), SKMP_FP64_V(8, 1, 3, false), SKMP_FP64_V(2, 1, 4, false),
-    SKMP_FP64_V(4, 1, 3, false),
+    SKMP_FP64_V(4, 1, 3, false), SKMP_FP64_V(8, 2, 2, false),
 };
 #undef SKMP_FP64_V
 constexpr int kNumFp64Variants = sizeof(kFp64Variants) / sizeof(kFp64Variants[0]);
@@ -1214,7 +1246,7 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 // keyed by precision and the log2 buckets of m and of the longest series'
 // window count), or by the built-in defaults.  FP32 units restart from an
 // exact FP64 seed, so their strip is always the refresh period.
-constexpr int kDefaultFp64Variant = 0;
+constexpr int kDefaultFp64Variant = 11;  // C = 8, prefetch 2, register column windows (fastest measured)
 constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (165 VGPRs, 10.5 KB LDS; fastest measured)
 static const int kTuneStrips[] = {1024, 2048, 4096};
 // The narrowest bands (C = 6 in FP64, C = 8 in FP32), for short appends.
