@@ -337,10 +337,13 @@ size_t mp_selfjoin_append_workspace(int64_t n_series, const int64_t* n_new, int3
  * n_old[s] samples (from mp_selfjoin or an earlier append with the same m,
  * excl and precision); on return they hold the profile of all n_new[s]
  * samples, as mp_selfjoin of the whole series would.  Only pairs with a
- * subsequence that ends in the new samples are computed: about
- * (n_new - n_old + 64 C) (n_new - m + 1) distance cells per group, C = 6
- * (FP64) or 8 (FP32) diagonals per lane for appends of fewer than 2048
- * subsequences, the batch join's C above that.
+ * subsequence that ends in the new samples are computed.  Appends of at most
+ * about 2000 / m new subsequences per series (at most 32) compute each new
+ * pair directly as an exact FP64 dot product; longer ones walk the diagonal
+ * bands from the first step that reaches a new subsequence, about
+ * (n_new - n_old + 64 C) (n_new - m + 1) cells per group with C = 6 (FP64) or
+ * 8 (FP32) diagonals per lane below 2048 new subsequences, the batch join's C
+ * above that.
  *   starts   host, n_series: ascending, disjoint, starts[s] + n_new[s] <= ldr, ldp.
  *   n_old, n_new host, n_series: 0 <= n_old <= n_new, n_new >= m; n_old < m
  *            joins the series afresh; n_old = n_new leaves it untouched.
