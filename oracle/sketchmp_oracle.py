@@ -23,9 +23,12 @@ blocking, fusion or reordering beyond what the definition states:
 * the AB-join between a test and a train series and the discord dimension
   detection (Algorithm 3), which scores each dimension of the discord's group
   by the AB-join of the test subsequence against that dimension's train
-  series.
+  series;
+* the streaming extension (Section III-B): the projection of newly arrived
+  samples with frozen statistics, the self-join profile maintained sample by
+  sample, and the point update of Section III-C.
 
-Readings where the paper is silent (each one is listed in the design doc):
+Readings where the paper is silent:
 
 * z-normalisation uses the population standard deviation; a constant
   dimension (sigma <= FLAT_REL * max|value|) normalises to all zeros.
@@ -35,6 +38,8 @@ Readings where the paper is silent (each one is listed in the design doc):
 * a pair (i, j) is a trivial match, and excluded, iff |i - j| < excl.
 * nearest-neighbour ties go to the smallest j; a row with no admissible
   partner gets P = +inf and I = -1 and is never reported as a discord.
+* in a stream the per-dimension (mu, sigma) stay those the sketch was built
+  with, and a point update's delta is the change of the raw sample.
 * the discord list is greedy on A[i] = max_g P_g[i] (first g on ties, the
   strict ">" of Algorithm 2); each pick masks |i - i*| < halfwidth (default
   m); ties in A go to the smallest i.
