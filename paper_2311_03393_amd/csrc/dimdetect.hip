@@ -14,12 +14,12 @@
 // <= 1e-10 max|Tbar_j|, i.e. sigma(window of T_j) <= 1e-10 max|T_j - mu_j|.
 //
 //   dd_scale:  max|T_j - mu_j| of every selected dimension of both series;
-//   dd_dist:   one block per (dimension, 256 train subsequences): the test
+//   dd_dist:   one block per (dimension, 1024 train subsequences): the test
 //              subsequence and the block's samples in LDS; each thread takes
-//              one subsequence: mean and sigma (two passes), then the
-//              distance from explicit differences of the normalised windows,
-//              all FP64; the block's nearest (smallest index on ties) goes to
-//              the workspace;
+//              four consecutive subsequences: means and sigmas (two passes),
+//              then the distances from explicit differences of the normalised
+//              windows, all FP64; the block's nearest (smallest index on ties)
+//              goes to the workspace;
 //   dd_reduce: the nearest over a dimension's blocks -> score, neighbour;
 //   dd_pick:   the first dimension with the strictly largest score above 0.
 #include <hip/hip_runtime.h>
@@ -51,7 +51,7 @@ struct DDState {
   int32_t m;
   int32_t excl;         // > 0: self-join setting, |t - i*| < excl excluded
   int64_t i_star;
-  int64_t nblk;         // blocks of 256 train subsequences per dimension
+  int64_t nblk;         // blocks of DD_SPAN train subsequences per dimension
   unsigned long long* scale;  // 2 x n_dims: max|T_j - mu_j| bits (train, test)
   double2* part;        // n_dims x nblk: (distance, index) of each block's nearest
   double* scores;
@@ -123,8 +123,38 @@ __device__ __forceinline__ void block_nearest(double& d, double& i, double* sd, 
   }
 }
 
+// Each thread takes DD_R consecutive train subsequences (windows r = 0 ..
+// DD_R - 1 starting at w + r): in each pass over the samples every LDS read
+// of w[k'] serves all the windows containing position k' (window r holds
+// positions r .. r + m - 1), with one partial sum per window.  The reads per
+// subsequence drop DD_R-fold; LDS bandwidth bounded the one-subsequence form.
+constexpr int DD_R = 4;
+constexpr int DD_SPAN = DD_THREADS * DD_R;  // train subsequences per block
+
+template <typename F>
+__device__ __forceinline__ void over_windows(const double* w, int m, F f) {
+#pragma unroll
+  for (int kp = 0; kp < DD_R - 1; ++kp) {  // positions before every window has started
+    const double x = w[kp];
+#pragma unroll
+    for (int r = 0; r <= kp; ++r) f(x, kp, r);
+  }
+  for (int kp = DD_R - 1; kp < m; ++kp) {  // positions inside every window
+    const double x = w[kp];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) f(x, kp, r);
+  }
+#pragma unroll
+  for (int e = 0; e < DD_R - 1; ++e) {  // positions after the first windows have ended
+    const int kp = m + e;
+    const double x = w[kp];
+#pragma unroll
+    for (int r = e + 1; r < DD_R; ++r) f(x, kp, r);
+  }
+}
+
 __global__ __launch_bounds__(DD_THREADS) void dd_dist(DDState s) {
-  extern __shared__ double dd_lds[];  // query m, then samples DD_THREADS + m - 1
+  extern __shared__ double dd_lds[];  // query m, then samples DD_SPAN + m - 1
   __shared__ double qstat[2];         // query mean, 1/sigma (0 when flat)
   __shared__ double sd[DD_THREADS / 64], si[DD_THREADS / 64];
   const int p = blockIdx.y;
@@ -132,10 +162,10 @@ __global__ __launch_bounds__(DD_THREADS) void dd_dist(DDState s) {
   const int64_t row = s.dims[p];
   double* q = dd_lds;
   double* seg = dd_lds + m;
-  const int64_t t0 = (int64_t)blockIdx.x * DD_THREADS;
+  const int64_t t0 = (int64_t)blockIdx.x * DD_SPAN;
   const int64_t n_sub = s.n_tr - m + 1;
   for (int k = threadIdx.x; k < m; k += DD_THREADS) q[k] = sample(s.Tte, s.f32, row * s.ld_te + s.i_star + k);
-  for (int k = threadIdx.x; k < DD_THREADS + m - 1; k += DD_THREADS) {
+  for (int k = threadIdx.x; k < DD_SPAN + m - 1; k += DD_THREADS) {
     const int64_t t = t0 + k;
     seg[k] = t < s.n_tr ? sample(s.Ttr, s.f32, row * s.ld_tr + t) : 0.0;
   }
@@ -165,40 +195,66 @@ __global__ __launch_bounds__(DD_THREADS) void dd_dist(DDState s) {
   for (int k = threadIdx.x; k < m; k += DD_THREADS) q[k] = (q[k] - mq) * iq;  // zero vector when flat
   __syncthreads();
 
-  const int64_t t = t0 + threadIdx.x;
-  bool ok = t < n_sub;
-  if (s.excl > 0) ok = ok && (t - s.i_star >= s.excl || s.i_star - t >= s.excl);
+  const int64_t tb = t0 + (int64_t)threadIdx.x * DD_R;  // the thread's first subsequence
+  bool ok[DD_R];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < DD_R; ++r) {
+    const int64_t t = tb + r;
+    ok[r] = t < n_sub;
+    if (s.excl > 0) ok[r] = ok[r] && (t - s.i_star >= s.excl || s.i_star - t >= s.excl);
+    any = any || ok[r];
+  }
   double best_d = INFINITY, best_i = (double)INT64_MAX;
-  if (ok) {
-    const double* w = seg + threadIdx.x;
-    double a = 0.0;
-    for (int k = 0; k < m; ++k) a += w[k];
-    const double mw = a / m;
-    double v = 0.0;
-    for (int k = 0; k < m; ++k) {
-      const double e = w[k] - mw;
-      v = fma(e, e, v);
-    }
-    const double sw = sqrt(v / m);
+  if (any) {
+    const double* w = seg + threadIdx.x * DD_R;
+    // pass 1: means
+    double S[DD_R];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) S[r] = 0.0;
+    over_windows(w, m, [&](double x, int, int r) { S[r] += x; });
+    double mw[DD_R];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) mw[r] = S[r] / m;
+    // pass 2: variances
+    double V[DD_R];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) V[r] = 0.0;
+    over_windows(w, m, [&](double x, int, int r) {
+      const double e = x - mw[r];
+      V[r] = fma(e, e, V[r]);
+    });
     const double scale_tr = __longlong_as_double((long long)s.scale[p]);
-    const bool wflat = const_tr || sw <= DD_FLAT_REL * scale_tr;
     const bool qflat = iq == 0.0;
-    double dist;
-    if (qflat && wflat) {
-      dist = 0.0;
-    } else if (qflat || wflat) {
-      dist = sqrt((double)m);
-    } else {
-      const double iw = 1.0 / sw;
-      double acc = 0.0;
-      for (int k = 0; k < m; ++k) {
-        const double e = q[k] - (w[k] - mw) * iw;
-        acc = fma(e, e, acc);
-      }
-      dist = sqrt(acc);
+    bool wflat[DD_R];
+    double iw[DD_R];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) {
+      const double sw = sqrt(V[r] / m);
+      wflat[r] = const_tr || sw <= DD_FLAT_REL * scale_tr;
+      iw[r] = wflat[r] ? 0.0 : 1.0 / sw;
     }
-    best_d = dist;
-    best_i = (double)t;
+    // pass 3: distances from explicit differences of the normalised windows
+    double A[DD_R];
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) A[r] = 0.0;
+    over_windows(w, m, [&](double x, int kp, int r) {
+      const double e = q[kp - r] - (x - mw[r]) * iw[r];
+      A[r] = fma(e, e, A[r]);
+    });
+#pragma unroll
+    for (int r = 0; r < DD_R; ++r) {
+      if (!ok[r]) continue;
+      double dist;
+      if (qflat && wflat[r]) dist = 0.0;
+      else if (qflat || wflat[r]) dist = sqrt((double)m);
+      else dist = sqrt(A[r]);
+      const double ti = (double)(tb + r);
+      if (closer(dist, ti, best_d, best_i)) {
+        best_d = dist;
+        best_i = ti;
+      }
+    }
   }
   block_nearest(best_d, best_i, sd, si);
   if (threadIdx.x == 0) s.part[(int64_t)p * s.nblk + blockIdx.x] = make_double2(best_d, best_i);
@@ -264,7 +320,7 @@ using namespace skmp;
 
 extern "C" size_t dim_detect_workspace(int64_t n_train, int32_t n_dims, int32_t m) {
   if (n_train < m || n_dims < 1 || m < 4) return 0;
-  const int64_t nblk = (n_train - m + 1 + DD_THREADS - 1) / DD_THREADS;
+  const int64_t nblk = (n_train - m + 1 + DD_SPAN - 1) / DD_SPAN;
   Carve cv(nullptr, 0);
   int64_t* a;
   unsigned long long* b;
@@ -292,7 +348,7 @@ extern "C" int dim_detect(const void* T_train, int64_t ld_train, int64_t n_train
                "excl > 0 is the self-join setting: the test series must be the train series");
   SKMP_REQUIRE(n_train - m + 1 < ((int64_t)1 << 52), "series too long");
   for (int32_t q = 0; q < n_dims; ++q) SKMP_REQUIRE(dims[q] >= 0 && dims[q] < d, "dimension index out of range");
-  const int64_t nblk = (n_train - m + 1 + DD_THREADS - 1) / DD_THREADS;
+  const int64_t nblk = (n_train - m + 1 + DD_SPAN - 1) / DD_SPAN;
   SKMP_REQUIRE(nblk < (1ll << 31), "series too long");
   Carve cv(workspace, ws_bytes);
   int64_t* dims_dev;
@@ -331,7 +387,7 @@ extern "C" int dim_detect(const void* T_train, int64_t ld_train, int64_t n_train
                      2 * (int64_t)n_dims);
   const int64_t chunks = std::min<int64_t>((std::max(n_train, n_test) + DD_THREADS - 1) / DD_THREADS, 64);
   hipLaunchKernelGGL(dd_scale, dim3((unsigned)n_dims, (unsigned)chunks), dim3(DD_THREADS), 0, st, s);
-  const size_t lds = sizeof(double) * (size_t)(m + DD_THREADS + m - 1);
+  const size_t lds = sizeof(double) * (size_t)(m + DD_SPAN + m - 1);
   hipLaunchKernelGGL(dd_dist, dim3((unsigned)nblk, (unsigned)n_dims), dim3(DD_THREADS), lds, st, s);
   hipLaunchKernelGGL(dd_reduce, dim3((unsigned)n_dims), dim3(DD_THREADS), 0, st, s);
   hipLaunchKernelGGL(dd_pick, dim3(1), dim3(64), 0, st, s);
