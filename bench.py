@@ -15,7 +15,8 @@ n = 2^20, k = 32, m = 256).
 
 Metric: matrix-profile cells per second, cells = k * n^2 / 2 per series per
 step.  Prints ONE JSON line.  ``value`` is the named precision's throughput
-over the K timed steps; ``paths`` repeats the measurement for the FP64 path
+over the K timed steps, each a replay of one step captured in a HIP graph
+(every kernel of the step runs; ``--eager`` times eager calls instead); ``paths`` repeats the measurement for the FP64 path
 (and any other precision asked for) on the same input, with each path's error
 against the FP64 path.  ``roofline`` covers the named path's tile kernel,
 timed with HIP events on the library's stream; ``cpu_baseline`` times the CPU
@@ -84,9 +85,10 @@ def _parse():
     ap.add_argument("--also", default=None,
                     help="comma-separated extra precisions measured into 'paths' (default: fp64 plus, where a "
                          "step takes well under a second, the other mixed forms)")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture one step into a HIP graph and time graph replays (stage timings then come from "
-                         "an extra eager pass)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager steps (the default times replays of one step captured in a HIP graph; "
+                         "stage timings always come from eager steps)")
+    ap.add_argument("--graph", action="store_true", help="the default (kept for old command lines)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB MiB before the steps (reference for HBM byte counters)")
     ap.add_argument("--autotune", action="store_true",
@@ -575,7 +577,7 @@ def main() -> int:
         torch.cuda.synchronize()
         _progress(f"{pr}: {warmup} warmup step(s) done")
         graph = None
-        if args.graph:
+        if not args.eager:
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph):
                 step()
@@ -753,7 +755,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32"}.get(prec, prec),
         "data": "synthetic",
-        "graph": bool(args.graph),
+        "graph": not args.eager,
         "autotuned": tuned or None,
         "config": {"workload": DESCR[args.workload] + (" + add/remove 16 dims and recompute" if upd else ""),
                    "precision": prec, "refresh": refresh, "self_joins_per_step": joins,
