@@ -5,7 +5,9 @@
 // source must outlive the graph and never change.  Every uploaded table is
 // therefore also kept, once per distinct content, in pinned host memory owned
 // by the library for the life of the process (up to kPinnedCap bytes in
-// total), and uploads copy from that immutable copy.  Outside capture a table
+// total, in slabs), and uploads copy from that immutable copy; lookups go
+// through a hash index, so a call's cost does not grow with the number of
+// distinct tables seen (every streaming append has a plan of its own).  Outside capture a table
 // that does not fit any more is copied from the caller's memory as before;
 // under capture (where allocating is not allowed) a table that was never
 // uploaded outside capture is an error, so one eager call with the same
@@ -14,7 +16,7 @@
 #include <string.h>
 
 #include <mutex>
-#include <vector>
+#include <unordered_map>
 
 #include "skmp_common.hpp"
 
@@ -27,9 +29,15 @@ struct Blob {
   void* host;
 };
 constexpr size_t kPinnedCap = size_t(64) << 20;
+// Pinned memory comes in slabs and tables are placed one after the other
+// (256-byte aligned), so caching a new table costs a memcpy, not a pinned
+// allocation; a table larger than a slab gets its own allocation.
+constexpr size_t kSlab = size_t(1) << 20;
 std::mutex g_mu;
-std::vector<Blob> g_blobs;
-size_t g_total = 0;
+std::unordered_multimap<uint64_t, Blob> g_blobs;  // by content hash
+char* g_slab = nullptr;
+size_t g_slab_used = kSlab;
+size_t g_total = 0;  // pinned bytes allocated (slabs and large tables)
 
 // Content hash of a table, 8 bytes per step (a match is confirmed with memcmp,
 // so the hash only has to separate tables quickly).
@@ -48,9 +56,33 @@ uint64_t table_hash(const void* p, size_t n) {
 }
 
 const Blob* find_blob(uint64_t h, const void* src, size_t bytes) {
-  for (const Blob& b : g_blobs)
-    if (b.hash == h && b.bytes == bytes && memcmp(b.host, src, bytes) == 0) return &b;
+  auto range = g_blobs.equal_range(h);
+  for (auto it = range.first; it != range.second; ++it)
+    if (it->second.bytes == bytes && memcmp(it->second.host, src, bytes) == 0) return &it->second;
   return nullptr;
+}
+
+// Pinned space for a new table, nullptr when the cap is reached.
+void* pinned_space(size_t bytes) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (need > kSlab / 4) {  // large: its own allocation
+    if (g_total + need > kPinnedCap) return nullptr;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, need, hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_total += need;
+    return p;
+  }
+  if (g_slab_used + need > kSlab) {
+    if (g_total + kSlab > kPinnedCap) return nullptr;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, kSlab, hipHostMallocDefault) != hipSuccess) return nullptr;
+    g_slab = static_cast<char*>(p);
+    g_slab_used = 0;
+    g_total += kSlab;
+  }
+  void* p = g_slab + g_slab_used;
+  g_slab_used += need;
+  return p;
 }
 }  // namespace
 
@@ -66,13 +98,10 @@ int upload_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
   const uint64_t h = table_hash(src, bytes);
   std::lock_guard<std::mutex> lk(g_mu);
   const Blob* hit = find_blob(h, src, bytes);
-  if (!hit && !capturing && g_total + bytes <= kPinnedCap) {
-    void* p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess && p) {
+  if (!hit && !capturing) {
+    if (void* p = pinned_space(bytes)) {
       memcpy(p, src, bytes);
-      g_blobs.push_back({h, bytes, p});
-      g_total += bytes;
-      hit = &g_blobs.back();
+      hit = &g_blobs.emplace(h, Blob{h, bytes, p})->second;
     }
   }
   if (hit) {
