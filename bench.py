@@ -431,7 +431,7 @@ def _bench_stream(args, prec: str, refresh: int) -> int:
 
     batches = {}
     for a in [int(x) for x in args.batch_list.split(",") if x]:
-        reps = max(1, min(args.steps, (n - n0) // a))
+        reps = max(1, min(max(args.steps, 100), (n - n0) // a))
         restore()
         append(n0, a)  # warm-up (plans, workspace)
         torch.cuda.synchronize()
@@ -445,10 +445,20 @@ def _bench_stream(args, prec: str, refresh: int) -> int:
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - t0) * 1e3)
             cur += a
+        # the stage split, from a pass with the stage timers on
         restore()
         skmp.timing_enable(True)
         for st in skmp.TIMERS:
             skmp.timing_read(st, reset=True)
+        cur = n0
+        for _ in range(reps):
+            append(cur, a)
+            cur += a
+        torch.cuda.synchronize()
+        skmp.timing_enable(False)
+        stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
+        # pipelined appends (no timers)
+        restore()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cur = n0
@@ -457,8 +467,6 @@ def _bench_stream(args, prec: str, refresh: int) -> int:
             cur += a
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
-        skmp.timing_enable(False)
-        stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
         # the grown profile against a batch join of the same samples (same precision)
         Pb, Ib = skmp.mp_selfjoin(R[:, :cur], [0, cur], k, m, excl, prec=prec, refresh=refresh)
         torch.cuda.synchronize()
