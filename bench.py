@@ -8,9 +8,9 @@ top_discords (top 10 per series).  Default workload: the water-treatment-shaped
 series, d = 51 (25 AR(1) sensors, 26 on/off actuators), n = 50,000, Gaussian
 sketch k = 8, m = 100, exclusion zone 25, three planted discords; its named
 precision is the FP32 path with an exact FP64 refresh every 256 rows.  Other
-workloads: c0 (small FP64 case), c2 (transportation-shaped, d = 1024,
-n = 131,072, m = 288), c3 (4096 merchant-shaped series, d = 32, lengths
-U[2048, 65536], FP32 input, k = 4, m = 64, generated on the GPU), c4 (d = 256,
+workloads: random-walk-small (small FP64 case), transportation (d = 1024,
+n = 131,072, m = 288), merchant-batch (4096 merchant-shaped series, d = 32, lengths
+U[2048, 65536], FP32 input, k = 4, m = 64, generated on the GPU), large-series (d = 256,
 n = 2^20, k = 32, m = 256).
 
 Metric: matrix-profile cells per second, cells = k * n^2 / 2 per series per
@@ -60,13 +60,13 @@ CELL_PEAK_BASIS = {
             "9.83e12 cells/s, i.e. 5.90e13 of the cell's lane-ops/s",
 }
 MFMA_16BIT_PEAK = 2.5e15  # dense BF16 / FP16 matrix-core peak of MI355X, FLOP/s
-NAMED = {"c0": ("fp64", 0), "c1": ("fp32", 256), "c2": ("bf16x3", 0), "c3": ("fp32", 256), "c4": ("fp16x3", 0)}
+NAMED = {"random-walk-small": ("fp64", 0), "water-treatment": ("fp32", 256), "transportation": ("bf16x3", 0), "merchant-batch": ("fp32", 256), "large-series": ("fp16x3", 0)}
 DESCR = {
-    "c0": "random-walk+sine d=8 n=4096 sum sketch k=1 m=64 excl=16",
-    "c1": "water-treatment-shaped d=51 n=50000 gaussian k=8 m=100 excl=25",
-    "c2": "transportation-shaped d=1024 n=131072 gaussian k=16 m=288 excl=72",
-    "c3": "merchant-shaped batch 4096 series d=32 L~U[2048,65536] fp32 input gaussian k=4 m=64 excl=16",
-    "c4": "random-walk+sine d=256 n=1048576 gaussian k=32 m=256 excl=64",
+    "random-walk-small": "random-walk+sine d=8 n=4096 sum sketch k=1 m=64 excl=16",
+    "water-treatment": "water-treatment-shaped d=51 n=50000 gaussian k=8 m=100 excl=25",
+    "transportation": "transportation-shaped d=1024 n=131072 gaussian k=16 m=288 excl=72",
+    "merchant-batch": "merchant-shaped batch 4096 series d=32 L~U[2048,65536] fp32 input gaussian k=4 m=64 excl=16",
+    "large-series": "random-walk+sine d=256 n=1048576 gaussian k=32 m=256 excl=64",
 }
 KERNELS = {"fp64": "sj_fp64_kernel<8,256,2,2,false>", "fp32": "sj_fp32_kernel<16,256,2,3>",
            "bf16x3": "sj_mfma_kernel<BF16X3>", "fp16x3": "sj_mfma_kernel<FP16X3>"}
@@ -77,7 +77,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="water-treatment", choices=["random-walk-small", "water-treatment", "transportation", "merchant-batch", "large-series"])
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16x3", "fp16x3"],
                     help="headline precision (default: the one the workload names)")
     ap.add_argument("--refresh", type=int, default=None,
@@ -277,8 +277,8 @@ def _bench_ab(args, prec: str, refresh: int) -> int:
 
     import datagen
     import paper_2311_03393_amd as skmp
-    if args.workload == "c3":
-        print("the AB-join measurement takes a single-series workload (c0, c1, c2, c4)", file=sys.stderr)
+    if args.workload == "merchant-batch":
+        print("the AB-join measurement takes a single-series workload (random-walk-small, water-treatment, transportation, large-series)", file=sys.stderr)
         return 2
     if prec not in ("fp64", "fp32"):
         prec, refresh = "fp32", 0
@@ -380,8 +380,8 @@ def _bench_stream(args, prec: str, refresh: int) -> int:
 
     import datagen
     import paper_2311_03393_amd as skmp
-    if args.workload == "c3":
-        print("the streaming measurement takes a single-series workload (c0, c1, c2, c4)", file=sys.stderr)
+    if args.workload == "merchant-batch":
+        print("the streaming measurement takes a single-series workload (random-walk-small, water-treatment, transportation, large-series)", file=sys.stderr)
         return 2
     if prec not in ("fp64", "fp32"):
         prec, refresh = "fp32", 0
@@ -528,8 +528,8 @@ def main() -> int:
         return _experiment_random_walks(args)
 
     dev = torch.device("cuda:0")
-    if args.workload == "c3":
-        w, T = datagen.make_c3_device(torch, dev)
+    if args.workload == "merchant-batch":
+        w, T = datagen.make_merchant_batch_device(torch, dev)
     else:
         w = datagen.make(args.workload)
         T = torch.from_numpy(w.T).to(dev)
@@ -549,7 +549,7 @@ def main() -> int:
            torch.empty((n_series,), dtype=torch.int32, device=dev))
     # the large single-series workload also adds and removes dimensions and
     # recomputes the profile of the changed groups inside every step
-    upd = w.update if args.workload == "c4" else None
+    upd = w.update if args.workload == "large-series" else None
     joins = 2 if upd else 1
     if upd:
         T_add = torch.from_numpy(upd["T_add"]).to(dev)
@@ -651,7 +651,7 @@ def main() -> int:
         torch.cuda.synchronize()
     also = args.also
     if also is None:
-        also = "fp64" if args.workload in ("c3", "c4") else "fp64,fp32,bf16x3,fp16x3"
+        also = "fp64" if args.workload in ("merchant-batch", "large-series") else "fp64,fp32,bf16x3,fp16x3"
     head = measure(prec, refresh, args.steps, args.warmup)
     paths = {f"{prec}" + (f"_refresh{refresh}" if refresh else ""): head}
     for extra in [x for x in also.split(",") if x and x != prec]:

@@ -11,27 +11,27 @@ layout the C-ABI consumes.
 
 Workload recipes (seeded numpy PCG64; data seed and sketch seed are recorded):
 
-* ``c0``  random walk + sine per dimension, one planted chirp burst, d=8,
+* ``random-walk-small``  random walk + sine per dimension, one planted chirp burst, d=8,
           n=4096, sum sketch k=1, m=64, excl=16 (Fig. 1 toy and Section IV-A
           random-walk generator).
-* ``c1``  water-treatment shaped (Section IV-D, SWaT has 51 sensors and
+* ``water-treatment``  water-treatment shaped (Section IV-D, SWaT has 51 sensors and
           actuators): 25 AR(1) sensors + 26 on/off actuators, d=51, n=50,000,
           three planted discords of length 100, Gaussian sketch k=8, m=100.
-* ``c2``  transportation shaped (Section IV-B, daily periodicity): d=1024,
+* ``transportation``  transportation shaped (Section IV-B, daily periodicity): d=1024,
           n=131,072, period 288, ten planted flattened/inverted days,
           Gaussian k=16, m=288.
-* ``c3``  merchant shaped batch (Section I motivation, Section IV-C):
+* ``merchant-batch``  merchant shaped batch (Section I motivation, Section IV-C):
           4096 series, d=32, lengths U{2048..65536}, smoothed Poisson(3)
           counts in float32, spike bursts in 1% of series, Gaussian k=4, m=64.
-* ``c4``  large single series, random walk + sine, d=256, n=2^20, five planted
+* ``large-series``  large single series, random walk + sine, d=256, n=2^20, five planted
           discords of length 256, Gaussian k=32, m=256, plus an add/remove of
           16 dimensions (Section III-C).
 
 ``scale`` shrinks n (and the batch) so the same recipe yields small test cases.
 
-``make_c3_device`` draws the full-size ``c3`` batch (4.4e9 values) on a GPU
+``make_merchant_batch_device`` draws the full-size merchant batch (4.4e9 values) on a GPU
 with torch's seeded generator instead of numpy (same recipe; the values differ
-from ``make_c3``'s).  Checks that need the input on the host copy the series
+from ``make_merchant_batch``'s).  Checks that need the input on the host copy the series
 they use back from the device tensor.
 """
 from __future__ import annotations
@@ -41,7 +41,7 @@ from typing import List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["Workload", "make", "make_c3_device", "random_walk_sine", "tiny_series", "CONFIGS"]
+__all__ = ["Workload", "make", "make_merchant_batch_device", "random_walk_sine", "tiny_series", "WORKLOADS"]
 
 
 @dataclass
@@ -58,7 +58,7 @@ class Workload:
     data_seed: int
     precision: str                # path the recipe names: fp64 | fp32 | bf16x3 | fp16x3
     planted: List[Tuple[int, int, int, int]] = field(default_factory=list)  # (series, dim, offset, length)
-    update: Optional[dict] = None  # c4: {"T_add", "add_ids", "rem_ids"}
+    update: Optional[dict] = None  # large-series: {"T_add", "add_ids", "rem_ids"}
 
     @property
     def d(self) -> int:
@@ -118,19 +118,19 @@ def _chirp_burst(x: np.ndarray, o: int, length: int, amp_sigmas: float) -> None:
     x[o:o + length] += amp_sigmas * s * np.sin(2.0 * np.pi * (t / 32.0 + t * t / (16.0 * length)))
 
 
-def make_c0(scale: float = 1.0, data_seed: int = 1000, sketch_seed: int = 2000) -> Workload:
+def make_random_walk_small(scale: float = 1.0, data_seed: int = 1000, sketch_seed: int = 2000) -> Workload:
     rng = _rng(data_seed)
     d, m = 8, 64
     n = max(4 * m, int(4096 * scale))
     T = random_walk_sine(rng, d, n)
     o = int(rng.integers(m, n - 2 * m))
     _chirp_burst(T[0], o, m, 2.0)
-    return Workload("c0", np.ascontiguousarray(T), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
+    return Workload("random-walk-small", np.ascontiguousarray(T), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
                     k=1, kind="sum", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="fp64", planted=[(0, 0, o, m)])
 
 
-def make_c1(scale: float = 1.0, data_seed: int = 1001, sketch_seed: int = 2001) -> Workload:
+def make_water_treatment(scale: float = 1.0, data_seed: int = 1001, sketch_seed: int = 2001) -> Workload:
     rng = _rng(data_seed)
     d_sens, d_act, m = 25, 26, 100
     n = max(8 * m, int(50_000 * scale))
@@ -158,12 +158,12 @@ def make_c1(scale: float = 1.0, data_seed: int = 1001, sketch_seed: int = 2001) 
             t = np.arange(m)
             X[dim, o:o + m] = ((t // 10) % 2).astype(np.float64)  # square-wave chatter, period 20
         planted.append((0, dim, o, m))
-    return Workload("c1", np.ascontiguousarray(X), np.array([0, n], np.int64), np.arange(d_sens + d_act, dtype=np.int64),
+    return Workload("water-treatment", np.ascontiguousarray(X), np.array([0, n], np.int64), np.arange(d_sens + d_act, dtype=np.int64),
                     k=8, kind="gauss", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="fp32", planted=planted)
 
 
-def make_c2(scale: float = 1.0, data_seed: int = 1002, sketch_seed: int = 2002) -> Workload:
+def make_transportation(scale: float = 1.0, data_seed: int = 1002, sketch_seed: int = 2002) -> Workload:
     rng = _rng(data_seed)
     P, m = 288, 288
     d = max(8, int(1024 * min(1.0, scale * 4)))
@@ -187,12 +187,12 @@ def make_c2(scale: float = 1.0, data_seed: int = 1002, sketch_seed: int = 2002) 
         else:
             X[dim, o:o + m] = 2.0 * mu - w                        # inverted day
         planted.append((0, dim, o, m))
-    return Workload("c2", np.ascontiguousarray(X), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
+    return Workload("transportation", np.ascontiguousarray(X), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
                     k=16, kind="gauss", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="bf16x3", planted=planted)
 
 
-def make_c3(scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
+def make_merchant_batch(scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
             n_series: Optional[int] = None) -> Workload:
     rng = _rng(data_seed)
     d, m = 32, 64
@@ -224,11 +224,11 @@ def make_c3(scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
         cs = np.cumsum(pad, axis=1)
         cs = np.concatenate([np.zeros((d, 1)), cs], axis=1)
         T[:, a:b] = ((cs[:, 5:] - cs[:, :-5]) / 5.0).astype(np.float32)
-    return Workload("c3", T, offsets, np.arange(d, dtype=np.int64), k=4, kind="gauss", m=m, excl=m // 4,
+    return Workload("merchant-batch", T, offsets, np.arange(d, dtype=np.int64), k=4, kind="gauss", m=m, excl=m // 4,
                     sketch_seed=sketch_seed, data_seed=data_seed, precision="fp32", planted=planted)
 
 
-def make_c4(scale: float = 1.0, data_seed: int = 1004, sketch_seed: int = 2004) -> Workload:
+def make_large_series(scale: float = 1.0, data_seed: int = 1004, sketch_seed: int = 2004) -> Workload:
     rng = _rng(data_seed)
     d, m, n_upd = 256, 256, 16
     n = max(8 * m, int((1 << 20) * scale))
@@ -244,15 +244,15 @@ def make_c4(scale: float = 1.0, data_seed: int = 1004, sketch_seed: int = 2004) 
     rem_ids = np.sort(rng.choice(free, size=n_upd, replace=False)).astype(np.int64)
     T_add = random_walk_sine(_rng(data_seed + 500), n_upd, n)
     add_ids = np.arange(d, d + n_upd, dtype=np.int64)
-    return Workload("c4", np.ascontiguousarray(T), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
+    return Workload("large-series", np.ascontiguousarray(T), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
                     k=32, kind="gauss", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="fp16x3", planted=planted,
                     update={"T_add": np.ascontiguousarray(T_add), "add_ids": add_ids, "rem_ids": rem_ids})
 
 
-def make_c3_device(torch, device, scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
+def make_merchant_batch_device(torch, device, scale: float = 1.0, data_seed: int = 1003, sketch_seed: int = 2003,
                    n_series: Optional[int] = None):
-    """The c3 recipe drawn on ``device``: returns (Workload with T = None, T as a
+    """The merchant-batch recipe drawn on ``device``: returns (Workload with T = None, T as a
     d x N float32 device tensor).  Lengths, spiky series and spike positions come
     from numpy (seeded); the Poisson counts from torch's generator seeded with
     data_seed; the 5-tap box filter replicates each series' edge samples."""
@@ -304,16 +304,16 @@ def make_c3_device(torch, device, scale: float = 1.0, data_seed: int = 1003, ske
     T[:, last] = (3 * y0 + y1 + y2) / 5.0
     T[:, last - 1] = (2 * y0 + y1 + y2 + y3) / 5.0
     del cnt
-    w = Workload("c3", None, offsets, np.arange(d, dtype=np.int64), k=4, kind="gauss", m=m, excl=m // 4,
+    w = Workload("merchant-batch", None, offsets, np.arange(d, dtype=np.int64), k=4, kind="gauss", m=m, excl=m // 4,
                  sketch_seed=sketch_seed, data_seed=data_seed, precision="fp32", planted=planted)
     return w, T
 
 
-CONFIGS = {"c0": make_c0, "c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4}
+WORKLOADS = {"random-walk-small": make_random_walk_small, "water-treatment": make_water_treatment, "transportation": make_transportation, "merchant-batch": make_merchant_batch, "large-series": make_large_series}
 
 
 def make(name: str, scale: float = 1.0, **kw) -> Workload:
-    return CONFIGS[name](scale=scale, **kw)
+    return WORKLOADS[name](scale=scale, **kw)
 
 
 def tiny_series(seed: int, d: int, n: int, kind: str = "rw") -> np.ndarray:

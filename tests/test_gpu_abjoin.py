@@ -111,7 +111,7 @@ def test_abjoin_water_treatment_halves_sampled(prec, c_oracle):
     """Test half vs train half of the water-treatment workload (d = 51, k = 8, m = 100)."""
     import torch
     import paper_2311_03393_amd as skmp
-    w = datagen.make("c1")
+    w = datagen.make("water-treatment")
     dev = torch.device("cuda:0")
     T = torch.from_numpy(w.T).to(dev)
     half = w.T.shape[1] // 2
@@ -119,7 +119,7 @@ def test_abjoin_water_treatment_halves_sampled(prec, c_oracle):
     Ra, _ = skmp.sketch_build(T[:, half:].contiguous(), [0, w.T.shape[1] - half], w.k, w.kind, w.sketch_seed,
                               dim_ids=w.dim_ids)
     Rb, _ = skmp.sketch_build(T[:, :half].contiguous(), [0, half], w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
-    _say("abjoin c1 halves", prec)
+    _say("abjoin water-treatment halves", prec)
     PA, IA = skmp.mp_abjoin(Ra, Rb, w.k, w.m, prec=prec, refresh=256 if prec == "fp32" else 0)
     torch.cuda.synchronize()
     m = w.m

@@ -36,8 +36,8 @@ def batch():
     import paper_2311_03393_amd as skmp
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
-    w, T = datagen.make_c3_device(torch, dev)
-    _say("c3 full size", T.shape, len(w.offsets) - 1, "series")
+    w, T = datagen.make_merchant_batch_device(torch, dev)
+    _say("merchant batch full size", T.shape, len(w.offsets) - 1, "series")
     R, _ = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
     torch.cuda.synchronize()
     lens = np.diff(w.offsets)
@@ -72,7 +72,7 @@ def test_c3_selfjoin_sampled_rows_and_top10(batch, c_oracle, prec):
     import paper_2311_03393_amd as skmp
     w, T, R, pick, host = batch
     m, excl, k = w.m, w.excl, w.k
-    _say("c3 selfjoin", prec)
+    _say("merchant batch selfjoin", prec)
     P, I = skmp.mp_selfjoin(R, w.offsets, k, m, excl, prec=prec, refresh=256 if prec == "fp32" else 0)
     idx, grp, score, nf = skmp.top_discords(P, w.offsets, k, m, 10)
     torch.cuda.synchronize()

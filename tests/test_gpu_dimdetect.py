@@ -109,7 +109,7 @@ def test_dim_detect_all_excluded_and_flat_query():
     _check(s2.cpu().numpy(), nn2.cpu().numpy(), int(best2.item()), ref, m, fp64_tol(m))
 
 
-@pytest.mark.parametrize("workload,kind,k", [("c0", "count", 3), ("c1", "gauss", 8)])
+@pytest.mark.parametrize("workload,kind,k", [("random-walk-small", "count", 3), ("water-treatment", "gauss", 8)])
 def test_two_phase_detection(workload, kind, k):
     """Algorithm 2 on the sketch finds (i*, g*); Algorithm 3 on g*'s dimensions
     (self-join setting) matches the oracle's scores at that i*."""

@@ -33,8 +33,8 @@ def large():
     import paper_2311_03393_amd as skmp
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
-    w = datagen.make("c4")
-    _say("c4 full size", w.T.shape)
+    w = datagen.make("large-series")
+    _say("large series full size", w.T.shape)
     T = torch.from_numpy(w.T).to(dev)
     R, stats = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
     torch.cuda.synchronize()
@@ -70,7 +70,7 @@ def test_c4_recomputed_profile_sampled(large, c_oracle, prec):
     import paper_2311_03393_amd as skmp
     w, R, _, changed = large
     m, excl, k = w.m, w.excl, w.k
-    _say("c4 selfjoin", prec)
+    _say("large series selfjoin", prec)
     P, I = skmp.mp_selfjoin(R, w.offsets, k, m, excl, prec=prec, refresh=256 if prec == "fp32" else 0,
                             group_mask=changed)
     torch.cuda.synchronize()

@@ -48,20 +48,20 @@ def _run_selfjoin(torch, dev, R_np, offsets, k, m, excl, prec="fp64", refresh=0)
 
 
 # ------------------------------------------------------------------ sketch
-@pytest.mark.parametrize("case", ["c0", "c1_small", "count", "batch_f32"])
+@pytest.mark.parametrize("case", ["random-walk-small", "water_treatment_small", "count", "batch_f32"])
 def test_sketch_build_parity(dev, case):
     import torch
     import paper_2311_03393_amd as skmp
     _say("sketch parity", case)
-    if case == "c0":
-        w = datagen.make("c0")
-    elif case == "c1_small":
-        w = datagen.make("c1", scale=0.1)
+    if case == "random-walk-small":
+        w = datagen.make("random-walk-small")
+    elif case == "water_treatment_small":
+        w = datagen.make("water-treatment", scale=0.1)
     elif case == "count":
-        w = datagen.make("c0")
+        w = datagen.make("random-walk-small")
         w.kind, w.k = "count", 3
     else:
-        w = datagen.make("c3", scale=0.05, n_series=6)
+        w = datagen.make("merchant-batch", scale=0.05, n_series=6)
     T = _to_dev(torch, w.T, dev)
     R, stats = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
     torch.cuda.synchronize()
@@ -219,7 +219,7 @@ def test_selfjoin_fp64_matches_oracle(dev, c_oracle, n, m, excl, k, seed):
 def test_selfjoin_c0_and_top10(dev, c_oracle):
     import torch
     import paper_2311_03393_amd as skmp
-    w = datagen.make("c0")
+    w = datagen.make("random-walk-small")
     R_np, _, _, _ = O.build(w.T, w.kind, w.k, w.sketch_seed)
     R = _to_dev(torch, R_np, dev)
     P, I = skmp.mp_selfjoin(R, w.offsets, w.k, w.m, w.excl)
@@ -363,7 +363,7 @@ def test_top_discords_block_maxima_edge_cases(dev, case):
 def test_update_dims_matches_rebuild(dev, c_oracle):
     import torch
     import paper_2311_03393_amd as skmp
-    w = datagen.make("c4", scale=1.0 / 256)           # d = 256, n = 4096, same recipe as the large case
+    w = datagen.make("large-series", scale=1.0 / 256)           # d = 256, n = 4096, same recipe as the large case
     n = w.T.shape[1]
     ids = w.dim_ids
     rem = w.update["rem_ids"]
@@ -413,8 +413,8 @@ def test_update_count_sketch_changed_groups(dev):
 def test_selfjoin_c1_full_size_sampled_and_certified(dev, c_oracle):
     import torch
     import paper_2311_03393_amd as skmp
-    w = datagen.make("c1")
-    _say("c1 full size", w.T.shape)
+    w = datagen.make("water-treatment")
+    _say("water-treatment full size", w.T.shape)
     T = _to_dev(torch, w.T, dev)
     R, _ = skmp.sketch_build(T, w.offsets, w.k, w.kind, w.sketch_seed, dim_ids=w.dim_ids)
     P, I = skmp.mp_selfjoin(R, w.offsets, w.k, w.m, w.excl)
@@ -446,7 +446,7 @@ def test_selfjoin_c1_full_size_sampled_and_certified(dev, c_oracle):
         # near ties: accept an eps-greedy sequence on the exact values
         for (i, g, s), (io, go, so) in zip(gpu, picks):
             assert i in exact and exact[i][0] >= so - 2 * tol
-    _say("c1 top10", [i for i, _, _ in gpu])
+    _say("water-treatment top10", [i for i, _, _ in gpu])
 
 
 # ------------------------------------------------------- mixed precisions

@@ -366,8 +366,8 @@ def test_top_discords_ordering_and_masking():
     assert (i, g, s) == out[0]
 
 
-def test_planted_discord_is_recovered_on_c0(c_oracle):
-    w = datagen.make("c0")
+def test_planted_discord_is_recovered_on_random_walk_small(c_oracle):
+    w = datagen.make("random-walk-small")
     R, S, mu, sd = O.build(w.T, w.kind, w.k, w.sketch_seed)
     P, I = c_oracle.profile(R[0], w.m, w.excl)
     top = O.top_discords(P[None], w.m, 10)
