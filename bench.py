@@ -68,7 +68,7 @@ DESCR = {
     "merchant-batch": "merchant-shaped batch 4096 series d=32 L~U[2048,65536] fp32 input gaussian k=4 m=64 excl=16",
     "large-series": "random-walk+sine d=256 n=1048576 gaussian k=32 m=256 excl=64",
 }
-KERNELS = {"fp64": "sj_fp64_kernel<8,256,2,2,false>", "fp32": "sj_fp32_kernel<16,256,2,3>",
+KERNELS = {"fp64": "sj_fp64_kernel<8,256,2,2,false>", "fp32": "sj_fp32_kernel<16,256,2,4>",
            "bf16x3": "sj_mfma_kernel<BF16X3>", "fp16x3": "sj_mfma_kernel<FP16X3>"}
 
 

@@ -24,9 +24,9 @@
 // conflicts.  Every TL steps the rows and columns that no later step of the
 // unit can reach are flushed into the global key arrays with 64-bit atomic
 // max; the others stay in LDS.  A work unit is one strip of S steps of one
-// band of one (series, group); the queue hands units out dynamically.  The
-// FP32 kernel (below) walks the same geometry; the BF16x3 / FP16x3 MFMA
-// tiles are in selfjoin_mixed.hip.
+// band of one (series, group); block b starts with unit b, a shared counter
+// hands out the rest.  The FP32 kernel (below) walks the same geometry; the
+// BF16x3 / FP16x3 MFMA tiles are in selfjoin_mixed.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -282,22 +282,25 @@ __device__ __forceinline__ unsigned long long kbits(double k) { return (unsigned
 // doubles); every lane then reads its windows from LDS.  Diagonals that end
 // before row rr (j0 + q >= n_cols) read clamped samples and are zeroed.  Must be
 // called by all 64 lanes with the same u.
-template <int C>
-constexpr int seed_chunk() { return (128 / C) * C; }
-template <int C>
-constexpr int seed_stage_len() { return 64 + seed_chunk<C>() + 64 * C + seed_chunk<C>(); }
+// MCH is a multiple of C: 128 samples by default; 96 where the workgroups of a
+// 4-wave-per-SIMD FP32 variant (16 per CU) must each fit in 10 KB of LDS.
+template <int C, int WPE = 0>
+constexpr int seed_chunk() { return ((WPE >= 4 && C == 16 ? 96 : 128) / C) * C; }
+template <int C, int MCH = seed_chunk<C>()>
+constexpr int seed_stage_len() { return 64 + MCH + 64 * C + MCH; }
 
 // LDS of the FP32 tile kernel's workgroup: the row and column key partials
 // (NROW + NCOL keys) and the exact-seed stage share one buffer, since the
 // stage is only used at the start of a work unit, before the walk touches the
 // keys (refill_keys empties them again).  The workgroup then needs the larger
-// of the two (10.5 KB instead of 16.75 KB at C = 16), so LDS no longer caps the
-// occupancy below the 3 waves per SIMD the register budget allows.
-template <typename K, int NROW, int NCOL, int C>
+// of the two (10.5 KB instead of 16.75 KB at C = 16; 10 KB with MCH = 96), so
+// LDS does not cap the occupancy below what the register budget allows (3 or 4
+// waves per SIMD).
+template <typename K, int NROW, int NCOL, int C, int MCH>
 constexpr int tile_lds_bytes() {
-  return (int)sizeof(K) * (NROW + NCOL) > (int)sizeof(double) * seed_stage_len<C>()
+  return (int)sizeof(K) * (NROW + NCOL) > (int)sizeof(double) * seed_stage_len<C, MCH>()
              ? (int)sizeof(K) * (NROW + NCOL)
-             : (int)sizeof(double) * seed_stage_len<C>();
+             : (int)sizeof(double) * seed_stage_len<C, MCH>();
 }
 
 template <typename K>
@@ -307,12 +310,11 @@ __device__ __forceinline__ void refill_keys(K* keys, int count, K empty, int t) 
   __syncthreads();
 }
 
-template <int C>
+template <int C, int MCH = seed_chunk<C>()>
 __device__ __forceinline__ void exact_seeds(double* stage, const double* __restrict__ r, const double* __restrict__ mu,
                                             const double* __restrict__ rc, const double* __restrict__ muc, int u,
                                             int db, int t, int n_cols, int nlast, int nlast_c, int m,
                                             double (&acc)[C]) {
-  constexpr int MCH = seed_chunk<C>();
   double* srow = stage;
   double* scol = stage + 64 + MCH;
   const int rr = max(u - t, 0);
@@ -331,17 +333,24 @@ __device__ __forceinline__ void exact_seeds(double* stage, const double* __restr
     for (int i = t; i < 64 * C + MCH; i += 64) scol[i] = rc[min(cbase + x0 + i, nlast_c)];
     __syncthreads();
     const int xe = min(MCH, m - x0);
-    for (int xx = 0; xx < xe; xx += C) {
+    int xx = 0;
+    for (; xx + C <= xe; xx += C) {
       double w[2 * C - 1];
 #pragma unroll
       for (int k = 0; k < 2 * C - 1; ++k) w[k] = scol[co + xx + k];
 #pragma unroll
       for (int dx = 0; dx < C; ++dx) {
-        const double a = (xx + dx < xe) ? srow[ro + xx + dx] - mr : 0.0;
+        const double a = srow[ro + xx + dx] - mr;
         sa += a;
 #pragma unroll
         for (int q = 0; q < C; ++q) acc[q] = fma(a, w[dx + q], acc[q]);
       }
+    }
+    for (; xx < xe; ++xx) {  // the last m mod C samples, one at a time (same summation order)
+      const double a = srow[ro + xx] - mr;
+      sa += a;
+#pragma unroll
+      for (int q = 0; q < C; ++q) acc[q] = fma(a, scol[co + xx + q], acc[q]);
     }
   }
 #pragma unroll
@@ -551,11 +560,15 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
   const int m = st.m;
 
-  for (;;) {
-    unsigned int unit = 0;
-    if (t == 0) unit = atomicAdd(st.counter, 1u);
-    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
-    if ((int64_t)unit >= st.total_units) break;
+  // work queue: the block's first unit is its own index (no contention on the
+  // queue head while the grid fills the chip); each later unit is the counter's
+  // value plus the grid size, taken when the previous unit is done
+  auto take = [&]() -> unsigned int {
+    unsigned int u = 0;
+    if (t == 0) u = atomicAdd(st.counter, 1u);
+    return __builtin_amdgcn_readfirstlane(__shfl(u, 0)) + gridDim.x;
+  };
+  for (unsigned int unit = blockIdx.x; (int64_t)unit < st.total_units; unit = take()) {
     const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
     const SeriesPlan sp = load_plan(st, s);
     const int64_t local = (int64_t)unit - sp.unit_base;
@@ -744,7 +757,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   constexpr uint32_t LMAX = (1u << LBITS) - 1;
   static_assert(TL % C == 0, "tile length must be a multiple of C");
   static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
-  __shared__ __align__(16) uint32_t lds[tile_lds_bytes<uint32_t, NROW, NCOL, C>() / 4];
+  constexpr int MCH = seed_chunk<C, WPE>();
+  __shared__ __align__(16) uint32_t lds[tile_lds_bytes<uint32_t, NROW, NCOL, C, MCH>() / 4];
   uint32_t* rowk = lds;
   uint32_t* colk = lds + NROW;
   double* sseed = reinterpret_cast<double*>(lds);
@@ -756,11 +770,15 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
   const int m = st.m;
 
-  for (;;) {
-    unsigned int unit = 0;
-    if (t == 0) unit = atomicAdd(st.counter, 1u);
-    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
-    if ((int64_t)unit >= st.total_units) break;
+  // work queue: the block's first unit is its own index (no contention on the
+  // queue head while the grid fills the chip); each later unit is the counter's
+  // value plus the grid size, taken when the previous unit is done
+  auto take = [&]() -> unsigned int {
+    unsigned int u = 0;
+    if (t == 0) u = atomicAdd(st.counter, 1u);
+    return __builtin_amdgcn_readfirstlane(__shfl(u, 0)) + gridDim.x;
+  };
+  for (unsigned int unit = blockIdx.x; (int64_t)unit < st.total_units; unit = take()) {
     const int s = uni(find_series(st.plan, st.n_series, (int64_t)unit, &SeriesPlan::unit_base));
     const SeriesPlan sp = load_plan(st, s);
     const int64_t local = (int64_t)unit - sp.unit_base;
@@ -792,7 +810,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     LaneStateF<C> ls;
     {  // exact FP64 seeds, rounded once to FP32
       double acc[C];
-      exact_seeds<C>(sseed, r, mu, rc, muc, u_begin, db, t, n_cols, (int)sp.n - 1, (int)sp.cn - 1, m, acc);
+      exact_seeds<C, MCH>(sseed, r, mu, rc, muc, u_begin, db, t, n_cols, (int)sp.n - 1, (int)sp.cn - 1, m, acc);
 #pragma unroll
       for (int q = 0; q < C; ++q) ls.Cq[q] = (float)acc[q];
     }
@@ -1234,7 +1252,7 @@ static void launch_fp32(dim3 grid, hipStream_t st, const SJState& s) {
 static const Fp64Variant kFp32Variants[] = {
     SKMP_FP32_V(8, 1, 2), SKMP_FP32_V(16, 1, 2), SKMP_FP32_V(8, 1, 3), SKMP_FP32_V(12, 1, 2), SKMP_FP32_V(8, 2, 3),
     SKMP_FP32_V(16, 2, 2), SKMP_FP32_V(16, 1, 3), SKMP_FP32_V(16, 2, 3), SKMP_FP32_V(2, 2, 4),
-    SKMP_FP32_V(4, 2, 4),
+    SKMP_FP32_V(4, 2, 4), SKMP_FP32_V(16, 2, 4),
 };
 #undef SKMP_FP32_V
 constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
@@ -1247,7 +1265,10 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 // window count), or by the built-in defaults.  FP32 units restart from an
 // exact FP64 seed, so their strip is always the refresh period.
 constexpr int kDefaultFp64Variant = 11;  // C = 8, prefetch 2, register column windows (fastest measured)
-constexpr int kDefaultFp32Variant = 7;  // C = 16, prefetch 2, 3 waves per SIMD (165 VGPRs, 10.5 KB LDS; fastest measured)
+// C = 16, prefetch 2, 4 waves per SIMD (128 VGPRs, the spills outside the step
+// loop; 10 KB LDS): 2 % faster than 3 waves per SIMD on the water-treatment
+// join, 1 % on long series (measured)
+constexpr int kDefaultFp32Variant = 10;
 static const int kTuneStrips[] = {1024, 2048, 4096};
 // The narrowest bands (C = 6 in FP64, C = 8 in FP32), for short appends.
 constexpr int kNarrowFp64Variant = 5;
