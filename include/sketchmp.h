@@ -167,6 +167,12 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  * is <= 1e-10 * max|R^(g)| over its series is flat and normalises to the zero
  * vector (dist(flat, flat) = 0, dist(flat, other) = sqrt(m)).  Reported P values
  * are recomputed in FP64 from explicit differences for the reported neighbour.
+ * SKMP_EINVAL (message in skmp_last_error) when the join needs more than
+ * 2^32 - 2^20 work units (groups x bands of 64 C diagonals x strips of
+ * `refresh` rows, C = 16 in FP32 and 8 in FP64; one series of 12 million
+ * windows with k = 8 at refresh 256 is about that): split the groups over
+ * calls (group_mask) or raise `refresh`.  The same holds for mp_abjoin and
+ * mp_selfjoin_append.
  */
 int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
                 int32_t excl, int32_t prec, int32_t refresh, uint64_t group_mask, double* P, int64_t* I,

@@ -1419,6 +1419,13 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   PlanInfo pl;
   int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true, ab, keep);
   if (rc) return rc;
+  // the persistent kernels number their units with 32-bit queue entries (one
+  // past the last is read by every block of the grid before it stops)
+  if (pl.total_units > (int64_t)UINT32_MAX - (1 << 20)) {
+    set_error("the join needs " + std::to_string(pl.total_units) +
+              " work units, more than 2^32 - 2^20: split the groups over calls (group_mask) or raise refresh");
+    return SKMP_EINVAL;
+  }
   for (int64_t q = 0; q < n_series; ++q) {
     SeriesPlan& p = pl.sp[q];
     p.r0 = io[q].r0;

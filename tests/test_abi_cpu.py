@@ -95,6 +95,21 @@ def test_selfjoin_rejects_bad_arguments_before_launch(L):
     assert L.mp_selfjoin(fake, 300, 2, p, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 16, None) == -2     # workspace
 
 
+def test_selfjoin_rejects_more_work_units_than_the_queue_numbers(L):
+    """One series of 13 million windows with k = 8 in FP32 at refresh 256 needs
+    8 x 12,696 bands x 50,782 strips > 2^32 work units: refused on the host
+    before anything is launched (32-bit queue entries would wrap)."""
+    n = 13_000_000
+    a, p = _offs(0, n)
+    fake = ctypes.c_void_p(16)
+    rc = L.mp_selfjoin(fake, n, 1, p, 8, 100, 25, 1, 256, 0xFF, fake, fake, n, ctypes.c_void_p(256), 1 << 40, None)
+    assert rc == -1
+    assert b"work units" in L.skmp_last_error()
+    # a quarter of the length is fine up to the workspace check
+    a, p = _offs(0, n // 4)
+    assert L.mp_selfjoin(fake, n, 1, p, 8, 100, 25, 1, 256, 0xFF, fake, fake, n, ctypes.c_void_p(256), 16, None) == -2
+
+
 def test_build_and_discords_reject_bad_arguments(L):
     a, p = _offs(0, 100)
     fake = ctypes.c_void_p(16)
