@@ -196,7 +196,10 @@ def _experiment_random_walks(args) -> int:
     in its favour); reported for (j*, i*) of Algorithms 2-3 and after the
     refinement (the top discord of dimension j*'s own self-join).  Speedup:
     exact time / sketched time, both end to end on the GPU in the same
-    precision; the ranking always uses FP64 exact scores."""
+    precision; the ranking always uses FP64 exact scores.  Score densities (the
+    figure of Section IV-A): a 40-bin density of every exact score over [0,
+    2 sqrt(m)], pooled over the trials, and per trial the exact discord's score
+    and the exact scores of the sketched and refined discords."""
     import math
 
     import numpy as np
@@ -211,8 +214,14 @@ def _experiment_random_walks(args) -> int:
     ds = [int(x) for x in args.dims_list.split(",")]
     rows = []
     for d in ds:
-        k = min(int(math.ceil(math.sqrt(d))), 64)
+        k = skmp.sketch_default_k(d)  # ceil(sqrt(d)), at most 64
         succ, succ_ref, t_sk, t_ref, t_ex, ranks, ranks_ref = 0, 0, [], [], [], [], []
+        # score densities (the figure of Section IV-A at d = 1000): every exact score, pooled over the
+        # trials, and per trial the exact discord's score and the sketched / refined discords' exact scores
+        smax = 2.0 * math.sqrt(m)
+        nbins = 40
+        hist = torch.zeros(nbins, dtype=torch.float64, device=dev)
+        s_exact, s_sketch, s_ref = [], [], []
         for trial in range(args.trials):
             seed = 7919 * d + trial
             g = torch.Generator(device=dev)
@@ -248,6 +257,10 @@ def _experiment_random_walks(args) -> int:
             total = d * n_sub
             rank = int((scores > scores[j_star, i_star]).sum().item()) + 1
             rank_ref = int((scores > scores[j_star, i_ref]).sum().item()) + 1
+            hist += torch.histc(scores, bins=nbins, min=0.0, max=smax)
+            s_exact.append(float(scores.max().item()))
+            s_sketch.append(float(scores[j_star, i_star].item()))
+            s_ref.append(float(scores[j_star, i_ref].item()))
             ranks.append(rank / total)
             ranks_ref.append(rank_ref / total)
             succ += int(rank <= 1e-4 * total)
@@ -259,9 +272,16 @@ def _experiment_random_walks(args) -> int:
                      "median_rank_fraction": float(np.median(ranks)),
                      "median_rank_fraction_refined": float(np.median(ranks_ref)),
                      "t_sketched_ms": 1e3 * tsk, "t_refine_ms": 1e3 * tref, "t_exact_ms": 1e3 * tex,
-                     "speedup": tex / tsk, "speedup_with_refinement": tex / (tsk + tref)})
+                     "speedup": tex / tsk, "speedup_with_refinement": tex / (tsk + tref),
+                     "score_density": {
+                         "bin_edges": [smax * b / nbins for b in range(nbins + 1)],
+                         "all_scores": (hist / (hist.sum() * (smax / nbins))).cpu().tolist(),
+                         "exact_discord_scores": s_exact, "sketched_discord_scores": s_sketch,
+                         "refined_discord_scores": s_ref}})
         _progress(f"random walks d={d} k={k}: success {succ}/{args.trials}, refined {succ_ref}/{args.trials}, "
-                  f"speedup {rows[-1]['speedup']:.1f}x ({rows[-1]['speedup_with_refinement']:.1f}x refined)")
+                  f"speedup {rows[-1]['speedup']:.1f}x ({rows[-1]['speedup_with_refinement']:.1f}x refined); "
+                  f"median scores: exact discord {np.median(s_exact):.3f}, sketched {np.median(s_sketch):.3f}, "
+                  f"refined {np.median(s_ref):.3f}")
     print(json.dumps({"experiment": "Section IV-A random walks: sketched vs exact discord", "n": n, "m": m,
                       "excl": excl, "precision": prec, "sketch": "count", "rows": rows}), flush=True)
     return 0

@@ -98,6 +98,15 @@ const char* skmp_version(void);
  */
 int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64_t* dim_ids, int64_t d, double* S_host);
 
+/*
+ * The number of sketched series for d dimensions: ceil(sqrt(d)), which balances
+ * the k self-joins of time detection against the d / k dimensions one group
+ * holds for dimension detection (the cost analysis of Section III and the
+ * choice of Section IV), capped at the library's 64 groups.  d >= 1, else
+ * SKMP_EINVAL.  Host only.
+ */
+int32_t sketch_default_k(int64_t d);
+
 /* Workspace bytes needed by sketch_build (offsets host, as in sketch_build); 0 on bad arguments. */
 size_t sketch_build_workspace(int64_t d, int64_t n_series, const int64_t* offsets, int32_t k);
 

@@ -39,7 +39,8 @@ FLAG_CHECK_FINITE = 1
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE", -5: "ENOTFOUND"}
 
 # every symbol include/sketchmp.h declares
-EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_build_workspace", "sketch_build",
+EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_default_k", "sketch_build_workspace",
+            "sketch_build",
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
             "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "dim_detect_workspace", "dim_detect",
             "sketch_append_workspace", "sketch_append", "sketch_point_update_workspace", "sketch_point_update",
@@ -73,6 +74,8 @@ def lib():
         L.skmp_last_error.restype = ctypes.c_char_p
         L.skmp_version.restype = ctypes.c_char_p
         L.sketch_coeffs.argtypes = [_i32, _i32, _u64, _i64p, _i64, _dp]
+        L.sketch_default_k.argtypes = [_i64]
+        L.sketch_default_k.restype = _i32
         L.sketch_build_workspace.argtypes = [_i64, _i64, _i64p, _i32]
         L.sketch_build_workspace.restype = _sz
         L.sketch_build.argtypes = [_vp, _i32, _i64, _i64, _i64, _i64p, _i64p, _i32, _i32, _u64, _u32, _vp, _i64,
@@ -188,13 +191,23 @@ def sketch_coeffs(kind: str, k: int, seed: int, dim_ids: Sequence[int]) -> np.nd
     return S
 
 
+def sketch_default_k(d: int) -> int:
+    """ceil(sqrt(d)) capped at 64 (see include/sketchmp.h)."""
+    k = lib().sketch_default_k(d)
+    _check(min(k, 0))
+    return k
+
+
 def sketch_build(T, offsets, k: int, kind: str, seed: int, dim_ids=None, check_finite: bool = False, R=None,
                  stats=None):
-    """Normalise every dimension per series and sketch: returns (R k x N, dim_stats n_series x d x 2)."""
+    """Normalise every dimension per series and sketch: returns (R k x N, dim_stats n_series x d x 2).
+    k = 0 takes sketch_default_k(d)."""
     torch = _torch()
     assert T.is_cuda and T.dim() == 2 and T.stride(1) == 1
     dtype = {torch.float64: F64, torch.float32: F32}[T.dtype]
     d, N = T.shape
+    if k == 0:
+        k = sketch_default_k(d)
     offs = _i64arr(offsets)
     n_series = offs.size - 1
     ids = None if dim_ids is None else _i64arr(dim_ids)

@@ -739,6 +739,18 @@ extern "C" int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64
   return launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S_host);
 }
 
+// ceil(sqrt(d)) in integers (no rounding of a floating square root), capped at 64
+extern "C" int32_t sketch_default_k(int64_t d) {
+  clear_error();
+  if (d < 1) {
+    set_error("d must be >= 1");
+    return SKMP_EINVAL;
+  }
+  int64_t s = 1;
+  while (s < 64 && s * s < d) ++s;
+  return (int32_t)s;
+}
+
 extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int64_t* offsets, int32_t k) {
   if (d < 1 || n_series < 1 || !offsets || k < 1) return 0;
   std::vector<int64_t> cpre = chunk_prefix(n_series, offsets);

@@ -263,3 +263,17 @@ def test_streaming_argument_checks(L):
                                  16, None) == -2     # workspace too small
     assert L.sketch_point_update(fake, 100, 100, 4, 1, 7, 6, None, 1, fake, 0, None, None, None, None, None, None,
                                  0, None) == 0       # no updates: nothing to do, nothing launched
+
+
+def test_default_k_is_the_ceiling_of_sqrt_d_capped_at_64(L):
+    """k = ceil(sqrt(d)) (the k of the cost analysis and of every experiment of
+    Section IV), against the smallest integer whose square reaches d, found by
+    counting; capped at the library's 64 groups; d < 1 is an error."""
+    for d in list(range(1, 5000)) + [10_000, 2**31, 2**40]:
+        s = 1
+        while s * s < d:
+            s += 1
+        assert L.sketch_default_k(d) == min(s, 64), d
+    assert [L.sketch_default_k(d) for d in (1, 2, 4, 5, 9, 10, 3969, 3970)] == [1, 2, 2, 3, 3, 4, 63, 64]
+    assert L.sketch_default_k(0) == -1 and L.sketch_default_k(-5) == -1
+    assert b"d must be" in L.skmp_last_error()
