@@ -378,11 +378,14 @@ int mp_selfjoin_append(const double* R, int64_t ldr, int64_t n_series, const int
 
 /*
  * The process's tuning table as text, one line per shape class:
- * "prec mlog nlog variant strip ms".  skmp_tuning_export writes at most len
- * bytes (NUL-terminated) into buf (may be NULL) and returns the size needed
- * including the NUL; skmp_tuning_import adds or replaces the entries of such
- * text (SKMP_EINVAL on a malformed line or an unknown variant, nothing
- * changed); skmp_tuning_clear empties the table.  Host-only, thread-safe.
+ * "prec mlog nlog variant strip ms", the variant by name (e.g. f32_c16_pd2_w4:
+ * diagonals per lane, prefetch depth, waves per SIMD), so a table written by
+ * one build means the same kernels in another or is refused.
+ * skmp_tuning_export writes at most len bytes (NUL-terminated) into buf (may
+ * be NULL) and returns the size needed including the NUL; skmp_tuning_import
+ * adds or replaces the entries of such text (SKMP_EINVAL on a malformed line
+ * or a variant this build does not have, nothing changed); skmp_tuning_clear
+ * empties the table.  Host-only, thread-safe.
  */
 size_t skmp_tuning_export(char* buf, size_t len);
 int skmp_tuning_import(const char* text);

@@ -466,7 +466,7 @@ def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp6
 
 
 def tuning_export() -> str:
-    """The process's tuning table, one 'prec mlog nlog variant strip ms' line per shape class."""
+    """The process's tuning table, one 'prec mlog nlog variant-name strip ms' line per shape class."""
     n = lib().skmp_tuning_export(None, 0)
     buf = ctypes.create_string_buffer(n)
     lib().skmp_tuning_export(buf, n)

@@ -1730,9 +1730,13 @@ extern "C" size_t skmp_tuning_export(char* buf, size_t len) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune) {
-      char line[160];
-      snprintf(line, sizeof(line), "%d %d %d %d %d %.6f\n", kv.first.prec, kv.first.mlog, kv.first.nlog,
-               kv.second.variant, kv.second.strip, kv.second.ms);
+      // variants are named, not numbered: a table stays valid across builds
+      // whose variant lists differ
+      int nv = 0;
+      const Fp64Variant* vs = variants_of(kv.first.prec, &nv);
+      char line[200];
+      snprintf(line, sizeof(line), "%d %d %d %s %d %.6f\n", kv.first.prec, kv.first.mlog, kv.first.nlog,
+               vs[kv.second.variant].name, kv.second.strip, kv.second.ms);
       text += line;
     }
   }
@@ -1754,17 +1758,22 @@ extern "C" int skmp_tuning_import(const char* text) {
     std::string line(p, e ? (size_t)(e - p) : strlen(p));
     p = e ? e + 1 : p + line.size();
     if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
-    int prec, mlog, nlog, v, sp;
+    int prec, mlog, nlog, sp;
     double ms;
-    char extra;
-    if (sscanf(line.c_str(), "%d %d %d %d %d %lf %c", &prec, &mlog, &nlog, &v, &sp, &ms, &extra) != 6) {
+    char name[64], extra;
+    if (sscanf(line.c_str(), "%d %d %d %63s %d %lf %c", &prec, &mlog, &nlog, name, &sp, &ms, &extra) != 6) {
       set_error("malformed tuning line: " + line);
       return SKMP_EINVAL;
     }
-    int nv = 0;
-    variants_of(prec, &nv);
     SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "tuning line for a precision without variants");
-    SKMP_REQUIRE(v >= 0 && v < nv, "tuning line names an unknown variant");
+    int nv = 0, v = -1;
+    const Fp64Variant* vs = variants_of(prec, &nv);
+    for (int i = 0; i < nv; ++i)
+      if (strcmp(vs[i].name, name) == 0) v = i;
+    if (v < 0) {
+      set_error(std::string("tuning line names a variant this build does not have: ") + name);
+      return SKMP_EINVAL;
+    }
     SKMP_REQUIRE(sp >= 64 && sp <= (1 << 20), "tuning line strip out of range");
     SKMP_REQUIRE(mlog >= 0 && mlog <= 12 && nlog >= 0 && nlog <= 32, "tuning line shape class out of range");
     rows.push_back({TuneKey{prec, mlog, nlog, 0}, TuneChoice{v, sp, ms}});

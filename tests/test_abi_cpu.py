@@ -126,13 +126,18 @@ def test_build_and_discords_reject_bad_arguments(L):
 def test_tuning_table_round_trip_and_validation(L):
     skmp.tuning_clear()
     assert skmp.tuning_export() == ""
-    text = "0 7 16 3 4096 3.25\n1 6 15 1 256 2.000000\n"
+    text = "0 7 16 c8_pd2_w2_clfalse 4096 3.25\n1 6 15 f32_c16_pd2_w4 256 2.000000\n"
     skmp.tuning_import(text)
     rows = sorted(line.split() for line in skmp.tuning_export().splitlines())
-    assert rows == [["0", "7", "16", "3", "4096", "3.250000"], ["1", "6", "15", "1", "256", "2.000000"]]
-    skmp.tuning_import("0 7 16 5 1024 1.0\n")  # replaces the FP64 class entry
-    assert "0 7 16 5 1024 1.000000" in skmp.tuning_export()
-    for bad in ["0 7 16 99 2048 1.0", "2 7 16 0 2048 1.0", "0 7 16 1 2048", "0 7 16 1 2048 1.0 x", "1 6 15 1 16 1"]:
+    assert rows == [["0", "7", "16", "c8_pd2_w2_clfalse", "4096", "3.250000"],
+                    ["1", "6", "15", "f32_c16_pd2_w4", "256", "2.000000"]]
+    skmp.tuning_import("0 7 16 c6_pd1_w3_cltrue 1024 1.0\n")  # replaces the FP64 class entry
+    assert "0 7 16 c6_pd1_w3_cltrue 1024 1.000000" in skmp.tuning_export()
+    for bad in ["0 7 16 c99_pd2_w2_clfalse 2048 1.0",   # no such variant
+                "0 7 16 3 2048 1.0",                     # numbered, not named
+                "0 7 16 f32_c16_pd2_w4 2048 1.0",        # an FP32 variant for FP64
+                "2 7 16 c8_pd2_w2_clfalse 2048 1.0", "0 7 16 c8_pd2_w2_clfalse 2048",
+                "0 7 16 c8_pd2_w2_clfalse 2048 1.0 x", "1 6 15 f32_c16_pd2_w4 16 1"]:
         with pytest.raises(skmp.SketchMPError):
             skmp.tuning_import(bad)
     assert len(skmp.tuning_export().splitlines()) == 2   # a rejected import changes nothing

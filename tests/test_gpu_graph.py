@@ -125,7 +125,10 @@ def test_autotune_choice_is_used_and_exact(prec, c_oracle):
     assert choice["strip"] in ((1024, 2048, 4096) if prec == "fp64" else (256,))
     rows = [line.split() for line in skmp.tuning_export().splitlines()]
     assert len(rows) == 1 and int(rows[0][0]) == {"fp64": 0, "fp32": 1}[prec]
-    assert int(rows[0][3]) == choice["variant"] and int(rows[0][4]) == choice["strip"]
+    assert rows[0][3].startswith({"fp64": "c", "fp32": "f32_c"}[prec]) and int(rows[0][4]) == choice["strip"]
+    skmp.tuning_clear()
+    skmp.tuning_import(" ".join(rows[0]))   # the named variant round-trips
+    assert skmp.tuning_export().split() == rows[0]
     P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec)
     torch.cuda.synchronize()
     P, I = P.cpu().numpy(), I.cpu().numpy()
