@@ -388,6 +388,10 @@ int mp_selfjoin_append(const double* R, int64_t ldr, int64_t n_series, const int
  * empties the table.  Host-only, thread-safe.
  */
 size_t skmp_tuning_export(char* buf, size_t len);
+/* The names of the compiled tile-kernel variants of prec (SKMP_FP64 or
+ * SKMP_FP32; others: none), one per line, in the form the tuning table uses;
+ * buffer and return value as for skmp_tuning_export. */
+size_t skmp_tile_variants(int32_t prec, char* buf, size_t len);
 int skmp_tuning_import(const char* text);
 int skmp_tuning_clear(void);
 

@@ -44,7 +44,7 @@ EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_default_
             "sketch_update_workspace", "sketch_update_dims", "mp_selfjoin_workspace", "mp_selfjoin",
             "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "dim_detect_workspace", "dim_detect",
             "sketch_append_workspace", "sketch_append", "sketch_point_update_workspace", "sketch_point_update",
-            "mp_selfjoin_append_workspace", "mp_selfjoin_append", "skmp_tuning_export",
+            "mp_selfjoin_append_workspace", "mp_selfjoin_append", "skmp_tuning_export", "skmp_tile_variants",
             "skmp_tuning_import", "skmp_tuning_clear",
             "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4, "dimdetect": 5}
@@ -117,6 +117,8 @@ def lib():
         L.skmp_tuning_export.argtypes = [ctypes.c_char_p, _sz]
         L.skmp_tuning_export.restype = _sz
         L.skmp_tuning_import.argtypes = [ctypes.c_char_p]
+        L.skmp_tile_variants.argtypes = [_i32, ctypes.c_char_p, _sz]
+        L.skmp_tile_variants.restype = _sz
         L.skmp_timing_enable.argtypes = [ctypes.c_int]
         L.skmp_timing_read.argtypes = [_i32, _i32, _dp, _i64p]
         _lib = L
@@ -463,6 +465,14 @@ def mp_selfjoin_autotune(R, offsets, k: int, m: int, excl: int, prec: str = "fp6
                                       workspace.numel(), _stream(torch), reps, ctypes.byref(v), ctypes.byref(sp),
                                       ctypes.byref(ms)))
     return {"variant": v.value, "strip": sp.value, "ms": ms.value}
+
+
+def tile_variants(prec: str) -> list:
+    """Names of the compiled tile-kernel variants of an FP64 or FP32 self-join."""
+    n = lib().skmp_tile_variants(PRECISIONS[prec], None, 0)
+    buf = ctypes.create_string_buffer(n)
+    lib().skmp_tile_variants(PRECISIONS[prec], buf, n)
+    return buf.value.decode().split()
 
 
 def tuning_export() -> str:

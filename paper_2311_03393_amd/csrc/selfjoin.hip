@@ -1725,6 +1725,21 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   return SKMP_OK;
 }
 
+extern "C" size_t skmp_tile_variants(int32_t prec, char* buf, size_t len) {
+  std::string text;
+  if (prec == SKMP_FP64 || prec == SKMP_FP32) {
+    int nv = 0;
+    const Fp64Variant* vs = variants_of(prec, &nv);
+    for (int i = 0; i < nv; ++i) text += std::string(vs[i].name) + "\n";
+  }
+  if (buf && len > 0) {
+    const size_t n = std::min(len - 1, text.size());
+    memcpy(buf, text.data(), n);
+    buf[n] = '\0';
+  }
+  return text.size() + 1;
+}
+
 extern "C" size_t skmp_tuning_export(char* buf, size_t len) {
   std::string text;
   {

@@ -141,6 +141,12 @@ def test_tuning_table_round_trip_and_validation(L):
         with pytest.raises(skmp.SketchMPError):
             skmp.tuning_import(bad)
     assert len(skmp.tuning_export().splitlines()) == 2   # a rejected import changes nothing
+    for prec, default in (("fp64", "c8_pd2_w2_clfalse"), ("fp32", "f32_c16_pd2_w4")):
+        names = skmp.tile_variants(prec)
+        assert default in names and len(set(names)) == len(names) >= 3
+        for name in names:   # every listed variant is accepted by the table
+            skmp.tuning_import(f"{skmp.PRECISIONS[prec]} 5 12 {name} 1024 1.0")
+    assert skmp.tile_variants("bf16x3") == []
     skmp.tuning_clear()
     assert skmp.tuning_export() == ""
 

@@ -165,12 +165,9 @@ def test_every_compiled_variant_matches_oracle(prec, c_oracle):
     tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
     tested = 0
     try:
-        for v in range(64):
+        for v in skmp.tile_variants(prec):
             skmp.tuning_clear()
-            try:
-                skmp.tuning_import(f"{ {'fp64': 0, 'fp32': 1}[prec]} {mlog} {nlog} {v} {strip} 1.0")
-            except skmp.SketchMPError:
-                break                                   # past the last compiled variant
+            skmp.tuning_import(f"{ {'fp64': 0, 'fp32': 1}[prec]} {mlog} {nlog} {v} {strip} 1.0")
             _say("variant", prec, v)
             P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec)
             torch.cuda.synchronize()
@@ -182,4 +179,4 @@ def test_every_compiled_variant_matches_oracle(prec, c_oracle):
             tested += 1
     finally:
         skmp.tuning_clear()
-    assert tested >= 3
+    assert tested == len(skmp.tile_variants(prec)) >= 3

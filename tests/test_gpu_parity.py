@@ -130,6 +130,23 @@ def test_count_sketch_many_dimensions(dev):
     assert np.max(np.abs(R.cpu().numpy() - R_o)) <= 1e-12 * np.max(np.abs(R_o))
 
 
+@pytest.mark.parametrize("d", [1, 10, 50])
+def test_sketch_default_k(dev, d):
+    """k = 0 takes ceil(sqrt(d)) groups (1, 4, 8 here): the same sketch as that k
+    passed explicitly, and the oracle's for that k."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    n = 700
+    T = datagen.tiny_series(900 + d, d, n)
+    R0, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], 0, "count", 5)
+    k = {1: 1, 10: 4, 50: 8}[d]
+    R1, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, "count", 5)
+    torch.cuda.synchronize()
+    assert R0.shape == (k, n) and torch.equal(R0, R1)
+    R_o, _, _, _ = O.build(T, "count", k, 5)
+    assert np.max(np.abs(R0.cpu().numpy() - R_o)) <= 1e-12 * max(1.0, np.max(np.abs(R_o)))
+
+
 @pytest.mark.parametrize("kind,k", [("count", 7), ("count", 64), ("sum", 1)])
 def test_device_drawn_coefficients_large_ids(dev, kind, k):
     """Count and sum coefficients are drawn on the device: large dimension ids
@@ -216,7 +233,7 @@ def test_selfjoin_fp64_matches_oracle(dev, c_oracle, n, m, excl, k, seed):
         assert np.all(np.isnan(P[g, n_sub:])) and np.all(I[g, n_sub:] == -2)  # tail untouched
 
 
-def test_selfjoin_c0_and_top10(dev, c_oracle):
+def test_selfjoin_random_walk_small_and_top10(dev, c_oracle):
     import torch
     import paper_2311_03393_amd as skmp
     w = datagen.make("random-walk-small")
