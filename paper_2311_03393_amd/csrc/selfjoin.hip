@@ -177,9 +177,10 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   st.colkey[sidx] = 0ull;
   if (x < 0 || x >= sp.n_sub) {
     const double qnan = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
-    st.dfdg[sidx] = make_double2(0.0, 0.0);
     st.invn[sidx] = qnan;
     st.mu[sidx] = 0.0;
+    if (!st.walk_stats) return;
+    st.dfdg[sidx] = make_double2(0.0, 0.0);
     st.cdfdg[tidx] = make_double2(0.0, 0.0);
     st.cinvn[tidx] = qnan;
     if (st.fdfdg) {
@@ -222,12 +223,14 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     dg = (w[m] - mu1) + (w[0] - mu);
   }
   const double iv = flat ? 0.0 : 1.0 / (sd * sqrt((double)m));
-  st.dfdg[sidx] = make_double2(df, dg);
   st.invn[sidx] = iv;
   st.mu[sidx] = mu;
-  st.cdfdg[tidx] = make_double2(df, dg);
-  st.cinvn[tidx] = iv;
-  if (st.fdfdg) {
+  if (st.walk_stats) {
+    st.dfdg[sidx] = make_double2(df, dg);
+    st.cdfdg[tidx] = make_double2(df, dg);
+    st.cinvn[tidx] = iv;
+  }
+  if (st.walk_stats && st.fdfdg) {
     st.fdfdg[sidx] = make_float2((float)df, (float)dg);
     st.finvn[sidx] = (float)iv;
     st.fcdfdg[tidx] = make_float2((float)df, (float)dg);
@@ -1484,6 +1487,16 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   }
   SKMP_CHECK_HIP(hipGetLastError());
 
+  // a short append: every series has at most append_direct_max(m) new windows
+  // (SKMP_APPEND_DIRECT overrides the limit, 0 turns the direct kernel off)
+  static const int env_direct = env_int("SKMP_APPEND_DIRECT", 0, APPEND_DIRECT);
+  const int direct_max = env_direct >= 0 ? env_direct : append_direct_max(m);
+  bool direct = keep != nullptr && !mfma && direct_max > 0;
+  for (int64_t q = 0; direct && q < n_series; ++q)
+    if (pl.sp[q].n_sub - pl.sp[q].keep > direct_max) direct = false;
+  // the direct kernel, the MFMA tiles and the merge read only mu and invn
+  s.walk_stats = (mfma || direct) ? 0 : 1;
+
   const dim3 cg((unsigned)pl.total_chunks);
   {
     StageTimer tm(SKMP_TIMER_SUBSTATS, st);
@@ -1493,13 +1506,6 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   }
   SKMP_CHECK_HIP(hipGetLastError());
 
-  // a short append: every series has at most append_direct_max(m) new windows
-  // (SKMP_APPEND_DIRECT overrides the limit, 0 turns the direct kernel off)
-  static const int env_direct = env_int("SKMP_APPEND_DIRECT", 0, APPEND_DIRECT);
-  const int direct_max = env_direct >= 0 ? env_direct : append_direct_max(m);
-  bool direct = keep != nullptr && !mfma && direct_max > 0;
-  for (int64_t q = 0; direct && q < n_series; ++q)
-    if (pl.sp[q].n_sub - pl.sp[q].keep > direct_max) direct = false;
   if (direct) {
     StageTimer tm(SKMP_TIMER_TILES, st);
     hipLaunchKernelGGL(append_direct_kernel, cg, fb, sizeof(double) * (256 + m - 1 + APPEND_DIRECT + m - 1 + 3), st,

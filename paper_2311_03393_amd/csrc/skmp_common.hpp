@@ -131,6 +131,7 @@ struct SJState {
   int64_t total_units;
   int64_t total_chunks;
   int32_t strip;        // steps per strip
+  int32_t walk_stats;   // 1: substats also writes what the diagonal walks read (df, dg in both layouts, FP32 copies)
 };
 
 __device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series, int64_t key,
