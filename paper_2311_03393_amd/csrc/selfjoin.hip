@@ -811,6 +811,9 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     unsigned long long* gco = st.colkey + cgbase + PADL;
 
     LaneStateF<C> ls;
+    // a wave computing seeds (FP64, single rate) yields the issue to the waves
+    // that walk (FP32 pairs dual-issue): 2 % faster on the water-treatment join
+    __builtin_amdgcn_s_setprio(0);
     {  // exact FP64 seeds, rounded once to FP32
       double acc[C];
       exact_seeds<C, MCH>(sseed, r, mu, rc, muc, u_begin, db, t, n_cols, (int)sp.n - 1, (int)sp.cn - 1, m, acc);
@@ -831,6 +834,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
         ls.colacc[q] = 0xFFFFFFFFu;
       }
     }
+    __builtin_amdgcn_s_setprio(1);
     StepLoadF ring[PD];
 #pragma unroll
     for (int k = 0; k < PD; ++k) ring[k] = load_step_f<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
