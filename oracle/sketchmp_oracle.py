@@ -216,31 +216,39 @@ def window_stats(r: np.ndarray, m: int):
     return mu, sd
 
 
-def flat_mask(r: np.ndarray, sd: np.ndarray) -> np.ndarray:
-    scale = float(np.max(np.abs(r))) if r.size else 0.0
+def flat_mask(r: np.ndarray, sd: np.ndarray, scale: float = None) -> np.ndarray:
+    """Flat subsequences: sigma <= FLAT_REL * scale, scale = max |r| of the series
+    unless given (a prefix of a longer series is judged on the whole series' scale)."""
+    if scale is None:
+        scale = float(np.max(np.abs(r))) if r.size else 0.0
     return sd <= FLAT_REL * scale
 
 
-def znorm_windows(r: np.ndarray, m: int) -> Tuple[np.ndarray, np.ndarray]:
+def znorm_windows(r: np.ndarray, m: int, scale: float = None) -> Tuple[np.ndarray, np.ndarray]:
     """All z-normalised subsequences (n-m+1) x m; flat ones are the zero vector."""
     W = np.lib.stride_tricks.sliding_window_view(np.asarray(r, np.float64), m)
     mu, sd = window_stats(r, m)
-    flat = flat_mask(r, sd)
+    flat = flat_mask(r, sd, scale)
     Z = np.zeros(W.shape)
     ok = ~flat
     Z[ok] = (W[ok] - mu[ok, None]) / sd[ok, None]
     return Z, flat
 
 
-def dist(x: np.ndarray, y: np.ndarray) -> float:
+def dist(x: np.ndarray, y: np.ndarray, scale: float = None) -> float:
     """z-normalised Euclidean distance between two subsequences (Def. 3).
 
-    Computed from explicit differences of the normalised vectors.
+    Computed from explicit differences of the normalised vectors.  ``scale``
+    is the largest |value| of the series the subsequences come from: a
+    subsequence is flat when its sigma is <= FLAT_REL * scale, the rule
+    matrix_profile applies.  Without a series (``scale`` None) the two
+    subsequences are taken as the whole series, i.e. scale = their max |value|.
     """
     x = np.asarray(x, np.float64)
     y = np.asarray(y, np.float64)
     m = x.size
-    scale = max(float(np.max(np.abs(x))), float(np.max(np.abs(y))))
+    if scale is None:
+        scale = max(float(np.max(np.abs(x))), float(np.max(np.abs(y))))
     zx, fx = _znorm_one(x, scale)
     zy, fy = _znorm_one(y, scale)
     if fx and fy:
@@ -275,13 +283,14 @@ def profile_row(Z: np.ndarray, flat: np.ndarray, i: int, excl: int) -> Tuple[flo
     return float(dd[jj]), jj
 
 
-def matrix_profile(r: np.ndarray, m: int, excl: int, rows=None) -> Tuple[np.ndarray, np.ndarray]:
+def matrix_profile(r: np.ndarray, m: int, excl: int, rows=None, scale: float = None) -> Tuple[np.ndarray, np.ndarray]:
     """Self-join matrix profile P (length n-m+1) and index I by brute force.
 
     Def. 6 with T_test = T_train (the self-join variant of Section III-B).
-    ``rows`` restricts the computation to a subset (others are NaN / -2).
+    ``rows`` restricts the computation to a subset (others are NaN / -2);
+    ``scale`` overrides the flat-window scale max |r| (see flat_mask).
     """
-    Z, flat = znorm_windows(r, m)
+    Z, flat = znorm_windows(r, m, scale)
     n_sub = Z.shape[0]
     P = np.full(n_sub, np.nan)
     I = np.full(n_sub, -2, dtype=np.int64)
@@ -433,9 +442,10 @@ def matrix_profile_streaming(r: np.ndarray, m: int, excl: int, n_start: int) -> 
     matrix_profile(r, m, excl)."""
     r = np.asarray(r, dtype=np.float64)
     n = r.size
+    scale = float(np.max(np.abs(r))) if n else 0.0   # the series' flat-window scale, as in matrix_profile
     n0 = max(n_start, m - 1)
     if n0 >= m:
-        P, I = matrix_profile(r[:n0], m, excl)
+        P, I = matrix_profile(r[:n0], m, excl, scale=scale)
         P, I = list(P), list(I)
     else:
         P, I = [], []
@@ -445,7 +455,7 @@ def matrix_profile_streaming(r: np.ndarray, m: int, excl: int, n_start: int) -> 
         for i in range(j):
             if j - i < excl:
                 continue
-            dij = dist(r[i:i + m], r[j:j + m])
+            dij = dist(r[i:i + m], r[j:j + m], scale)
             if dij < pj:
                 pj, ij = dij, i
             if dij < P[i]:

@@ -173,6 +173,95 @@ def test_flat_subsequence_distances():
     assert O.dist(c, x) == math.sqrt(m)
 
 
+def _explicit_z(r, m, scale):
+    """z-normalised windows written out with numpy (population sigma; flat ->
+    zero vector), independent of the oracle's own normalisation code."""
+    W = np.lib.stride_tricks.sliding_window_view(np.asarray(r, np.float64), m)
+    mu = W.mean(axis=1, keepdims=True)
+    sd = W.std(axis=1, keepdims=True)
+    flat = sd[:, 0] <= O.FLAT_REL * scale
+    Z = np.where(flat[:, None], 0.0, (W - mu) / np.where(sd > 0, sd, 1.0))
+    return Z, flat
+
+
+def _pair_series(seed):
+    """A random walk with a flat stretch, a near-flat stretch (sigma tiny but
+    nonzero, flat against the series' max |r|), and a scaled exact repeat."""
+    rng = np.random.default_rng(seed)
+    m = 12
+    r = rng.standard_normal(260).cumsum() + 40.0        # max |r| ~ 40-60
+    r[30:55] = 7.0                                         # flat windows 30..43
+    r[90:118] = 1e-9 * rng.standard_normal(28)             # near-flat: sigma ~1e-9 < 1e-10 * max|r|
+    r[200:200 + m] = -2.5 * r[150:150 + m] + 3.0           # window 200 = affine copy of 150 (rho = -1)
+    r[230:230 + m] = 0.5 * r[150:150 + m] - 1.0            # window 230 = affine copy of 150 (rho = +1)
+    return r, m
+
+
+@pytest.mark.parametrize("seed,excl", [(11, 3), (12, 12), (13, 1)])
+def test_pair_dist_reproduces_every_profile_entry(seed, excl, c_oracle):
+    """The checker behind every full-size neighbour check: for every row,
+    the exact distance of the pair (i, I[i]) equals the brute-force profile
+    entry P[i] bit for bit (flat rows, near-flat rows, exact repeats)."""
+    r, m = _pair_series(seed)
+    P, I = c_oracle.profile(r, m, excl)
+    fin = I >= 0
+    rows = np.arange(P.size)[fin]
+    d = c_oracle.pair_dist(r, m, rows, I[fin])
+    assert np.array_equal(d, P[fin])
+    # the constructions are seen: flat and near-flat rows at 0, the rho = +1 copy at 0
+    assert P[30] == 0.0 and P[95] == 0.0
+    assert P[230] < 1e-6 and I[230] == 150
+    # numpy's pairwise distance with the series' scale agrees
+    scale = float(np.max(np.abs(r)))
+    for i in (0, 30, 95, 150, 200, 230, P.size - 1):
+        assert abs(O.dist(r[i:i + m], r[I[i]:I[i] + m], scale) - P[i]) < 1e-12
+
+
+def test_pair_dist_matches_scipy_cdist_on_random_pairs(c_oracle):
+    """pair_dist against scipy cdist of explicitly normalised windows, on
+    random pairs that include flat and near-flat windows; d(x, -x) = 2 sqrt(m)."""
+    r, m = _pair_series(21)
+    scale = float(np.max(np.abs(r)))
+    Z, flat = _explicit_z(r, m, scale)
+    rng = np.random.default_rng(5)
+    pi = rng.integers(0, Z.shape[0], 400)
+    pj = rng.integers(0, Z.shape[0], 400)
+    pi[:4] = [30, 30, 95, 150]
+    pj[:4] = [40, 150, 150, 200]
+    d = c_oracle.pair_dist(r, m, pi, pj)
+    ref = cdist(Z, Z)[pi, pj]
+    assert np.max(np.abs(d - ref)) < 1e-10
+    assert d[0] == 0.0 and d[1] == math.sqrt(m) and d[2] == math.sqrt(m)
+    assert abs(d[3] - 2.0 * math.sqrt(m)) < 1e-9
+    assert flat[30] and flat[95] and not flat[150]
+
+
+def test_flat_rule_uses_the_series_scale(c_oracle):
+    """A window of tiny but nonzero sigma is flat against the series' max |r|
+    (not against its own values): pair_dist, the profile and numpy's dist with
+    the series' scale all treat it as flat; judged on the two windows alone it
+    is a shape like any other."""
+    r, m = _pair_series(31)
+    scale = float(np.max(np.abs(r)))
+    x, y, z = r[95:95 + m], r[100:100 + m], r[150:150 + m]
+    assert O.dist(x, y, scale) == 0.0 and O.dist(x, z, scale) == math.sqrt(m)
+    assert 0.0 < O.dist(x, y) < 2.0 * math.sqrt(m) and O.dist(x, y) != math.sqrt(m)
+    d = c_oracle.pair_dist(r, m, np.array([95, 95]), np.array([100, 150]))
+    assert d[0] == 0.0 and d[1] == math.sqrt(m)
+
+
+def test_streaming_profile_with_near_flat_windows_equals_batch(c_oracle):
+    """The pairwise streaming profile judges near-flat windows on the series'
+    scale, as the batch profile does, so the two agree."""
+    r, m = _pair_series(41)
+    excl = 3
+    Ps, Is = O.matrix_profile_streaming(r, m, excl, 100)
+    P, I = c_oracle.profile(r, m, excl)
+    assert np.max(np.abs(Ps - P)) < 1e-12
+    assert np.array_equal(Is, I)
+    assert Ps[95] == 0.0
+
+
 def _scipy_profile(r, m, excl):
     W = np.lib.stride_tricks.sliding_window_view(r, m)
     Z = (W - W.mean(axis=1, keepdims=True)) / W.std(axis=1, keepdims=True)
