@@ -411,6 +411,25 @@ int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* 
                  void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * top_discords without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, semantics and outputs as top_discords
+ * minus the workspace: the intermediate arrays live in a device array that
+ * the library owns (about 25 MB, held on each device the call runs on until
+ * the process ends), and the series table travels as a kernel argument, so
+ * the call makes no device or pinned allocation.  Limits: n_series <= 64 and
+ * offsets[n_series] <= 2^21 samples in total; larger inputs give SKMP_EINVAL
+ * before anything is launched (use top_discords for them).  Every call on a
+ * device shares that device's array: calls that overlap on one device (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller.  Call with the stream's device current.  The array needs no
+ * clearing between calls (every element a call reads it first writes).
+ */
+int top_discords_noalloc(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                         int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group, double* score,
+                         int32_t* n_found, void* stream);
+
+/*
  * Stage timing.  When enabled, each launch of a timed stage is bracketed by HIP
  * events recorded on the stream the stage runs on; skmp_timing_read waits for
  * those events and returns the summed device time (ms) and the number of timed

@@ -46,7 +46,8 @@ EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_default_
             "sketch_append_workspace", "sketch_append", "sketch_point_update_workspace", "sketch_point_update",
             "mp_selfjoin_append_workspace", "mp_selfjoin_append", "skmp_tuning_export", "skmp_tile_variants",
             "skmp_tuning_import", "skmp_tuning_clear",
-            "top_discords_workspace", "top_discords", "skmp_timing_enable", "skmp_timing_read")
+            "top_discords_workspace", "top_discords", "top_discords_noalloc", "skmp_timing_enable",
+            "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4, "dimdetect": 5}
 
 
@@ -112,6 +113,7 @@ def lib():
         L.top_discords_workspace.restype = _sz
         L.top_discords.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz,
                                    _vp]
+        L.top_discords_noalloc.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
         L.mp_selfjoin_autotune.argtypes = [_vp, _i64, _i64, _i64p, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i64,
                                            _vp, _sz, _vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]
         L.skmp_tuning_export.argtypes = [ctypes.c_char_p, _sz]
@@ -508,4 +510,24 @@ def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0, out
     _check(lib().top_discords(P.data_ptr(), _ld(P), n_series, _ptr64(offs), k, m, top_k, halfwidth,
                               idx.data_ptr(), grp.data_ptr(), score.data_ptr(), nf.data_ptr(), ws.data_ptr(),
                               ws.numel(), _stream(torch)))
+    return idx, grp, score, nf
+
+
+def top_discords_noalloc(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0, out=None):
+    """top_discords through the allocation-free entry point (library-owned
+    scratch; at most 64 series and 2^21 samples).  With ``out`` given, the call
+    allocates nothing: (idx, group, score, n_found) device tensors."""
+    torch = _torch()
+    offs = _i64arr(offsets)
+    n_series = offs.size - 1
+    if out is None:
+        idx = torch.empty((n_series, top_k), dtype=torch.int64, device=P.device)
+        grp = torch.empty((n_series, top_k), dtype=torch.int32, device=P.device)
+        score = torch.empty((n_series, top_k), dtype=torch.float64, device=P.device)
+        nf = torch.empty((n_series,), dtype=torch.int32, device=P.device)
+    else:
+        idx, grp, score, nf = out
+    _check(lib().top_discords_noalloc(P.data_ptr(), _ld(P), n_series, _ptr64(offs), k, m, top_k, halfwidth,
+                                      idx.data_ptr(), grp.data_ptr(), score.data_ptr(), nf.data_ptr(),
+                                      _stream(torch)))
     return idx, grp, score, nf

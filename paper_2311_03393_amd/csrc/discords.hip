@@ -13,6 +13,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <climits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -270,9 +273,9 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(DiscState st) {
   if (tid == 0) st.n_found[s] = found;
 }
 
-// Block size (log2) and per-series block ranges.
-static int disc_plan(int64_t n_series, const int64_t* offsets, int32_t m, std::vector<DiscSeries>& ds,
-                     int64_t& blocks) {
+// Block size (log2) and per-series block ranges; ds (n_series entries) may be
+// null when only the block count is wanted.
+static int disc_plan(int64_t n_series, const int64_t* offsets, int32_t m, DiscSeries* ds, int64_t& blocks) {
   int64_t max_nsub = 0;
   for (int64_t s = 0; s < n_series; ++s) {
     const int64_t n = offsets[s + 1] - offsets[s];
@@ -280,18 +283,71 @@ static int disc_plan(int64_t n_series, const int64_t* offsets, int32_t m, std::v
   }
   int shift = DISC_BLK_MIN_SHIFT;
   while ((max_nsub + (1ll << shift) - 1) >> shift > SEL_LDS_BLOCKS) ++shift;
-  ds.resize(n_series);
   blocks = 0;
   for (int64_t s = 0; s < n_series; ++s) {
     const int64_t n = offsets[s + 1] - offsets[s];
-    ds[s].col = offsets[s];
-    ds[s].n_sub = n >= m ? n - m + 1 : 0;
-    ds[s].blk_base = blocks;
-    ds[s].nblk = (int32_t)((ds[s].n_sub + (1ll << shift) - 1) >> shift);
-    ds[s].pad_ = 0;
-    blocks += ds[s].nblk;
+    const int64_t n_sub = n >= m ? n - m + 1 : 0;
+    const int32_t nblk = (int32_t)((n_sub + (1ll << shift) - 1) >> shift);
+    if (ds) {
+      ds[s].col = offsets[s];
+      ds[s].n_sub = n_sub;
+      ds[s].blk_base = blocks;
+      ds[s].nblk = nblk;
+      ds[s].pad_ = 0;
+    }
+    blocks += nblk;
   }
   return shift;
+}
+
+// ------------------------------------------- allocation-free variant's scratch
+// top_discords_noalloc keeps its intermediate arrays (series table, A, G and
+// the block maxima) in one file-scope device array instead of a workspace.
+// Limits: at most NA_MAX_SERIES series and NA_MAX_SAMPLES samples in total.
+// The series table reaches the device as a kernel argument (no host table, no
+// pinned staging), so the call allocates nothing.
+constexpr int NA_MAX_SERIES = 64;
+constexpr int64_t NA_MAX_SAMPLES = int64_t(1) << 21;
+// blocks <= sum over series of ceil(n_sub / 256) <= N / 256 + n_series
+constexpr int64_t NA_MAX_BLOCKS = (NA_MAX_SAMPLES >> DISC_BLK_MIN_SHIFT) + NA_MAX_SERIES;
+constexpr size_t na_round(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t NA_OFF_A = na_round(sizeof(DiscSeries) * NA_MAX_SERIES);
+constexpr size_t NA_OFF_G = NA_OFF_A + na_round(sizeof(double) * NA_MAX_SAMPLES);
+constexpr size_t NA_OFF_BVAL = NA_OFF_G + na_round(sizeof(int32_t) * NA_MAX_SAMPLES);
+constexpr size_t NA_OFF_BIDX = NA_OFF_BVAL + na_round(sizeof(double) * NA_MAX_BLOCKS);
+constexpr size_t NA_OFF_BGRP = NA_OFF_BIDX + na_round(sizeof(int32_t) * NA_MAX_BLOCKS);
+constexpr size_t NA_SCRATCH_BYTES = NA_OFF_BGRP + na_round(sizeof(int8_t) * NA_MAX_BLOCKS);
+
+static __device__ __align__(256) unsigned char scratch[NA_SCRATCH_BYTES];
+
+struct DiscTable {
+  DiscSeries s[NA_MAX_SERIES];
+};
+
+__global__ __launch_bounds__(64) void disc_table_kernel(DiscTable tab, int n_series, DiscSeries* dst) {
+  for (int s = threadIdx.x; s < n_series; s += 64) dst[s] = tab.s[s];
+}
+
+// Device address of ``scratch`` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+static int noalloc_scratch(unsigned char** out) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static unsigned char* addr[MAX_DEV] = {};
+  int dev = 0;
+  SKMP_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEV) {
+    set_error("device index out of range for the allocation-free scratch table");
+    return SKMP_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    SKMP_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = addr[dev];
+  return SKMP_OK;
 }
 
 }  // namespace skmp
@@ -301,9 +357,8 @@ using namespace skmp;
 extern "C" size_t top_discords_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m) {
   (void)k;
   if (n_series < 1 || !offsets || m < 1) return 0;
-  std::vector<DiscSeries> ds;
   int64_t blocks;
-  disc_plan(n_series, offsets, m, ds, blocks);
+  disc_plan(n_series, offsets, m, nullptr, blocks);
   Carve cv(nullptr, 0);
   cv.take<DiscSeries>(n_series);
   cv.take<double>(offsets[n_series]);
@@ -314,10 +369,10 @@ extern "C" size_t top_discords_workspace(int64_t n_series, const int64_t* offset
   return cv.used + 256;
 }
 
-extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k,
-                            int32_t m, int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group, double* score,
-                            int32_t* n_found, void* workspace, size_t ws_bytes, void* stream) {
-  clear_error();
+// Argument checks shared by both entry points.
+static int disc_validate(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
+                         int32_t top_k, int32_t halfwidth, const int64_t* idx, const int32_t* group,
+                         const double* score, const int32_t* n_found) {
   SKMP_REQUIRE(P && offsets && idx && group && score && n_found, "null pointer argument");
   SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
   SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
@@ -328,11 +383,31 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   for (int64_t s = 0; s < n_series; ++s) SKMP_REQUIRE(offsets[s + 1] >= offsets[s], "offsets must be non-decreasing");
   for (int64_t s = 0; s < n_series; ++s)
     SKMP_REQUIRE(offsets[s + 1] - offsets[s] < (int64_t)INT_MAX, "series too long");
+  SKMP_REQUIRE(ldp >= offsets[n_series], "ldp must be >= the total number of samples");
+  return SKMP_OK;
+}
+
+// combine + select on arrays already placed (st.ser filled or about to be, in
+// stream order).
+static int disc_launch(const double* P, int64_t ldp, int32_t k, int64_t n_series, int64_t blocks, const DiscState& st,
+                       hipStream_t stream_) {
+  if (blocks > 0)
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, stream_, P, ldp, k, st);
+  const size_t lds = (size_t)SEL_LDS_BLOCKS * (sizeof(double) + sizeof(int) + sizeof(int8_t));
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), lds, stream_, st);
+  SKMP_CHECK_HIP(hipGetLastError());
+  return SKMP_OK;
+}
+
+extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k,
+                            int32_t m, int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group, double* score,
+                            int32_t* n_found, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (int rc = disc_validate(P, ldp, n_series, offsets, k, m, top_k, halfwidth, idx, group, score, n_found)) return rc;
   const int64_t N = offsets[n_series];
-  SKMP_REQUIRE(ldp >= N, "ldp must be >= the total number of samples");
-  std::vector<DiscSeries> ds;
+  std::vector<DiscSeries> ds(n_series);
   int64_t blocks;
-  const int shift = disc_plan(n_series, offsets, m, ds, blocks);
+  const int shift = disc_plan(n_series, offsets, m, ds.data(), blocks);
   Carve cv(workspace, ws_bytes);
   DiscSeries* ser = cv.take<DiscSeries>(n_series);
   DiscState st;
@@ -358,10 +433,40 @@ extern "C" int top_discords(const double* P, int64_t ldp, int64_t n_series, cons
   hipStream_t stream_ = static_cast<hipStream_t>(stream);
   if (int rc = upload_async(ser, ds.data(), sizeof(DiscSeries) * n_series, stream_)) return rc;
   StageTimer tm(SKMP_TIMER_DISCORDS, stream_);
-  if (blocks > 0)
-    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)blocks), dim3(256), 0, stream_, P, ldp, k, st);
-  const size_t lds = (size_t)SEL_LDS_BLOCKS * (sizeof(double) + sizeof(int) + sizeof(int8_t));
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)n_series), dim3(SEL_THREADS), lds, stream_, st);
-  SKMP_CHECK_HIP(hipGetLastError());
-  return SKMP_OK;
+  return disc_launch(P, ldp, k, n_series, blocks, st, stream_);
+}
+
+extern "C" int top_discords_noalloc(const double* P, int64_t ldp, int64_t n_series, const int64_t* offsets, int32_t k,
+                                    int32_t m, int32_t top_k, int32_t halfwidth, int64_t* idx, int32_t* group,
+                                    double* score, int32_t* n_found, void* stream) {
+  clear_error();
+  if (int rc = disc_validate(P, ldp, n_series, offsets, k, m, top_k, halfwidth, idx, group, score, n_found)) return rc;
+  SKMP_REQUIRE(n_series <= NA_MAX_SERIES, "top_discords_noalloc: more than 64 series");
+  const int64_t N = offsets[n_series];
+  SKMP_REQUIRE(N <= NA_MAX_SAMPLES, "top_discords_noalloc: more than 2^21 samples in total");
+  DiscTable tab;
+  int64_t blocks;
+  const int shift = disc_plan(n_series, offsets, m, tab.s, blocks);
+  unsigned char* base = nullptr;
+  if (int rc = noalloc_scratch(&base)) return rc;
+  DiscState st;
+  st.ser = reinterpret_cast<DiscSeries*>(base);
+  st.n_series = (int)n_series;
+  st.top_k = top_k;
+  st.halfwidth = halfwidth > 0 ? halfwidth : m;
+  st.shift = shift;
+  st.total_blocks = blocks;
+  st.A = reinterpret_cast<double*>(base + NA_OFF_A);
+  st.G = reinterpret_cast<int32_t*>(base + NA_OFF_G);
+  st.bval = reinterpret_cast<double*>(base + NA_OFF_BVAL);
+  st.bidx = reinterpret_cast<int32_t*>(base + NA_OFF_BIDX);
+  st.bgrp = reinterpret_cast<int8_t*>(base + NA_OFF_BGRP);
+  st.idx = idx;
+  st.group = group;
+  st.score = score;
+  st.n_found = n_found;
+  hipStream_t stream_ = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(disc_table_kernel, dim3(1), dim3(64), 0, stream_, tab, (int)n_series,
+                     reinterpret_cast<DiscSeries*>(base));
+  return disc_launch(P, ldp, k, n_series, blocks, st, stream_);
 }

@@ -123,6 +123,20 @@ def test_build_and_discords_reject_bad_arguments(L):
                                 fake, None, 0, None, None, 0, None, fake, 1 << 20, None) == -1  # duplicate id
 
 
+def test_noalloc_discords_refuse_inputs_beyond_their_scratch(L):
+    """The allocation-free top_discords checks its limits (64 series, 2^21
+    samples) on the host before it touches the device."""
+    fake = ctypes.c_void_p(16)
+    a, p = _offs(*range(0, 66 * 10, 10))              # 65 series
+    assert L.top_discords_noalloc(fake, 1000, 65, p, 2, 4, 3, 0, fake, fake, fake, fake, None) == -1
+    assert b"64 series" in L.skmp_last_error()
+    a, p = _offs(0, 2 ** 21, 2 ** 21 + 1)              # 2^21 + 1 samples
+    assert L.top_discords_noalloc(fake, 2 ** 22, 2, p, 2, 4, 3, 0, fake, fake, fake, fake, None) == -1
+    assert b"2^21" in L.skmp_last_error()
+    a, p = _offs(0, 100)
+    assert L.top_discords_noalloc(fake, 100, 1, p, 2, 16, 0, 0, fake, fake, fake, fake, None) == -1  # top_k = 0
+
+
 def test_tuning_table_round_trip_and_validation(L):
     skmp.tuning_clear()
     assert skmp.tuning_export() == ""
