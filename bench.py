@@ -40,24 +40,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X VALU issue: 256 CUs x 4 SIMDs at 2.4 GHz.  FP64 arithmetic, integer
-# and min/max instructions retire 16 lanes per clock per SIMD (3.93e13
-# lane-ops/s; FP64 vector 78.6 TFLOP/s); FP32 FMA / MUL / ADD retire 32 lanes
-# per clock per SIMD without packed math (7.86e13; FP32 vector 157.3 TFLOP/s).
+# Published MI355X peaks: FP32 vector 157.3 TFLOP/s, FP64 vector 78.6 TFLOP/s,
+# dense BF16 / FP16 matrix 2.5 PFLOP/s.  The roofline of a diagonal tile
+# kernel counts the method's 6 operations per valid half-matrix cell (2 FMA of
+# the recurrence, 2 MUL of the normalisation, 2 MIN of the row and column
+# reductions) as flops against the vector peak of the path's precision.
+PUBLISHED_PEAK = {"fp64": 78.6e12, "fp32": 157.3e12}
+OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MIN/MAX (row, column)
+# Issue-slot model (a separate, labelled reading, not the roofline): 256 CUs x
+# 4 SIMDs at 2.4 GHz; FP64 arithmetic, integer and min/max instructions retire
+# 16 lanes per clock per SIMD (3.93e13 lane-ops/s); FP32 FMA / MUL / ADD 32
+# lanes per clock per SIMD without packed math (7.86e13).
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 VALU_FP32_FAST_PEAK = 2 * VALU_LANE_OPS_PEAK
-OPS_PER_CELL = 6  # 2 FMA (recurrence) + 2 MUL (normalise) + 2 MIN/MAX (row, column)
-# cells/s at which each path's per-cell mix saturates the VALU:
+# cells/s at which each path's per-cell mix saturates the VALU issue:
 #   FP64: 6 single-rate ops -> 6 / 3.93e13 s per lane-cell;
 #   FP32: 4 double-rate FP32 ops + 2 single-rate minima -> 4 / 7.86e13 + 2 / 3.93e13.
 CELL_PEAK = {"fp64": VALU_LANE_OPS_PEAK / 6.0,
              "fp32": 1.0 / (4.0 / VALU_FP32_FAST_PEAK + 2.0 / VALU_LANE_OPS_PEAK)}
 CELL_PEAK_BASIS = {
-    "fp64": "VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 FP64 lane-ops/s; a cell = 2 FMA + 2 MUL + "
+    "fp64": "issue model: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 FP64 lane-ops/s; a cell = 2 FMA + 2 MUL + "
             "2 MIN, all single rate -> 6.55e12 cells/s",
-    "fp32": "VALU issue on gfx950: FP32 FMA/MUL at 32 lanes/clk/SIMD (7.86e13/s, FP32 vector 157.3 TFLOP/s), "
-            "integer minima at 16 (3.93e13/s); a cell = 2 FMA + 2 MUL (FP32) + 2 MIN (u32) = 4 issue slots -> "
-            "9.83e12 cells/s, i.e. 5.90e13 of the cell's lane-ops/s",
+    "fp32": "issue model: FP32 FMA/MUL at 32 lanes/clk/SIMD (7.86e13/s), integer minima at 16 (3.93e13/s); a cell "
+            "= 2 FMA + 2 MUL (FP32) + 2 MIN (u32) = 4 issue slots -> 9.83e12 cells/s",
 }
 MFMA_16BIT_PEAK = 2.5e15  # dense BF16 / FP16 matrix-core peak of MI355X, FLOP/s
 NAMED = {"random-walk-small": ("fp64", 0), "water-treatment": ("fp32", 256), "transportation": ("bf16x3", 0), "merchant-batch": ("fp32", 256), "large-series": ("fp16x3", 0)}
@@ -107,6 +112,8 @@ def _parse():
     ap.add_argument("--dims-list", default="250,500,1000,2500,5000,7500,10000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the oracle on every group of the workload (water-treatment: about 50 s on 16 cores)")
     return ap.parse_args()
 
 
@@ -140,41 +147,102 @@ def _valid_half_pairs(n_sub: int, excl: int) -> int:
     return L * (L + 1) // 2
 
 
-def _cpu_baseline(R_host_series, w, target_s: float):
-    """The plain-C FP64 brute-force oracle, timed on a bounded sample of rows.
+def _roofline_vector(prec: str, cells: float, avg_ms: float, launches: int, kernel: str, tr) -> dict:
+    """Roofline of a diagonal tile kernel: the method's 6 operations per valid
+    cell, counted as flops, per second of the kernel's own average launch time,
+    against the published vector peak of its precision.  The issue-slot model
+    (how far the kernel is from what the VALU can issue for its instruction
+    mix) is reported beside it, labelled as such."""
+    t = avg_ms * 1e-3
+    achieved = OPS_PER_CELL * cells / t
+    peak = PUBLISHED_PEAK[prec]
+    return {
+        "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None, "traffic_detail": tr,
+        "kernel": kernel,
+        "per_launch": {"cells": cells, "flops_per_cell": OPS_PER_CELL, "avg_ms": avg_ms, "launches": launches},
+        "basis": f"6 flops per valid half-matrix cell (2 FMA + 2 MUL + 2 MIN) over the tile kernel's average launch "
+                 f"time, against the published MI355X {prec.upper()} vector peak {peak / 1e12:.1f} TFLOP/s",
+        "issue_model": {"cells_per_s_bound": CELL_PEAK[prec], "frac": cells / t / CELL_PEAK[prec],
+                        "basis": CELL_PEAK_BASIS[prec]},
+    }
 
-    R_host_series: list of (series index, k x L host array).  Rows are drawn in
-    batches of 256 from random (series, group) pairs; the time per row of a
-    series is taken as proportional to its number of windows, and the full
-    profile's time is extrapolated from that rate."""
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_baseline(R_host_series, w, target_s: float, full: bool = False):
+    """The plain-C FP64 brute-force oracle on the host cores.
+
+    R_host_series: list of (series index, k x L host array).  When one whole
+    group's profile of a series fits the time budget (estimated from a short
+    row sample), whole profiles are timed, group after group, until the budget
+    is spent (``full``: every group of every listed series); otherwise rows
+    are drawn in batches of 256 from random (series, group) pairs.  The time
+    per row of a series is proportional to its number of windows, and the
+    whole workload's time is extrapolated from the measured rate (no
+    extrapolation when every group of every series was timed)."""
     import numpy as np
     from oracle import c_oracle
     c = c_oracle()
     rng = np.random.default_rng(0)
     lens = w.lengths()
-    first = R_host_series[0][1]
-    c.profile(first[0], w.m, w.excl, rows=rng.choice(first.shape[1] - w.m + 1, 8, replace=False))  # warm-up
-    rows_done, win_rows, t = 0, 0.0, 0.0
-    while t < target_s:
-        s, Rs = R_host_series[int(rng.integers(len(R_host_series)))]
-        n_sub = Rs.shape[1] - w.m + 1
-        rows = rng.choice(n_sub, min(256, n_sub), replace=False)
-        t0 = time.perf_counter()
-        c.profile(Rs[int(rng.integers(w.k))], w.m, w.excl, rows=rows)
-        t += time.perf_counter() - t0
-        rows_done += rows.size
-        win_rows += rows.size * n_sub
-    sec_per_window_row = t / win_rows
     n_sub_all = np.maximum(lens - w.m + 1, 0).astype(np.float64)
-    t_full = sec_per_window_row * w.k * float(np.sum(n_sub_all * n_sub_all))
+    work_all = w.k * float(np.sum(n_sub_all * n_sub_all))      # window-rows x windows of the whole workload
+    first = R_host_series[0][1]
+    n_first = first.shape[1] - w.m + 1
+    rows = rng.choice(n_first, min(256, n_first), replace=False)
+    c.profile(first[0], w.m, w.excl, rows=rows[:8])  # warm-up
+    t0 = time.perf_counter()
+    c.profile(first[0], w.m, w.excl, rows=rows)
+    est_group = (time.perf_counter() - t0) / (rows.size * n_first) * n_first * n_first
+    rows_done, win_rows, t = 0, 0.0, 0.0
+    if full or est_group <= 1.5 * target_s:
+        groups_done = 0
+        for s, Rs in R_host_series:
+            n_sub = Rs.shape[1] - w.m + 1
+            for g in range(w.k):
+                if not full and t >= target_s:
+                    break
+                t0 = time.perf_counter()
+                c.profile(Rs[g], w.m, w.excl)
+                t += time.perf_counter() - t0
+                rows_done += n_sub
+                win_rows += float(n_sub) * n_sub
+                groups_done += 1
+        whole = full and len(R_host_series) == len(lens)
+        sample = (f"whole brute-force profiles of {groups_done} (series, group) pairs "
+                  f"({groups_done} of {w.k * len(lens)}), {rows_done} rows, {t:.1f} s measured" +
+                  ("" if whole else ", the whole workload extrapolated by its window-rows"))
+    else:
+        while t < target_s:
+            s, Rs = R_host_series[int(rng.integers(len(R_host_series)))]
+            n_sub = Rs.shape[1] - w.m + 1
+            rows = rng.choice(n_sub, min(256, n_sub), replace=False)
+            t0 = time.perf_counter()
+            c.profile(Rs[int(rng.integers(w.k))], w.m, w.excl, rows=rows)
+            t += time.perf_counter() - t0
+            rows_done += rows.size
+            win_rows += rows.size * n_sub
+        sample = (f"{rows_done} profile rows (batches of 256 random rows of a random group of "
+                  f"{len(R_host_series)} series), each a full O(n m) brute-force row; {t:.1f} s measured")
+    t_full = t / win_rows * work_all
     return {
         "value": w.cells() / t_full,
         "unit": "cells/s",
         "cores": c.threads(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
-        "sample": f"{rows_done} profile rows (batches of 256 random rows of a random group of "
-                  f"{len(R_host_series)} series), each a full O(n m) brute-force row; {t:.1f} s measured, full "
-                  f"profile extrapolated to {t_full:.0f} s",
+        "sample": sample + f"; whole workload {t_full:.0f} s",
     }
 
 
@@ -355,7 +423,8 @@ def _bench_ab(args, prec: str, refresh: int) -> int:
         picks[pr] = out[0].cpu().clone()
         return {"precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
                 "tile_kernel_ms": tile_s * 1e3, "tile_launches": tiles_n,
-                "tile_frac_of_valu_issue": cells / tile_s / CELL_PEAK[pr],
+                "tile_frac_of_vector_peak": OPS_PER_CELL * cells / tile_s / PUBLISHED_PEAK[pr],
+                "tile_frac_of_issue_model": cells / tile_s / CELL_PEAK[pr],
                 "stages_ms_per_step": {st: v[0] / max(steps, 1) for st, v in stage.items()},
                 "top10": [int(x) for x in out[0][0].cpu()]}
 
@@ -366,9 +435,6 @@ def _bench_ab(args, prec: str, refresh: int) -> int:
         ref, got = profiles["fp64"], profiles[prec]
         head["vs_fp64"] = {"max_abs_dP": float((got - ref).abs().max()), "tolerance_dP": 1e-3 * 2 * m ** 0.5,
                            "top10_equal": bool(torch.equal(picks[prec], picks["fp64"]))}
-    tile_s = head["tile_kernel_ms"] * 1e-3
-    achieved = OPS_PER_CELL * cells / tile_s
-    peak = OPS_PER_CELL * CELL_PEAK[prec]
     result = {
         "metric": "AB-join matrix-profile cells/sec (k*na'*nb' per s)",
         "value": head["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -377,11 +443,7 @@ def _bench_ab(args, prec: str, refresh: int) -> int:
         "config": {"workload": DESCR[args.workload] + ": test = second half, train = first half",
                    "precision": prec, "refresh": refresh, "na": na, "nb": nb, "cells_per_step": cells,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "Tops/s", "frac": achieved / peak, "traffic": None, "basis": CELL_PEAK_BASIS[prec],
-                     "kernel": KERNELS[prec], "per_launch": {"cells": cells, "ops_per_cell": OPS_PER_CELL,
-                                                             "avg_ms": head["tile_kernel_ms"],
-                                                             "launches": head["tile_launches"]}},
+        "roofline": _roofline_vector(prec, cells, head["tile_kernel_ms"], head["tile_launches"], KERNELS[prec], None),
         "paths": results,
     }
     print(json.dumps(result), flush=True)
@@ -618,16 +680,23 @@ def main() -> int:
                 step()
             torch.cuda.synchronize()
             skmp.timing_enable(False)
+        # every timed step is bracketed by events on the stream the library runs on (torch's current
+        # stream): median and minimum per step beside the mean over the K steps
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for e0, e1 in evs:
+            e0.record()
             if graph is not None:
                 graph.replay()
             else:
                 step()
+            e1.record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _progress(f"{pr}: {steps} timed step(s), {(t1 - t0) * 1e3 / steps:.3f} ms each")
+        per_step = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+        _progress(f"{pr}: {steps} timed step(s), {(t1 - t0) * 1e3 / steps:.3f} ms each "
+                  f"(median {per_step[len(per_step) // 2]:.3f}, min {per_step[0]:.3f})")
         skmp.timing_enable(False)
         stage = {st: skmp.timing_read(st, reset=True) for st in skmp.TIMERS}
         del ws, graph
@@ -637,10 +706,14 @@ def main() -> int:
         profiles[pr] = P[:, wmask].clone()
         picks[pr] = out[0].cpu().clone()
         groups[pr] = out[1].cpu().clone()
+        med = float(np.median(per_step))
         return {
             "precision": pr, "refresh": rf, "ms_per_step": ms, "cells_per_s": cells / (ms * 1e-3),
+            "ms_per_step_median": med, "ms_per_step_min": per_step[0], "cells_per_s_median": cells / (med * 1e-3),
             "tile_kernel_ms": tile_avg_s * 1e3, "tile_launches": tiles_n,
-            "tile_frac_of_valu_issue": (valid / tile_avg_s / CELL_PEAK[pr] if pr in CELL_PEAK else None),
+            "tile_frac_of_vector_peak": (OPS_PER_CELL * valid / tile_avg_s / PUBLISHED_PEAK[pr]
+                                         if pr in PUBLISHED_PEAK else None),
+            "tile_frac_of_issue_model": (valid / tile_avg_s / CELL_PEAK[pr] if pr in CELL_PEAK else None),
             "tile_frac_of_mfma_peak": (6.0 * m * valid / tile_avg_s / MFMA_16BIT_PEAK
                                        if pr in ("bf16x3", "fp16x3") else None),
             "stages_ms_per_step": {st: v[0] / max(steps, 1) for st, v in stage.items()},
@@ -720,10 +793,11 @@ def main() -> int:
             dimdet = {"i_star": i_star, "group": g_star, "n_dims": int(len(dims)),
                       "j_star": int(dims[int(best.item())]), "ms": per,
                       "roofline": {"bound": "alu", "achieved": ops / (per * 1e-3) / 1e12,
-                                   "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tops/s",
-                                   "frac": ops / (per * 1e-3) / VALU_LANE_OPS_PEAK,
-                                   "basis": "7 m single-rate FP64 lane-ops per (dimension, train subsequence): "
-                                            "mean, variance, explicit-difference distance"}}
+                                   "peak": PUBLISHED_PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+                                   "frac": ops / (per * 1e-3) / PUBLISHED_PEAK["fp64"],
+                                   "basis": "7 m FP64 operations per (dimension, train subsequence) counted as "
+                                            "flops (mean, variance, explicit-difference distance), against the "
+                                            "published FP64 vector peak 78.6 TFLOP/s"}}
 
     tile_avg_s = head["tile_kernel_ms"] * 1e-3
     tr = _traffic(KERNELS[prec], args.workload)
@@ -746,21 +820,7 @@ def main() -> int:
             "basis": "dense 16-bit MFMA peak 2.5 PFLOP/s; 3 products x 2m flops per valid half-matrix cell",
         }
     else:
-        achieved = OPS_PER_CELL * valid / tile_avg_s
-        peak = OPS_PER_CELL * CELL_PEAK[prec]
-        roofline = {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": peak / 1e12,
-            "unit": "Tops/s",
-            "frac": achieved / peak,
-            "traffic": (tr["fetch_bytes"] + tr["write_bytes"]) if tr else None,
-            "traffic_detail": tr,
-            "kernel": KERNELS[prec],
-            "per_launch": {"cells": valid, "ops_per_cell": OPS_PER_CELL, "avg_ms": head["tile_kernel_ms"],
-                           "launches": head["tile_launches"]},
-            "basis": CELL_PEAK_BASIS[prec] + "; 6 lane-ops per valid half-matrix cell",
-        }
+        roofline = _roofline_vector(prec, valid, head["tile_kernel_ms"], head["tile_launches"], KERNELS[prec], tr)
     # the sketch stage is HBM-bound: T is read twice (statistics, projection), R written once
     sk_ms = head["stages_ms_per_step"]["sketch"]
     sk_bytes = 2.0 * d * N * T.element_size() + k * N * 8.0
@@ -778,6 +838,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
+        "ms_per_step_median": head["ms_per_step_median"],
+        "ms_per_step_min": head["ms_per_step_min"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -798,7 +860,7 @@ def main() -> int:
         rng = np.random.default_rng(1)
         pick = rng.choice(n_series, size=min(n_series, 8), replace=False)
         series = [(int(s), R[:, int(offsets[s]):int(offsets[s + 1])].cpu().numpy()) for s in pick]
-        result["cpu_baseline"] = _cpu_baseline(series, w, args.cpu_seconds)
+        result["cpu_baseline"] = _cpu_baseline(series, w, args.cpu_seconds, full=args.cpu_full)
     print(json.dumps(result), flush=True)
     return 0
 
