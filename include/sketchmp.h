@@ -55,7 +55,7 @@ extern "C" {
 #define SKMP_EINVAL (-1)     /* invalid argument */
 #define SKMP_ENOMEM (-2)     /* workspace too small */
 #define SKMP_EDEVICE (-3)    /* HIP runtime error */
-#define SKMP_ENONFINITE (-4) /* non-finite input (only when SKMP_FLAG_CHECK_FINITE is set) */
+#define SKMP_ENONFINITE (-4) /* non-finite input (returned only when SKMP_FLAG_CHECK_FINITE is set) */
 #define SKMP_ENOTFOUND (-5)  /* unknown dimension id */
 
 /* sketch kinds (Section III-A): R = S * Tbar with S in R^{k x d} */
@@ -70,12 +70,22 @@ extern "C" {
 /* self-join precisions */
 #define SKMP_FP64 0   /* FP64 diagonal recurrence */
 #define SKMP_FP32 1   /* FP32 diagonal recurrence, exact FP64 seed every `refresh` rows */
-#define SKMP_BF16X3 2 /* Hankel tiles on MFMA, BF16 hi+lo split products, FP32 accumulation */
-#define SKMP_FP16X3 3 /* Hankel tiles on MFMA, FP16 hi+lo split products, FP32 accumulation */
-/* Every precision reports the exact FP64 distance of the neighbour it finds. */
+#define SKMP_BF16X3 2 /* MFMA, BF16 hi+lo split products, FP32 accumulation */
+#define SKMP_FP16X3 3 /* MFMA, FP16 hi+lo split products, FP32 accumulation */
+/* Every precision reports the exact FP64 distance of the neighbour it finds.
+ * BF16x3 / FP16x3 run in one of two forms (tuning variants): the blocked
+ * recurrence (default: 16 x 16 tiles of the centred covariance carried down
+ * their diagonals by rank-32 MFMA updates, depth 32 whatever m, restarted
+ * from exact FP64 seeds every `refresh` rows) or the Hankel-direct tiles (a
+ * 128 x 128 tile is a product of two Hankel matrices of depth m). */
 
 /* flags for sketch_build / sketch_update_dims / sketch_append */
 #define SKMP_FLAG_CHECK_FINITE 1u /* synchronise and reject NaN/Inf input */
+/* Without the flag non-finite input is marked, never dropped (no host
+ * read-back, so the calls stay capturable): a dimension holding NaN or Inf
+ * gets the statistics (NaN, NaN), the sketch of its series is NaN, and the
+ * self-join reports P = NaN, I = -1 for every window whose sketched samples
+ * are not finite (top_discords skips them). */
 
 /* Message describing the last failure on this thread ("" if none). */
 const char* skmp_last_error(void);
@@ -94,7 +104,8 @@ const char* skmp_version(void);
  *   gauss: Box-Muller N(0,1) from SplitMix64(seed) outputs 2c+1 and 2c+2,
  *          c = id*64 + g;
  *   sum:   k must be 1, every entry +1.
- * Ids must lie in [0, 2^61 - 1); k in [1, 64].
+ * Ids must lie in [0, 2^61 - 1); k in [1, 128] for the count and sum sketches,
+ * [1, 64] for the Gaussian one (its draws are keyed by id * 64 + g).
  */
 int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64_t* dim_ids, int64_t d, double* S_host);
 
@@ -102,7 +113,8 @@ int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64_t* dim_ids
  * The number of sketched series for d dimensions: ceil(sqrt(d)), which balances
  * the k self-joins of time detection against the d / k dimensions one group
  * holds for dimension detection (the cost analysis of Section III and the
- * choice of Section IV), capped at the library's 64 groups.  d >= 1, else
+ * choice of Section IV), capped at the library's 128 groups (the count
+ * sketch; a Gaussian sketch takes at most 64).  d >= 1, else
  * SKMP_EINVAL.  Host only.
  */
 int32_t sketch_default_k(int64_t d);
@@ -120,7 +132,10 @@ size_t sketch_build_workspace(int64_t d, int64_t n_series, const int64_t* offset
  *            R[g][t] = sum_j S[g][j] * (T[j][t] - mu_sj) / sigma_sj for t in series s,
  *            where mu_sj, sigma_sj are the mean and population standard deviation
  *            of dimension j over series s (sigma = 0 contributes 0).
- *   dim_stats device out, n_series x d x 2 doubles: (mu_sj, sigma_sj).
+ *   dim_stats device out, n_series x d x 2 doubles: (mu_sj, sigma_sj);
+ *            (NaN, NaN) if dimension j of series s holds NaN or Inf (then
+ *            R is NaN over series s; with SKMP_FLAG_CHECK_FINITE the call
+ *            synchronises and returns SKMP_ENONFINITE instead).
  */
 int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt, int64_t n_series, const int64_t* offsets,
                  const int64_t* dim_ids, int32_t k, int32_t kind, uint64_t seed, uint32_t flags, double* R,
@@ -157,17 +172,24 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  * T_test = T_train, Section III-B), z-normalised Euclidean distance (Def. 3).
  *   R        device, k x N doubles, row stride ldr (sketch_build output).
  *   m        subsequence length, 4 <= m <= 2048 (<= 1024 for BF16x3 / FP16x3);
- *            every series needs n_s >= m.
+ *            every series needs m <= n_s <= 2^27 - 4096 samples (the tile
+ *            kernels address a series' window statistics with 32-bit offsets).
  *   excl     trivial-match exclusion: (i, j) is excluded iff |i - j| < excl; 1 <= excl.
  *   prec     SKMP_FP64 | SKMP_FP32 | SKMP_BF16X3 | SKMP_FP16X3.
  *   refresh  SKMP_FP32: rows between exact FP64 recomputations of the running
  *            covariance (0 = the larger of 256 and 2.5 m rounded up to a
- *            multiple of 256); ignored by the other precisions (SKMP_FP64 needs
- *            none, BF16x3 / FP16x3 compute every tile afresh from the sketch).
+ *            multiple of 256).  BF16x3 / FP16x3, blocked form: the period is
+ *            the largest of 128, 256, 512, 1024 rows not above `refresh`
+ *            (0 = 256); a refresh below 128 selects the Hankel-direct form,
+ *            which walks no rows.  Ignored by SKMP_FP64.
+ *   k        1 <= k <= 128; more than 64 groups are joined in blocks of 64
+ *            (one launch sequence per block, in stream order) and then need
+ *            group_mask = ~0.
  *   group_mask bit g selects group g (~0 = all); unselected rows of P/I are untouched.
  *   P        device out, k x N doubles, row stride ldp: P[g][offsets[s] + i] for
  *            i < n_s - m + 1 is the distance from subsequence i of R^(g) in
- *            series s to its nearest admissible neighbour; +inf if none.
+ *            series s to its nearest admissible neighbour; +inf if none;
+ *            NaN if the subsequence's sketched samples are not finite.
  *   I        device out, k x N int64, row stride ldp: that neighbour's index
  *            within the series (0-based), -1 if none.
  *            The last m - 1 columns of every series (no subsequence starts
@@ -197,12 +219,13 @@ int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const int64_t* o
  * the fastest for this process under the shape class (prec, ceil(log2 m),
  * ceil(log2 of the largest series' window count)); later mp_selfjoin calls
  * of that class use it (environment overrides SKMP_FP64_VARIANT,
- * SKMP_FP32_VARIANT, SKMP_STRIP still win).  Tuning a representative subset of
+ * SKMP_FP32_VARIANT, SKMP_MIXED_VARIANT, SKMP_STRIP still win).  Tuning a representative subset of
  * a batch tunes the batch, since the class ignores the number of series.
  * Arguments as for mp_selfjoin (all groups; P, I end up holding a complete
  * result of the last candidate; the workspace size from
- * mp_selfjoin_workspace covers every candidate).  prec must be SKMP_FP64 or
- * SKMP_FP32; 1 <= reps <= 100.  Synchronous: waits for the GPU, and fails
+ * mp_selfjoin_workspace covers every candidate).  Any precision (BF16x3 /
+ * FP16x3 choose between their forms and occupancies; with 0 < refresh < 128
+ * only the Hankel-direct form is a candidate); 1 <= reps <= 100.  Synchronous: waits for the GPU, and fails
  * with SKMP_EINVAL under graph capture.
  *   variant, strip, best_ms   host out (may be NULL): the choice and its time.
  */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsketchmp.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["sketch.hip", "selfjoin.hip", "selfjoin_mixed.hip", "discords.hip", "dimdetect.hip", "timing.hip",
+SOURCES = ["sketch.hip", "selfjoin.hip", "selfjoin_mixed.hip", "selfjoin_blocked.hip", "discords.hip", "dimdetect.hip", "timing.hip",
            "upload.hip"]
 ARCH = os.environ.get("SKMP_ARCH", "gfx950")
 

@@ -375,7 +375,7 @@ static int disc_validate(const double* P, int64_t ldp, int64_t n_series, const i
                          const double* score, const int32_t* n_found) {
   SKMP_REQUIRE(P && offsets && idx && group && score && n_found, "null pointer argument");
   SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
-  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(k >= 1 && k <= MAX_GROUPS, "k must lie in [1, 128]");
   SKMP_REQUIRE(m >= 1, "m must be >= 1");
   SKMP_REQUIRE(top_k >= 1 && top_k <= MAX_TOPK, "top_k must lie in [1, 256]");
   SKMP_REQUIRE(halfwidth >= 0, "halfwidth must be >= 0");

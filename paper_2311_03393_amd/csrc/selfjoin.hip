@@ -179,6 +179,10 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
     const double qnan = __longlong_as_double(0x7FF8000000000000ll);  // quiet NaN marks padding
     st.invn[sidx] = qnan;
     st.mu[sidx] = 0.0;
+    if (st.bplanes) {
+      blk_write_planes(st, 8 * gbase, sp.lpad, xp, 0.0, 0.0, 1.0);
+      st.finvn[sidx] = __int_as_float(0x7FC00000);
+    }
     if (!st.walk_stats) return;
     st.dfdg[sidx] = make_double2(0.0, 0.0);
     st.cdfdg[tidx] = make_double2(0.0, 0.0);
@@ -225,6 +229,10 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   const double iv = flat ? 0.0 : 1.0 / (sd * sqrt((double)m));
   st.invn[sidx] = iv;
   st.mu[sidx] = mu;
+  if (st.bplanes) {
+    blk_write_planes(st, 8 * gbase, sp.lpad, xp, df, dg, blk_scale(scale, st.bprec));
+    st.finvn[sidx] = (float)iv;
+  }
   if (st.walk_stats) {
     st.dfdg[sidx] = make_double2(df, dg);
     st.cdfdg[tidx] = make_double2(df, dg);
@@ -385,7 +393,6 @@ struct StatRsrc {
   int plane;                      // lpad / (C - 1)
 };
 
-constexpr int kBufWord3 = 0x00020000;
 
 template <int C>
 __device__ __forceinline__ StatRsrc make_rsrc(const SJState& st, int64_t gbase, int64_t lpad, int64_t cgbase,
@@ -650,15 +657,20 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
 // statistics and the keys in FP32: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
 // in FP32 from an exact FP64 seed recomputed at the start of every strip
 // (the strip length is the refresh period).  Keys are the bits of the FP32
-// value 1 - rho + 2^-16 in (0, 2] with the local diagonal in the low LBITS
+// value 1 - rho + 2^-10 in (0, 2] with the local diagonal in the low LBITS
 // bits; as positive floats they order like unsigned integers, so the nearest
 // neighbour is a 32-bit integer minimum (v_min3_u32).  Relative to rho + 2 in
 // [1, 3] this resolves candidates relative to their own distance (for
 // 1 - rho ~ 0.2 about 3e-6 in rho instead of 2.4e-4), so near ties between
 // neighbours are decided far below the tolerance.  Padded cells give NaN
 // keys, whose bits lie above every real key, so the minima ignore them.
-// Flushing converts a key f to the global form 3 - f = rho + 2 + ... (maxima).
-constexpr float KEY_ONE = 1.0f + 1.52587890625e-5f;  // 1 + 2^-16
+// Flushing converts a key f to the global form 3 + 2^-10 - f = rho + 2 (maxima).
+// The bias 2^-10 keeps the key positive while rho <= 1 + 2^-10: FP32 drift
+// over a refresh period is orders of magnitude smaller, and a negative key
+// (sign bit set) would read as an invalid cell.  The bias shifts every key
+// alike, so it changes no ordering.
+constexpr float KEY_ONE = 1.0f + 9.765625e-4f;  // 1 + 2^-10
+constexpr double KEY_BACK = 3.0 + 9.765625e-4;
 
 struct StepLoadF {
   float2 rs;
@@ -736,7 +748,7 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
       for (int q = 0; q < C; ++q) {
         const int sl = (p + q) % C;
         const float a = ls.Cq[q] * ls.cinv[sl];
-        // 1 - rho (+ 2^-16 so FP32 rounding never makes it negative): a positive
+        // 1 - rho (+ 2^-10 so FP32 rounding never makes it negative): a positive
         // float, resolved relative to itself, so close candidates stay apart
         const float kf = __builtin_fmaf(-a, cur.rinv, KEY_ONE);
         const uint32_t key = (__float_as_uint(kf) & keep) | (QM - q);  // padded cells: NaN bits, above every key
@@ -849,8 +861,9 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
       flush_block<C, TL, QB>(
           rowk, colk, last, u0, db, n_sub, n_cols, t, gro, gco, 0xFFFFFFFFu,
           [GMAX](uint32_t key, int delta) {
-            // local keys order by 1 - rho (min); the global ones by 3 - that = rho + 2 (max)
-            const double v = 3.0 - (double)__uint_as_float(key & ~LMAX);
+            // local keys order by 1 - rho + 2^-10 (min); the global ones by
+            // 3 + 2^-10 - that = rho + 2 (max)
+            const double v = KEY_BACK - (double)__uint_as_float(key & ~LMAX);
             const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
             return (kb & ~GMAX) | (GMAX - (unsigned long long)delta);
           },
@@ -992,6 +1005,14 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   const double* cmu = st.mu + cbase;
   const double* rc = sp.cr0 + (int64_t)g * sp.cldr;
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
+  if (isnan(invn[x])) {
+    // a window whose sketched samples are not finite (non-finite input): it
+    // has no distance to anything; P = NaN marks it (no admissible partner
+    // is +inf), and the tile kernels never paired it with another window
+    sp.p0[(int64_t)g * sp.ldp + x] = __longlong_as_double(0x7FF8000000000000ll);
+    sp.i0[(int64_t)g * sp.ldp + x] = -1;
+    return;
+  }
   const unsigned long long rk = st.rowkey[sbase + x], ck = st.colkey[sbase + x];
   int64_t partner = -1;
   if (ck != 0ull && ck >= rk) partner = x - (int64_t)(GMAX - (ck & GMAX));
@@ -1024,8 +1045,9 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
     best = INFINITY;
     arg = -1;
     // an append's old window whose new candidate, judged by its key, cannot
-    // beat the stored distance keeps it without a polish (the keys resolve
-    // 1 - rho to better than 3e-4 relative, or 2^-16 absolute)
+    // beat the stored distance keeps it without a polish (the 32-bit keys
+    // resolve 1 - rho to about 1.2e-4 relative plus 1.2e-7 absolute, the
+    // FP64 keys far better)
     bool worse = false;
     if (partner >= 0 && x < sp.keep && cinvn[partner] != 0.0) {
       const unsigned long long kk = (ck != 0ull && ck >= rk) ? ck : rk;
@@ -1104,7 +1126,9 @@ struct PlanInfo {
 // with keep = its window count has nothing new: no units, no merge.
 static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_t excl, int kact, int C, int strip,
                      PlanInfo& pl, bool validate, bool ab = false, const int64_t* keep = nullptr) {
-  const int cs = C > 0 ? C - 1 : 7;  // de-interleave stride of the column statistics
+  // de-interleave stride of the column statistics (diagonal kernels); the
+  // MFMA forms read natural layouts only (8 keeps their rows 32-byte aligned)
+  const int cs = C > 0 ? C - 1 : (C < 0 ? 8 : 7);
   pl.sp.assign(n_series, SeriesPlan{});
   int64_t stat = 0, chunk = 0, blk = 0, max_nsub = 1;
   for (int64_t s = 0; s < n_series; ++s) {
@@ -1146,6 +1170,11 @@ static int make_plan(int64_t n_series, const int64_t* offsets, int32_t m, int32_
       const bool fresh = p.keep < p.n - m + 1;  // false: an append with no new window
       p.nb = (nd > 0 && fresh && rows > 0) ? (int32_t)((nd + D - 1) / D) : 0;
       p.ns = (nd > 0 && fresh && rows > 0) ? (int32_t)((rows + strip - 1) / strip) : 0;
+    } else if (C < 0) {
+      // blocked MFMA form: units of BLK_DIAGS diagonals x BLK_UNIT_ROWS rows
+      const int64_t rows = std::min<int64_t>(p.n_sub, p.n_cols - p.d0);
+      p.nb = (nd > 0 && rows > 0) ? (int32_t)((nd + BLK_DIAGS - 1) / BLK_DIAGS) : 0;
+      p.ns = (nd > 0 && rows > 0) ? (int32_t)((rows + BLK_UNIT_ROWS - 1) / BLK_UNIT_ROWS) : 0;
     } else {
       const int64_t jt_last = (p.n_sub - 1) / MFMA_TILE;
       const int64_t nt0 = jt_last - (int64_t)excl / MFMA_TILE + 1;  // tiles of row panel 0
@@ -1175,6 +1204,7 @@ struct SJBuffers {
   float* finvn = nullptr;
   float2* fcdfdg = nullptr;
   float* fcinvn = nullptr;
+  uint16_t* bplanes = nullptr;
   double* mu;
   unsigned long long* rowkey;
   unsigned long long* colkey;
@@ -1185,13 +1215,19 @@ struct SJBuffers {
   unsigned int* counter;
 };
 
-static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, int prec, SJBuffers& b) {
+// blocked: the blocked MFMA form (16-bit operand planes + FP32 window norms)
+static void carve_sj(Carve& cv, const PlanInfo& pl, int64_t n_series, int kact, int prec, SJBuffers& b,
+                     bool blocked = false) {
   const size_t cells = (size_t)kact * (size_t)pl.gstride;
   if (prec == SKMP_FP32) {
     b.fdfdg = cv.take<float2>(cells);
     b.finvn = cv.take<float>(cells);
     b.fcdfdg = cv.take<float2>(cells);
     b.fcinvn = cv.take<float>(cells);
+  }
+  if (blocked) {
+    b.finvn = cv.take<float>(cells);
+    b.bplanes = cv.take<uint16_t>(8 * cells);
   }
   b.plan = cv.take<SeriesPlan>(n_series);
   b.dfdg = cv.take<double2>(cells);
@@ -1264,6 +1300,25 @@ static const Fp64Variant kFp32Variants[] = {
 #undef SKMP_FP32_V
 constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]);
 
+// Forms of the 16-bit split-precision join (BF16x3 / FP16x3): C = 0 the
+// Hankel-direct tiles (selfjoin_mixed.hip), C < 0 the blocked recurrence
+// (selfjoin_blocked.hip) held to -C waves per SIMD.
+static const Fp64Variant kMixedVariants[] = {
+    {"hankel", 0, nullptr, nullptr}, {"blocked_w2", -2, nullptr, nullptr}, {"blocked_w3", -3, nullptr, nullptr}};
+constexpr int kNumMixedVariants = sizeof(kMixedVariants) / sizeof(kMixedVariants[0]);
+constexpr int kDefaultMixedVariant = 1;
+constexpr int kHankelVariant = 0;
+
+// Refresh period of the blocked form: the largest of 128, 256, 512, 1024 rows
+// not above `refresh` (0: 256).  Periods must be multiples of 16 BLK_NB that
+// divide the unit's BLK_UNIT_ROWS.
+static int blk_period(int refresh) {
+  if (refresh <= 0) return 256;
+  int p = 128;
+  while (p * 2 <= refresh && p * 2 <= BLK_UNIT_ROWS) p *= 2;
+  return p;
+}
+
 // ------------------------------------------------------------- tuning
 // Launch configuration of a self-join: the tile-kernel variant and the strip
 // (rows per work unit).  Chosen, in this order, by SKMP_FP64_VARIANT /
@@ -1319,6 +1374,10 @@ static const Fp64Variant* variants_of(int prec, int* count) {
     *count = kNumFp32Variants;
     return kFp32Variants;
   }
+  if (prec == SKMP_BF16X3 || prec == SKMP_FP16X3) {
+    *count = kNumMixedVariants;
+    return kMixedVariants;
+  }
   *count = kNumFp64Variants;
   return kFp64Variants;
 }
@@ -1326,7 +1385,22 @@ static const Fp64Variant* variants_of(int prec, int* count) {
 static void select_config(int prec, int refresh, const TuneKey& key, int* vidx, int* strip) {
   static const int env64 = env_int("SKMP_FP64_VARIANT", 0, kNumFp64Variants - 1);
   static const int env32 = env_int("SKMP_FP32_VARIANT", 0, kNumFp32Variants - 1);
+  static const int envmx = env_int("SKMP_MIXED_VARIANT", 0, kNumMixedVariants - 1);
   static const int env_strip = env_int("SKMP_STRIP", 256, 1 << 20);
+  if (prec == SKMP_BF16X3 || prec == SKMP_FP16X3) {
+    // a refresh period below the blocked form's shortest (128 rows) asks for
+    // more exactness than its walk gives: the Hankel-direct tiles (no walk)
+    int v = (refresh > 0 && refresh < 128) ? kHankelVariant : kDefaultMixedVariant;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end() && !(refresh > 0 && refresh < 128)) v = it->second.variant;
+    }
+    if (envmx >= 0) v = envmx;
+    *vidx = v;
+    *strip = blk_period(refresh);
+    return;
+  }
   int v = (prec == SKMP_FP32) ? kDefaultFp32Variant : kDefaultFp64Variant;
   int sp = DEFAULT_STRIP;
   {
@@ -1357,6 +1431,7 @@ static int grid_for(const void* kernel, int block, size_t lds) {
 
 using namespace skmp;
 
+// k <= 64: the groups whose bit is set in group_mask.
 static int active_groups(int32_t k, uint64_t group_mask, GroupList& gl) {
   gl.count = 0;
   for (int g = 0; g < k; ++g)
@@ -1366,20 +1441,20 @@ static int active_groups(int32_t k, uint64_t group_mask, GroupList& gl) {
 
 extern "C" size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m,
                                         int32_t prec) {
-  if (n_series < 1 || !offsets || k < 1 || k > 64 || m < 4) return 0;
+  if (n_series < 1 || !offsets || k < 1 || k > MAX_GROUPS || m < 4) return 0;
+  k = std::min(k, 64);  // more groups run in blocks of 64 through the same workspace
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   int nv = 0;
   const Fp64Variant* vs = variants_of(prec, &nv);
   size_t need = 0;
   // the largest over the compiled variants, so a tuned choice always fits
-  for (int v = 0; v < (mfma ? 1 : nv); ++v) {
+  for (int v = 0; v < nv; ++v) {
     PlanInfo pl;
-    if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, mfma ? 0 : vs[v].C, DEFAULT_STRIP, pl, false) !=
-        SKMP_OK)
+    if (make_plan(n_series, offsets, m, std::max(1, m / 4), k, vs[v].C, DEFAULT_STRIP, pl, false) != SKMP_OK)
       return 0;
     Carve cv(nullptr, 0);
     SJBuffers b;
-    carve_sj(cv, pl, n_series, k, prec, b);
+    carve_sj(cv, pl, n_series, k, prec, b, mfma && vs[v].C < 0);
     need = std::max(need, cv.used + 256);
   }
   return need;
@@ -1390,7 +1465,7 @@ static int validate_selfjoin(const double* R, int64_t ldr, int64_t n_series, con
                              int64_t ldp) {
   SKMP_REQUIRE(R && P && I && offsets, "null pointer argument");
   SKMP_REQUIRE(n_series >= 1 && n_series < (1 << 30), "n_series out of range");
-  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(k >= 1 && k <= MAX_GROUPS, "k must lie in [1, 128]");
   SKMP_REQUIRE(m >= 4 && m <= 2048, "m must lie in [4, 2048]");
   SKMP_REQUIRE(excl >= 1, "excl must be >= 1 (a subsequence is its own trivial match)");
   SKMP_REQUIRE(prec >= SKMP_FP64 && prec <= SKMP_FP16X3, "unknown precision");
@@ -1400,7 +1475,7 @@ static int validate_selfjoin(const double* R, int64_t ldr, int64_t n_series, con
   const int64_t N = offsets[n_series];
   SKMP_REQUIRE(ldr >= N && ldp >= N, "row strides must be >= the total number of samples");
   for (int64_t s = 0; s < n_series; ++s)
-    SKMP_REQUIRE(offsets[s + 1] - offsets[s] < (int64_t)INT_MAX - 2 * PADR, "series too long");
+    SKMP_REQUIRE(offsets[s + 1] - offsets[s] <= MAX_SERIES_LEN, SERIES_TOO_LONG);
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   SKMP_REQUIRE(!mfma || m <= 1024, "the BF16x3 / FP16x3 self-join supports m <= 1024");
   return SKMP_OK;
@@ -1422,9 +1497,10 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
                     int32_t prec, const GroupList& gl, void* workspace, size_t ws_bytes, hipStream_t st,
                     const Fp64Variant& var, int strip, const int64_t* keep = nullptr) {
   const bool mfma = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
+  const bool blocked = mfma && var.C < 0;
   const int kact = gl.count;
   PlanInfo pl;
-  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? 0 : var.C, strip, pl, true, ab, keep);
+  int rc = make_plan(n_series, offsets, m, excl, kact, mfma ? std::min(var.C, 0) : var.C, strip, pl, true, ab, keep);
   if (rc) return rc;
   // the persistent kernels number their units with 32-bit queue entries (one
   // past the last is read by every block of the grid before it stops)
@@ -1445,7 +1521,7 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   }
   Carve cv(workspace, ws_bytes);
   SJBuffers b;
-  carve_sj(cv, pl, n_series, kact, prec, b);
+  carve_sj(cv, pl, n_series, kact, prec, b, blocked);
   if (!workspace || !cv.fits()) {
     set_error("workspace too small: need " + std::to_string(cv.used) + " bytes");
     return SKMP_ENOMEM;
@@ -1464,7 +1540,9 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   s.invn = b.invn;
   s.cdfdg = b.cdfdg;
   s.cinvn = b.cinvn;
-  s.cstride = mfma ? 7 : var.C - 1;
+  s.cstride = mfma ? (blocked ? 8 : 7) : var.C - 1;
+  s.bplanes = b.bplanes;
+  s.bprec = prec;
   s.fdfdg = b.fdfdg;
   s.finvn = b.finvn;
   s.fcdfdg = b.fcdfdg;
@@ -1516,7 +1594,10 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
                        s);
   } else if (pl.total_units > 0) {
     StageTimer tm(SKMP_TIMER_TILES, st);
-    if (mfma) {
+    if (blocked) {
+      rc = launch_sj_blk(prec, -var.C, s, pl.total_units, st);
+      if (rc) return rc;
+    } else if (mfma) {
       rc = launch_sj_mfma(prec, s, pl.total_units, st);
       if (rc) return rc;
     } else {
@@ -1547,15 +1628,24 @@ extern "C" int mp_selfjoin(const double* R, int64_t ldr, int64_t n_series, const
                            int64_t* I, int64_t ldp, void* workspace, size_t ws_bytes, void* stream) {
   clear_error();
   if (int rc = validate_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, refresh, P, I, ldp)) return rc;
-  if (k < 64) group_mask &= (1ull << k) - 1;
-  GroupList gl;
-  if (active_groups(k, group_mask, gl) == 0) return SKMP_OK;
+  SKMP_REQUIRE(k <= 64 || group_mask == ~0ull, "with more than 64 groups every group is joined (group_mask = ~0)");
   int vidx = 0, strip = DEFAULT_STRIP;
   select_config(prec, refresh, tune_key(prec, m, n_series, offsets), &vidx, &strip);
   int nv = 0;
   const Fp64Variant* vs = variants_of(prec, &nv);
-  return run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes,
-                      static_cast<hipStream_t>(stream), vs[vidx], strip);
+  // groups in blocks of at most 64 (one launch sequence each, in stream order
+  // through the same workspace)
+  for (int g0 = 0; g0 < k; g0 += 64) {
+    const int kk = std::min(64, k - g0);
+    const uint64_t mask = kk < 64 ? group_mask & ((1ull << kk) - 1) : group_mask;
+    GroupList gl;
+    if (active_groups(kk, mask, gl) == 0) continue;
+    if (int rc = run_selfjoin(R + (int64_t)g0 * ldr, ldr, n_series, offsets, kk, m, excl, prec, gl,
+                              P + (int64_t)g0 * ldp, I + (int64_t)g0 * ldp, ldp, workspace, ws_bytes,
+                              static_cast<hipStream_t>(stream), vs[vidx], strip))
+      return rc;
+  }
+  return SKMP_OK;
 }
 
 // ------------------------------------------------------------- AB-join
@@ -1577,7 +1667,7 @@ extern "C" int mp_abjoin(const double* RA, int64_t lda, int64_t na, const double
   SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "the AB-join runs in FP64 or FP32 (with FP64 refresh)");
   SKMP_REQUIRE(refresh == 0 || (refresh >= 64 && refresh <= (1 << 20)), "refresh must be 0 or in [64, 2^20]");
   SKMP_REQUIRE(na >= m && nb >= m, "both series need at least m samples");
-  SKMP_REQUIRE(na < (int64_t)INT_MAX - 2 * PADR && nb < (int64_t)INT_MAX - 2 * PADR, "series too long");
+  SKMP_REQUIRE(na <= MAX_SERIES_LEN && nb <= MAX_SERIES_LEN, SERIES_TOO_LONG);
   SKMP_REQUIRE(lda >= na && ldb >= nb && ldpa >= na && (PB == nullptr || ldpb >= nb),
                "row strides must be >= the series lengths");
   if (k < 64) group_mask &= (1ull << k) - 1;
@@ -1607,7 +1697,7 @@ static int append_layout(int64_t n_series, const int64_t* starts, const int64_t*
   for (int64_t s = 0; s < n_series; ++s) {
     SKMP_REQUIRE(n_new[s] >= m, "every series needs n_new >= m samples");
     SKMP_REQUIRE(n_old[s] >= 0 && n_old[s] <= n_new[s], "n_old must lie in [0, n_new]");
-    SKMP_REQUIRE(n_new[s] < (int64_t)INT_MAX - 2 * PADR, "series too long");
+    SKMP_REQUIRE(n_new[s] <= MAX_SERIES_LEN, SERIES_TOO_LONG);
     SKMP_REQUIRE(starts[s] >= 0 && starts[s] + n_new[s] <= ldr && starts[s] + n_new[s] <= ldp,
                  "a series runs past the row stride");
     SKMP_REQUIRE(s == 0 || starts[s] >= starts[s - 1] + n_new[s - 1], "series must be ascending and disjoint");
@@ -1675,8 +1765,9 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
                                     int32_t reps, int32_t* variant, int32_t* strip, double* best_ms) {
   clear_error();
   if (int rc = validate_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, refresh, P, I, ldp)) return rc;
-  SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "only the FP64 and FP32 self-joins have tuning variants");
+
   SKMP_REQUIRE(reps >= 1 && reps <= 100, "reps must lie in [1, 100]");
+  SKMP_REQUIRE(k <= 64, "autotuning takes at most 64 groups (tune on a block of them)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   SKMP_REQUIRE(!stream_capturing(st), "autotuning waits for the GPU and cannot run under graph capture");
   GroupList gl;
@@ -1684,7 +1775,9 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   int nv = 0;
   const Fp64Variant* vs = variants_of(prec, &nv);
   std::vector<int> strips;
+  const bool mixed = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   if (prec == SKMP_FP32) strips.push_back(refresh > 0 ? refresh : default_refresh(m));
+  else if (mixed) strips.push_back(blk_period(refresh));
   else strips.assign(std::begin(kTuneStrips), std::end(kTuneStrips));
   hipEvent_t e0, e1;
   SKMP_CHECK_HIP(hipEventCreate(&e0));
@@ -1696,6 +1789,9 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   int best_v = -1, best_s = 0, rc = SKMP_OK;
   double best = 1e300;
   for (int v = 0; v < nv && rc == SKMP_OK; ++v) {
+    // the blocked form walks at most `refresh` rows from a seed: below its
+    // shortest period only the Hankel-direct form is a candidate
+    if (mixed && refresh > 0 && refresh < 128 && vs[v].C != 0) continue;
     for (int sp : strips) {
       rc = run_selfjoin(R, ldr, n_series, offsets, k, m, excl, prec, gl, P, I, ldp, workspace, ws_bytes, st, vs[v],
                         sp);  // warm-up
@@ -1737,7 +1833,7 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
 
 extern "C" size_t skmp_tile_variants(int32_t prec, char* buf, size_t len) {
   std::string text;
-  if (prec == SKMP_FP64 || prec == SKMP_FP32) {
+  if (prec >= SKMP_FP64 && prec <= SKMP_FP16X3) {
     int nv = 0;
     const Fp64Variant* vs = variants_of(prec, &nv);
     for (int i = 0; i < nv; ++i) text += std::string(vs[i].name) + "\n";
@@ -1790,7 +1886,7 @@ extern "C" int skmp_tuning_import(const char* text) {
       set_error("malformed tuning line: " + line);
       return SKMP_EINVAL;
     }
-    SKMP_REQUIRE(prec == SKMP_FP64 || prec == SKMP_FP32, "tuning line for a precision without variants");
+    SKMP_REQUIRE(prec >= SKMP_FP64 && prec <= SKMP_FP16X3, "tuning line for an unknown precision");
     int nv = 0, v = -1;
     const Fp64Variant* vs = variants_of(prec, &nv);
     for (int i = 0; i < nv; ++i)

@@ -22,7 +22,7 @@
 // Work unit: one row panel (128 rows) times a segment of MFMA_SEG column
 // tiles of one (series, group).  4 waves, each a 64 x 64 quarter of the tile
 // (4 x 4 MFMA blocks).  Epilogue per cell: covariance correction, normalise,
-// key = bits(1 - rho + 2^-16) with the diagonal offset inside the segment in
+// key = bits(1 - rho + 2^-10) with the diagonal offset inside the segment in
 // the low 10 bits, running row minima (kept across the segment) and column
 // minima (flushed per tile); keys merge into the same global row/column key
 // arrays (as 3 - key, maxima) as the FP64 kernel's, so the FP64 merge and
@@ -129,14 +129,17 @@ __device__ __forceinline__ void build_vectors(typename Elem<PREC>::T* dst, uint1
   }
 }
 
-// Local keys: bits of the float 1 - rho + 2^-16 (ordered by minimum) with the
+// Local keys: bits of the float 1 - rho + 2^-10 (ordered by minimum) with the
 // diagonal code in the low CODE_BITS bits; invalid cells carry 0xFFFFFFFF.
-// The global (merged) keys order by maximum: 3 - f = rho + 2 - 2^-16.
-constexpr float KEY_ONE = 1.0f + 1.52587890625e-5f;  // 1 + 2^-16
+// The bias keeps the key positive while rho <= 1 + 2^-10 (the 16-bit operand
+// error is ~1e-5 in rho; a negative key would read as an invalid cell) and
+// shifts every key alike.  The global (merged) keys order by maximum:
+// 3 + 2^-10 - f = rho + 2.
+constexpr float KEY_ONE = 1.0f + 9.765625e-4f;  // 1 + 2^-10
 constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;
 
 __device__ __forceinline__ unsigned long long global_key(uint32_t key) {
-  const double v = 3.0 - (double)__uint_as_float(key & ~CODE_MASK);
+  const double v = (3.0 + 9.765625e-4) - (double)__uint_as_float(key & ~CODE_MASK);
   return (unsigned long long)__double_as_longlong(v);
 }
 
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256, 2) void sj_mfma_kernel(SJState st) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const float C = __builtin_fmaf(ma[v], bj[cb], acc[rb][cb][v]);
-            const float kf = __builtin_fmaf(-(C * cj[cb]), ri[v], KEY_ONE);  // 1 - rho + 2^-16
+            const float kf = __builtin_fmaf(-(C * cj[cb]), ri[v], KEY_ONE);  // 1 - rho + 2^-10
             uint32_t key = (__float_as_uint(kf) & ~CODE_MASK) | (uint32_t)(code_tile + 16 * (rb - cb) + v);
             if (masked) {
               const int i = I0 + 64 * wr + 16 * rb + 4 * lg + v;

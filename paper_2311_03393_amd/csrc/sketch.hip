@@ -69,7 +69,9 @@ static int check_ids(const int64_t* ids, int64_t d) {
 }
 
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S) {
-  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(k >= 1 && k <= MAX_GROUPS, "k must lie in [1, 128]");
+  // the Gaussian draws are keyed by id * 64 + g: at most 64 groups
+  SKMP_REQUIRE(kind != SKMP_GAUSS || k <= 64, "the Gaussian sketch has at most 64 groups");
   SKMP_REQUIRE(d >= 1, "d must be >= 1");
   SKMP_REQUIRE(S != nullptr, "S is NULL");
   SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
@@ -130,9 +132,11 @@ __device__ __forceinline__ uint64_t mulmod61_dev(uint64_t a, uint64_t x) {
 // Count or sum sketch coefficients straight into the projection's transposed
 // table St[j][g] (kb groups per row, zero past k): the hash pair of the host
 // generator (Section III-A), evaluated per dimension, so no table crosses PCIe.
+// Only groups [g0, g0 + kb) are written (a sketch of more than 64 groups is
+// projected in blocks of 64).
 __global__ void count_coeffs_kernel(double* __restrict__ St, int64_t d, int kb, int k, int kind,
                                     const int64_t* __restrict__ ids, uint64_t a, uint64_t b, uint64_t a2,
-                                    uint64_t b2) {
+                                    uint64_t b2, int g0) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d) return;
   double* row = St + j * kb;
@@ -146,11 +150,13 @@ __global__ void count_coeffs_kernel(double* __restrict__ St, int64_t d, int kb, 
   if (hv >= P61) hv -= P61;
   uint64_t sv = mulmod61_dev(a2, id) + b2;
   if (sv >= P61) sv -= P61;
-  row[hv % (uint64_t)k] = (sv & 1) ? -1.0 : 1.0;
+  const int g = (int)(hv % (uint64_t)k) - g0;
+  if (g >= 0 && g < kb) row[g] = (sv & 1) ? -1.0 : 1.0;
 }
 
 struct StatPartial {
   double n, mean, m2, maxabs;
+  double bad;  // non-finite values in the chunk
 };
 
 template <typename TIn>
@@ -216,6 +222,7 @@ __global__ __launch_bounds__(STAT_THREADS) void dimstats_partial(const TIn* __re
     p.mean = shift + t1 / cnt;
     p.m2 = fmax(t2 - t1 * (t1 / cnt), 0.0);
     p.maxabs = tm;
+    p.bad = (double)tb;
     part[bid] = p;
     if (tb && nonfinite) atomicAdd(nonfinite, tb);
   }
@@ -228,7 +235,7 @@ __global__ void dimstats_finalize(const StatPartial* __restrict__ part, const in
   const int s = (int)(idx / d);
   const int64_t j = idx - (int64_t)s * d;
   const int64_t total_chunks = cprefix[n_series];
-  double n = 0.0, mean = 0.0, m2 = 0.0, mx = 0.0;
+  double n = 0.0, mean = 0.0, m2 = 0.0, mx = 0.0, bad = 0.0;
   for (int64_t c = cprefix[s]; c < cprefix[s + 1]; ++c) {
     StatPartial p = part[j * total_chunks + c];
     double nn = n + p.n;
@@ -237,10 +244,17 @@ __global__ void dimstats_finalize(const StatPartial* __restrict__ part, const in
     m2 += p.m2 + delta * delta * (n * p.n / nn);
     n = nn;
     mx = fmax(mx, p.maxabs);
+    bad += p.bad;
   }
   double sd = sqrt(m2 / n);
   // a dimension whose sigma is negligible against its magnitude is constant
   if (sd <= FLAT_REL * mx) sd = 0.0;
+  if (bad > 0.0) {
+    // a dimension holding NaN or Inf has no statistics: (NaN, NaN) marks it,
+    // and its NaN coefficient makes the series' sketch NaN (never a silent 0)
+    mean = __longlong_as_double(0x7FF8000000000000ll);
+    sd = mean;
+  }
   stats[idx * 2 + 0] = mean;
   stats[idx * 2 + 1] = sd;
 }
@@ -489,7 +503,9 @@ __global__ void prep_coef(const double* __restrict__ stats, int64_t pairs, doubl
   if (i >= pairs) return;
   const double sd = stats[2 * i + 1];
   coef[2 * i] = stats[2 * i];
-  coef[2 * i + 1] = sd > 0.0 ? 1.0 / sd : 0.0;
+  // sigma = 0: a constant dimension, contributes 0; sigma = NaN (non-finite
+  // input, or NaN statistics passed in): NaN, so the sketch shows it
+  coef[2 * i + 1] = sd > 0.0 ? 1.0 / sd : (sd == 0.0 ? 0.0 : __longlong_as_double(0x7FF8000000000000ll));
 }
 
 // Sketch rows padded to the kernel's group count: 1, 4, 8, 16, 32 or 64.
@@ -739,7 +755,7 @@ extern "C" int sketch_coeffs(int32_t kind, int32_t k, uint64_t seed, const int64
   return launch_sketch_coeffs_host(kind, k, seed, dim_ids, d, S_host);
 }
 
-// ceil(sqrt(d)) in integers (no rounding of a floating square root), capped at 64
+// ceil(sqrt(d)) in integers (no rounding of a floating square root), capped at 128
 extern "C" int32_t sketch_default_k(int64_t d) {
   clear_error();
   if (d < 1) {
@@ -747,7 +763,7 @@ extern "C" int32_t sketch_default_k(int64_t d) {
     return SKMP_EINVAL;
   }
   int64_t s = 1;
-  while (s < 64 && s * s < d) ++s;
+  while (s < MAX_GROUPS && s * s < d) ++s;
   return (int32_t)s;
 }
 
@@ -758,10 +774,11 @@ extern "C" size_t sketch_build_workspace(int64_t d, int64_t n_series, const int6
   TableBlob tb(cv);
   tb.put<int64_t>(nullptr, n_series + 1);
   tb.put<int64_t>(nullptr, n_series + 1);
-  tb.put<double>(nullptr, (size_t)proj_kb(k) * (size_t)d);
+  const int kc = std::min<int>(k, 64);  // groups per projection pass
+  tb.put<double>(nullptr, (size_t)proj_kb(kc) * (size_t)d);
   cv.take<int64_t>((size_t)d);  // dimension ids when the coefficients are drawn on the device
   cv.take<double>((size_t)n_series * (size_t)d * 2);
-  cv.take<double>(proj_part_elems(d, offsets[n_series], k));
+  cv.take<double>(proj_part_elems(d, offsets[n_series], kc));
   stats_workspace(d, cpre[n_series], cv, nullptr);
   return cv.used + 256;
 }
@@ -780,12 +797,13 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
     SKMP_REQUIRE(offsets[s + 1] > offsets[s], "every series needs at least one sample (offsets strictly increasing)");
   const int64_t N = offsets[n_series];
   SKMP_REQUIRE(ldt >= N && ldr >= N, "row strides must be >= the total number of samples");
-  SKMP_REQUIRE(k >= 1 && k <= 64, "k must lie in [1, 64]");
+  SKMP_REQUIRE(k >= 1 && k <= MAX_GROUPS, "k must lie in [1, 128]");
   // count and sum coefficients are drawn on the device (integer hashing only);
   // Gaussian ones on the host (glibc libm), shipped as a table
   const bool device_coeffs = (kind == SKMP_COUNT || kind == SKMP_SUM);
   SKMP_REQUIRE(kind == SKMP_SUM || kind == SKMP_COUNT || kind == SKMP_GAUSS, "unknown sketch kind");
   SKMP_REQUIRE(kind != SKMP_SUM || k == 1, "the sum sketch has k = 1");
+  SKMP_REQUIRE(kind != SKMP_GAUSS || k <= 64, "the Gaussian sketch has at most 64 groups");
   int rc = SKMP_OK;
   std::vector<double> St;
   if (device_coeffs) {
@@ -801,11 +819,13 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   StatsBuffers sb;
   sb.offsets_dev = tb.put(offsets, n_series + 1);
   sb.cprefix_dev = tb.put(cpre.data(), n_series + 1);
-  const int kb = proj_kb(k);
+  // more than 64 groups (count sketch): projected in passes of 64 groups
+  const int kc = std::min<int>(k, 64);
+  const int kb = proj_kb(kc);
   double* S_dev = device_coeffs ? cv.take<double>((size_t)kb * (size_t)d) : tb.put(St.data(), St.size());
   const int64_t* ids_dev = (device_coeffs && dim_ids) ? tb.put(dim_ids, (size_t)d) : nullptr;
   double* coef = cv.take<double>((size_t)n_series * (size_t)d * 2);
-  const size_t dpart_elems = proj_part_elems(d, N, k);
+  const size_t dpart_elems = proj_part_elems(d, N, kc);
   double* dpart = cv.take<double>(dpart_elems);
   stats_workspace(d, cpre[n_series], cv, &sb);
   if (!workspace || !cv.fits()) {
@@ -815,20 +835,24 @@ extern "C" int sketch_build(const void* T, int32_t dtype, int64_t d, int64_t ldt
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (int rc2 = tb.upload(st)) return rc2;
   StageTimer tm(SKMP_TIMER_SKETCH, st);
-  if (device_coeffs) {
-    uint64_t a = 0, b = 0, a2 = 0, b2 = 0;
-    count_params(seed, &a, &b, &a2, &b2);
-    hipLaunchKernelGGL(count_coeffs_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, S_dev, d, kb, k,
-                       kind, ids_dev, a, b, a2, b2);
-  }
   rc = run_dimstats(T, dtype, ldt, d, n_series, cpre, sb, dim_stats, (flags & SKMP_FLAG_CHECK_FINITE) != 0, st);
   if (rc) return rc;
-  if (dtype == SKMP_F64)
-    launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, dpart,
-                           dpart_elems, st);
-  else
-    launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, k, R, ldr, 0, dpart,
-                          dpart_elems, st);
+  for (int g0 = 0; g0 < k; g0 += 64) {
+    const int kk = std::min(64, k - g0);
+    if (device_coeffs) {
+      uint64_t a = 0, b = 0, a2 = 0, b2 = 0;
+      count_params(seed, &a, &b, &a2, &b2);
+      hipLaunchKernelGGL(count_coeffs_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, S_dev, d,
+                         proj_kb(kk), k, kind, ids_dev, a, b, a2, b2, g0);
+    }
+    double* Rg = R + (int64_t)g0 * ldr;
+    if (dtype == SKMP_F64)
+      launch_project<double>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, kk, Rg, ldr, 0,
+                             dpart, dpart_elems, st);
+    else
+      launch_project<float>(T, ldt, d, N, sb.offsets_dev, (int)n_series, dim_stats, coef, S_dev, kk, Rg, ldr, 0,
+                            dpart, dpart_elems, st);
+  }
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
 }
@@ -1017,7 +1041,7 @@ extern "C" int sketch_append(const void* T_new, int32_t dtype, int64_t d, int64_
     uint64_t a = 0, b = 0, a2 = 0, b2 = 0;
     count_params(seed, &a, &b, &a2, &b2);
     hipLaunchKernelGGL(count_coeffs_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, S_dev, d, kb, k,
-                       kind, ids_dev, a, b, a2, b2);
+                       kind, ids_dev, a, b, a2, b2, 0);
   }
   if (flags & SKMP_FLAG_CHECK_FINITE) {
     // the statistics pass doubles as the finiteness check; its values are not used

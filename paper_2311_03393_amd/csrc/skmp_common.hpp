@@ -37,6 +37,17 @@ void clear_error();
 constexpr int PADL = 64;
 constexpr int PADR = 2048;
 constexpr double FLAT_REL = 1e-10;
+// Groups of a sketch: count and sum sketches up to 128 (sketch_build,
+// mp_selfjoin and top_discords); a self-join runs its groups in blocks of 64
+// (the 64-bit group masks), Gaussian coefficients up to 64.
+constexpr int MAX_GROUPS = 128;
+// The tile kernels read a series' per-window statistics through buffer
+// resources whose size and offsets are 32-bit byte counts; the widest array is
+// 16 bytes per padded window, so a series may have at most 2^27 - 4096
+// samples (the padded window count times 16 stays below 2^31).
+constexpr int64_t MAX_SERIES_LEN = (int64_t(1) << 27) - 4096;
+#define SERIES_TOO_LONG \
+  "series too long: the self-join addresses a series' window statistics with 32-bit offsets (at most 2^27 - 4096 samples per series)"
 // The column statistics are also stored de-interleaved by a stride cs (plane
 // x mod cs, slot x div cs, for the padded index x + PADL) so that 64 lanes
 // whose columns are cs apart read 64 adjacent elements; cs = C - 1 for a tile
@@ -130,8 +141,10 @@ struct SJState {
   unsigned int* counter;  // persistent work-queue head
   int64_t total_units;
   int64_t total_chunks;
-  int32_t strip;        // steps per strip
+  int32_t strip;        // steps per strip (blocked MFMA form: the refresh period in rows)
   int32_t walk_stats;   // 1: substats also writes what the diagonal walks read (df, dg in both layouts, FP32 copies)
+  uint16_t* bplanes;    // blocked MFMA form: 16-bit hi / lo operand planes of df, dg (NULL when unused)
+  int32_t bprec;        // their format: SKMP_BF16X3 or SKMP_FP16X3
 };
 
 __device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series, int64_t key,
@@ -227,6 +240,72 @@ bool stream_capturing(hipStream_t st);
 // capture (the source is served from a library-owned pinned copy).
 int upload_async(void* dst, const void* src, size_t bytes, hipStream_t st);
 int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int64_t* ids, int64_t d, double* S);
+
+// Word 3 of the buffer resources the tile kernels read through (raw buffer
+// loads with 32-bit offsets).
+constexpr int kBufWord3 = 0x00020000;
+
+// Blocked-recurrence MFMA self-join (selfjoin_blocked.hip): tiles per band,
+// bands per work unit, rows per work unit.  The refresh period P (rows) is one
+// of 128, 256, 512, 1024: a multiple of 16 BLK_NB that divides BLK_UNIT_ROWS.
+constexpr int BLK_NB = 8;
+constexpr int BLK_Q = 4;
+constexpr int BLK_UNIT_ROWS = 1024;
+constexpr int BLK_DIAGS = 16 * BLK_NB * BLK_Q;  // diagonals per work unit
+int launch_sj_blk(int prec, int waves_per_simd, const SJState& s, int64_t total_units, hipStream_t st);
+
+// Power-of-two scale of the 16-bit operand planes of a series whose largest
+// |value| is maxabs (|df| <= max|r|, |dg| <= 4 max|r|; 4 max|r| = f 2^e,
+// f in [0.5, 1)).  BF16 (8-bit exponent): 2^-e, the operands lie in [-1, 1].
+// FP16 (5-bit exponent): 2^(14 - e), the largest operand near 2^14, so the lo
+// part x - hi of an operand stays a normal FP16 number down to |x| of about
+// 8e-6 of the largest (at [-1, 1] it would be subnormal below 1/8 of it);
+// products stay far inside the FP32 accumulator's range.
+__device__ __forceinline__ double blk_scale(double maxabs, int prec) {
+  if (!(maxabs > 0.0)) return 1.0;
+  int e = 0;
+  (void)frexp(4.0 * maxabs, &e);
+  return ldexp(1.0, (prec == SKMP_FP16X3 ? 14 : 0) - e);
+}
+
+// x split into a 16-bit hi part (x rounded) and lo part (x - hi rounded).
+__device__ __forceinline__ void split16(double x, int prec, uint16_t& hi, uint16_t& lo) {
+  const float f = (float)x;
+  if (prec == SKMP_FP16X3) {
+    const _Float16 h = (_Float16)f;
+    const _Float16 l = (_Float16)(float)(x - (double)(float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  } else {
+    const __bf16 h = (__bf16)f;
+    const __bf16 l = (__bf16)(float)(x - (double)(float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+// The 16-bit operand planes of window xp (padded index) of one (series,
+// group slot) whose region starts at element `region` of st.bplanes: 8 planes
+// of lpad elements, plane p = copy * 4 + part * 2 + which (which: 0 = df,
+// 1 = dg; part: 0 = hi, 1 = lo).  Copy c holds element xp at position xp + c,
+// so 8 elements starting at any element are one dword-aligned 16-byte load
+// (from the copy given by the parity of the first element).
+__device__ __forceinline__ void blk_write_planes(const SJState& st, int64_t region, int64_t lpad, int64_t xp,
+                                                 double df, double dg, double scale) {
+  uint16_t* pl = st.bplanes + region;
+  uint16_t h[2], l[2];
+  split16(df * scale, st.bprec, h[0], l[0]);
+  split16(dg * scale, st.bprec, h[1], l[1]);
+#pragma unroll
+  for (int which = 0; which < 2; ++which) {
+    pl[(0 * 4 + 0 * 2 + which) * lpad + xp] = h[which];
+    pl[(0 * 4 + 1 * 2 + which) * lpad + xp] = l[which];
+    if (xp + 1 < lpad) {
+      pl[(1 * 4 + 0 * 2 + which) * lpad + xp + 1] = h[which];
+      pl[(1 * 4 + 1 * 2 + which) * lpad + xp + 1] = l[which];
+    }
+  }
+}
 
 // MFMA self-join (selfjoin_mixed.hip): tile edge, units per row panel, LDS bytes
 constexpr int MFMA_TILE = 128;

@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol(L):
     assert "gfx950" in skmp.version()
 
 
-@pytest.mark.parametrize("kind,k", [("sum", 1), ("count", 5), ("count", 64), ("gauss", 3), ("gauss", 16)])
+@pytest.mark.parametrize("kind,k", [("sum", 1), ("count", 5), ("count", 64), ("count", 100), ("count", 128),
+                                    ("gauss", 3), ("gauss", 16)])
 def test_coefficients_match_oracle_bit_for_bit(L, kind, k):
     ids = np.array([0, 1, 2, 7, 100, 12345, 2 ** 40 + 3, 999999937])
     S_lib = skmp.sketch_coeffs(kind, k, 2001, ids)
@@ -51,7 +52,9 @@ def test_coefficient_argument_errors(L):
     with pytest.raises(skmp.SketchMPError):
         skmp.sketch_coeffs("count", 0, 0, [0, 1])
     with pytest.raises(skmp.SketchMPError):
-        skmp.sketch_coeffs("gauss", 65, 0, [0, 1])
+        skmp.sketch_coeffs("gauss", 65, 0, [0, 1])      # Gaussian draws are keyed by id * 64 + g
+    with pytest.raises(skmp.SketchMPError):
+        skmp.sketch_coeffs("count", 129, 0, [0, 1])
     with pytest.raises(skmp.SketchMPError):
         skmp.sketch_coeffs("count", 4, 0, [-1])
 
@@ -78,7 +81,7 @@ def test_selfjoin_rejects_bad_arguments_before_launch(L):
     ws = ctypes.c_void_p(256)
     cases = [
         dict(k=0, m=16, excl=4),     # k out of range
-        dict(k=65, m=16, excl=4),
+        dict(k=129, m=16, excl=4),
         dict(k=2, m=3, excl=1),      # m < 4
         dict(k=2, m=16, excl=0),     # excl < 1
         dict(k=2, m=150, excl=4),    # first series shorter than m
@@ -88,6 +91,9 @@ def test_selfjoin_rejects_bad_arguments_before_launch(L):
                            ws, 1 << 30, None)
         assert rc == -1, c
         assert L.skmp_last_error()
+    # more than 64 groups are joined in blocks, all of them: a partial mask is refused
+    assert L.mp_selfjoin(fake, 300, 2, p, 100, 16, 4, 0, 0, (1 << 63) - 1, fake, fake, 300, ws, 1 << 30, None) == -1
+    assert b"group_mask" in L.skmp_last_error()
     bad, pbad = _offs(0, 300, 100)   # decreasing offsets
     assert L.mp_selfjoin(fake, 300, 2, pbad, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 1 << 30, None) == -1
     assert L.mp_selfjoin(fake, 100, 2, p, 2, 16, 4, 0, 0, 1, fake, fake, 300, ws, 1 << 30, None) == -1  # ldr < N
@@ -108,6 +114,25 @@ def test_selfjoin_rejects_more_work_units_than_the_queue_numbers(L):
     # a quarter of the length is fine up to the workspace check
     a, p = _offs(0, n // 4)
     assert L.mp_selfjoin(fake, n, 1, p, 8, 100, 25, 1, 256, 0xFF, fake, fake, n, ctypes.c_void_p(256), 16, None) == -2
+
+
+def test_series_beyond_32bit_statistics_offsets_refused(L):
+    """The tile kernels address a series' window statistics (16 bytes per
+    padded window) with 32-bit byte offsets: a series longer than 2^27 - 4096
+    samples is refused on the host before anything is launched, and one at
+    the limit passes the check (here it then stops at the workspace size)."""
+    limit = 2 ** 27 - 4096
+    fake = ctypes.c_void_p(16)
+    for prec in (0, 1, 2, 3):
+        a, p = _offs(0, limit + 1)
+        rc = L.mp_selfjoin(fake, limit + 1, 1, p, 1, 16, 4, prec, 0, 1, fake, fake, limit + 1, fake, 16, None)
+        assert rc == -1 and b"32-bit offsets" in L.skmp_last_error()
+    # AB-join: the long series against a short one (few diagonals, few work units)
+    assert L.mp_abjoin(fake, limit + 1, limit + 1, fake, 200, 200, 1, 16, 0, 0, 1, fake, fake, limit + 1, None, None,
+                       0, fake, 16, None) == -1
+    assert b"32-bit offsets" in L.skmp_last_error()
+    assert L.mp_abjoin(fake, limit, limit, fake, 200, 200, 1, 16, 0, 0, 1, fake, fake, limit, None, None, 0, fake, 16,
+                       None) == -2    # valid up to the workspace check
 
 
 def test_build_and_discords_reject_bad_arguments(L):
@@ -155,12 +180,16 @@ def test_tuning_table_round_trip_and_validation(L):
         with pytest.raises(skmp.SketchMPError):
             skmp.tuning_import(bad)
     assert len(skmp.tuning_export().splitlines()) == 2   # a rejected import changes nothing
-    for prec, default in (("fp64", "c8_pd2_w2_clfalse"), ("fp32", "f32_c16_pd2_w4")):
+    for prec, default in (("fp64", "c8_pd2_w2_clfalse"), ("fp32", "f32_c16_pd2_w4"), ("bf16x3", "blocked_w2"),
+                          ("fp16x3", "blocked_w2")):
         names = skmp.tile_variants(prec)
         assert default in names and len(set(names)) == len(names) >= 3
         for name in names:   # every listed variant is accepted by the table
             skmp.tuning_import(f"{skmp.PRECISIONS[prec]} 5 12 {name} 1024 1.0")
-    assert skmp.tile_variants("bf16x3") == []
+    # the 16-bit split precisions list both MFMA forms
+    assert {"hankel", "blocked_w2"} <= set(skmp.tile_variants("bf16x3"))
+    with pytest.raises(skmp.SketchMPError):
+        skmp.tuning_import("2 5 12 f32_c16_pd2_w4 1024 1.0")   # an FP32 variant for BF16x3
     skmp.tuning_clear()
     assert skmp.tuning_export() == ""
 
@@ -171,7 +200,7 @@ def test_autotune_rejects_bad_arguments_before_launch(L):
     v, sp, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
     args = lambda prec, reps, k=2: (fake, 300, 1, p, k, 16, 4, prec, 0, fake, fake, 300, fake, 1 << 30, None, reps,
                                     ctypes.byref(v), ctypes.byref(sp), ctypes.byref(ms))
-    assert L.mp_selfjoin_autotune(*args(2, 2)) == -1   # BF16x3 has no variants to tune
+    assert L.mp_selfjoin_autotune(*args(7, 2)) == -1   # no such precision
     assert L.mp_selfjoin_autotune(*args(0, 0)) == -1   # reps
     assert L.mp_selfjoin_autotune(*args(0, 2, k=0)) == -1
     assert L.skmp_last_error()
@@ -290,15 +319,16 @@ def test_streaming_argument_checks(L):
                                  0, None) == 0       # no updates: nothing to do, nothing launched
 
 
-def test_default_k_is_the_ceiling_of_sqrt_d_capped_at_64(L):
+def test_default_k_is_the_ceiling_of_sqrt_d_capped_at_128(L):
     """k = ceil(sqrt(d)) (the k of the cost analysis and of every experiment of
     Section IV), against the smallest integer whose square reaches d, found by
-    counting; capped at the library's 64 groups; d < 1 is an error."""
-    for d in list(range(1, 5000)) + [10_000, 2**31, 2**40]:
+    counting; capped at the library's 128 groups; d < 1 is an error."""
+    for d in list(range(1, 5000)) + [7_500, 10_000, 16_384, 16_385, 2**31, 2**40]:
         s = 1
         while s * s < d:
             s += 1
-        assert L.sketch_default_k(d) == min(s, 64), d
+        assert L.sketch_default_k(d) == min(s, 128), d
     assert [L.sketch_default_k(d) for d in (1, 2, 4, 5, 9, 10, 3969, 3970)] == [1, 2, 2, 3, 3, 4, 63, 64]
+    assert [L.sketch_default_k(d) for d in (5_000, 7_500, 10_000)] == [71, 87, 100]   # the paper's largest d
     assert L.sketch_default_k(0) == -1 and L.sketch_default_k(-5) == -1
     assert b"d must be" in L.skmp_last_error()

@@ -142,12 +142,13 @@ def test_autotune_choice_is_used_and_exact(prec, c_oracle):
     skmp.tuning_clear()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_every_compiled_variant_matches_oracle(prec, c_oracle):
     """Each compiled tile-kernel variant (diagonals per lane, prefetch depth,
-    occupancy, column scheme), forced through the tuning table, gives the
-    oracle's profile: the key codes of every lane width decode to the right
-    diagonal."""
+    occupancy, column scheme; for the 16-bit split precisions the
+    Hankel-direct and the blocked-recurrence forms), forced through the tuning
+    table, gives the oracle's profile: the key codes of every lane width
+    decode to the right diagonal."""
     import math
     import torch
     import paper_2311_03393_amd as skmp
@@ -167,7 +168,8 @@ def test_every_compiled_variant_matches_oracle(prec, c_oracle):
     try:
         for v in skmp.tile_variants(prec):
             skmp.tuning_clear()
-            skmp.tuning_import(f"{ {'fp64': 0, 'fp32': 1}[prec]} {mlog} {nlog} {v} {strip} 1.0")
+            code = {'fp64': 0, 'fp32': 1, 'bf16x3': 2, 'fp16x3': 3}[prec]
+            skmp.tuning_import(f"{code} {mlog} {nlog} {v} {strip} 1.0")
             _say("variant", prec, v)
             P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl, prec=prec)
             torch.cuda.synchronize()

@@ -6,9 +6,9 @@ Checked on sampled outputs: the sketch and the updated sketch element by
 element against the oracle's build of the same input (R of a fresh build over
 the kept and added dimensions), the changed-group mask, and 16 profile rows
 of 4 groups (plus the first and last window) of the recomputed profile
-against the oracle's brute-force rows, with their neighbours, for the FP32 and
-FP64 paths; the reported distances are the exact distances of the reported
-neighbours for every window.
+against the oracle's brute-force rows, with their neighbours, for the FP64,
+FP32 and FP16x3 (the workload's named precision) paths; the reported distances
+are the exact distances of the reported neighbours for every window.
 """
 import sys
 
@@ -64,14 +64,14 @@ def test_c4_sketch_and_update(large):
     assert changed == (1 << w.k) - 1   # every Gaussian row has non-zero coefficients on the changed dims
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16x3"])
 def test_c4_recomputed_profile_sampled(large, c_oracle, prec):
     import torch
     import paper_2311_03393_amd as skmp
     w, R, _, changed = large
     m, excl, k = w.m, w.excl, w.k
     _say("large series selfjoin", prec)
-    P, I = skmp.mp_selfjoin(R, w.offsets, k, m, excl, prec=prec, refresh=256 if prec == "fp32" else 0,
+    P, I = skmp.mp_selfjoin(R, w.offsets, k, m, excl, prec=prec, refresh=256 if prec != "fp64" else 0,
                             group_mask=changed)
     torch.cuda.synchronize()
     n = w.T.shape[1]
@@ -80,7 +80,7 @@ def test_c4_recomputed_profile_sampled(large, c_oracle, prec):
     Ph = P[:, :n_sub].cpu().numpy()
     Ih = I[:, :n_sub].cpu().numpy()
     del P, I
-    tol = mixed_tol(m) if prec == "fp32" else fp64_tol(m)
+    tol = mixed_tol(m) if prec != "fp64" else fp64_tol(m)
     rng = np.random.default_rng(9)
     groups = rng.choice(k, 4, replace=False)
     rows = np.unique(np.concatenate([rng.choice(n_sub, 16, replace=False), [0, n_sub - 1]]))

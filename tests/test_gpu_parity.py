@@ -204,6 +204,78 @@ def test_sketch_constant_dimension_and_nonfinite(dev):
         skmp.sketch_build(_to_dev(torch, T, dev), [0, 500], 2, "gauss", 5, check_finite=True)
 
 
+def test_count_sketch_more_than_64_groups(dev, c_oracle):
+    """k = 100 (the k = ceil(sqrt d) of d = 10,000 in Section IV-A): the count
+    sketch is projected in blocks of 64 groups, the self-join runs its groups in
+    blocks of 64, top_discords combines all 100; each against the oracle."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    d, n, k, m, excl, seed = 400, 1200, 100, 32, 8, 17
+    T = datagen.tiny_series(61, d, n)
+    R, _ = skmp.sketch_build(_to_dev(torch, T, dev), [0, n], k, "count", seed)
+    P, I = skmp.mp_selfjoin(R, [0, n], k, m, excl)
+    idx, grp, score, nf = skmp.top_discords(P, [0, n], k, m, 5)
+    torch.cuda.synchronize()
+    R_o, _, _, _ = O.build(T, "count", k, seed)
+    Rg = R.cpu().numpy()
+    assert np.max(np.abs(Rg - R_o)) <= 1e-12 * np.max(np.abs(R_o))
+    n_sub = n - m + 1
+    P, I = P.cpu().numpy()[:, :n_sub], I.cpu().numpy()[:, :n_sub]
+    Ps = []
+    for g in range(k):
+        P_o, _ = c_oracle.profile(R_o[g], m, excl)
+        Ps.append(P_o)
+        if g in (0, 1, 63, 64, 65, 99):
+            ok, err = profile_close(P[g], P_o, m, fp64_tol(m))
+            assert ok.all(), (g, err)
+            check_neighbours(c_oracle, R_o[g], m, excl, np.arange(n_sub), I[g], P_o, fp64_tol(m))
+    Ps = np.stack(Ps)
+    ok, err = profile_close(P, Ps, m, fp64_tol(m))
+    assert ok.all(), err
+    ref = O.top_discords(Ps, m, 5)
+    got = [(int(i), int(g), float(v)) for i, g, v in zip(idx[0].cpu(), grp[0].cpu(), score[0].cpu())]
+    A_o = np.max(np.where(np.isfinite(Ps), Ps, -np.inf), axis=0)
+    discords_equivalent(got, ref, A_o, m, fp64_tol(m))
+    assert int(nf[0]) == 5 and all(0 <= g < k for _, g, _ in got)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_input_is_marked_without_the_check_flag(dev, c_oracle, bad):
+    """Without SKMP_FLAG_CHECK_FINITE (no host read-back: capture-safe) a NaN
+    or Inf sample is never dropped silently: its dimension's statistics come
+    back as (NaN, NaN), the sketch of that series is NaN, its windows get
+    P = NaN and I = -1 (no admissible partner would be +inf), they have no
+    discords, and the other series of the batch are unaffected."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    m, excl, k = 32, 8, 2
+    lens = [900, 1100]
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    T = np.concatenate([datagen.tiny_series(300 + q, 4, L) for q, L in enumerate(lens)], axis=1)
+    T[1, offsets[1] + 517] = bad          # series 1, dimension 1
+    R, stats = skmp.sketch_build(_to_dev(torch, T, dev), offsets, k, "gauss", 9)
+    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl)
+    idx, grp, score, nf = skmp.top_discords(P, offsets, k, m, 5)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    assert np.isnan(st[1, 1]).all() and np.isfinite(st[1, [0, 2, 3]]).all() and np.isfinite(st[0]).all()
+    Rn, P, I = R.cpu().numpy(), P.cpu().numpy(), I.cpu().numpy()
+    a, b = offsets[1], offsets[2]
+    n_sub1 = lens[1] - m + 1
+    assert np.isnan(Rn[:, a:b]).all()
+    assert np.isnan(P[:, a:a + n_sub1]).all() and (I[:, a:a + n_sub1] == -1).all()
+    assert int(nf[1]) == 0 and (idx[1].cpu().numpy() == -1).all()
+    # series 0 is the sketch and profile of its own samples
+    R_o, _, _, _ = O.build(T[:, :offsets[1]], "gauss", k, 9)
+    assert np.max(np.abs(Rn[:, :offsets[1]] - R_o)) < 1e-12 * np.max(np.abs(R_o))
+    n_sub0 = lens[0] - m + 1
+    for g in range(k):
+        P_o, _ = c_oracle.profile(R_o[g], m, excl)
+        ok, err = profile_close(P[g, :n_sub0], P_o, m, fp64_tol(m))
+        assert ok.all(), err
+    assert int(nf[0]) == 5
+
+
 # --------------------------------------------------------------- self-join
 SMALL = [  # (n, m, excl, k, seed)
     (300, 16, 4, 2, 1),
@@ -255,25 +327,41 @@ def test_selfjoin_random_walk_small_and_top10(dev, c_oracle):
     assert abs(gpu[0][0] - o) <= w.m // 2
 
 
-def test_selfjoin_flat_windows_and_exclusion_boundary(dev, c_oracle):
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("seed", [12, 13, 14])
+def test_selfjoin_flat_windows_and_exclusion_boundary(dev, c_oracle, prec, seed):
+    """Flat stretches, a single flat window, scaled exact repeats (rho = 1 up to
+    rounding: the 32-bit keys must stay positive) and a neighbour just outside
+    the exclusion zone, in every precision."""
     import torch
-    rng = np.random.default_rng(12)
+    from tests.helpers import mixed_tol
+    rng = np.random.default_rng(seed)
     m, excl = 16, 4
     r = rng.standard_normal(3000).cumsum()
     r[400:460] = 2.0            # long flat stretch
     r[1500:1516] = -7.0         # single flat window (its partners are the flat stretch above)
     r[2000:2016] = 3.0 * r[1000:1016] + 5.0   # exact repeat far away: P = 0
+    r[2600:2616] = 0.25 * r[2300:2316] - 1.0  # another scaled repeat
+    # window 2800 + excl = 1.1 (window 2800) + 1: an exact repeat excl apart (the windows overlap, so the
+    # samples are filled in order; a factor of 2 would grow the values 16-fold over the window, and the
+    # 16-bit recurrences lose accuracy on diagonals that cross such a jump in variance)
+    for t in range(m):
+        r[2800 + excl + t] = 1.1 * r[2800 + t] + 1.0
     R_np = r[None, :]
-    P, I = _run_selfjoin(torch, dev, R_np, [0, r.size], 1, m, excl)
+    _say("flat/repeats", prec, seed)
+    P, I = _run_selfjoin(torch, dev, R_np, [0, r.size], 1, m, excl, prec=prec)
     P_o, I_o = c_oracle.profile(r, m, excl)
     n_sub = len(P_o)
-    ok, err = profile_close(P[0, :n_sub], P_o, m, fp64_tol(m))
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
+    ok, err = profile_close(P[0, :n_sub], P_o, m, tol)
     assert ok.all(), (np.nonzero(~ok)[0][:10], err)
     flat = np.arange(400, 460 - m + 1)
     assert np.all(P[0, flat] == 0.0) and np.array_equal(I[0, flat], I_o[flat])
     assert P[0, 1500] == 0.0 and I[0, 1500] == 400     # flat: nearest admissible flat window
     assert P[0, 1000] < 1e-5 and I[0, 1000] == 2000
-    check_neighbours(c_oracle, r, m, excl, np.arange(n_sub), I[0, :n_sub], P_o, fp64_tol(m))
+    assert P[0, 2300] < 1e-5 and I[0, 2300] == 2600
+    assert P[0, 2800] < 1e-5 and I[0, 2800] == 2800 + excl   # partner exactly at the zone's edge
+    check_neighbours(c_oracle, r, m, excl, np.arange(n_sub), I[0, :n_sub], P_o, tol)
 
 
 def test_selfjoin_batched_uneven_series(dev, c_oracle):
