@@ -105,13 +105,15 @@ def _nonoverlapping_offsets(rng, n: int, length: int, count: int, lo: int) -> Li
 
 
 def _chirp_burst(x: np.ndarray, o: int, length: int, amp_sigmas: float) -> None:
-    """Add a swept-frequency sine burst of amplitude amp_sigmas * std(x) on [o, o+length).
+    """Add a swept-frequency sine burst on [o, o+length) whose amplitude is
+    amp_sigmas times the local sigma: the standard deviation of x over that
+    window before insertion.
 
     The frequency sweeps from 1/32 upwards so that no shifted copy of the burst
     resembles it; a fixed-period burst whose period is below the trivial-match
     zone would be matched by its own shifted copies and would not be a discord.
     """
-    s = float(np.std(x))
+    s = float(np.std(x[o:o + length]))
     if s == 0.0:
         s = 1.0
     t = np.arange(length, dtype=np.float64)
@@ -124,7 +126,7 @@ def make_random_walk_small(scale: float = 1.0, data_seed: int = 1000, sketch_see
     n = max(4 * m, int(4096 * scale))
     T = random_walk_sine(rng, d, n)
     o = int(rng.integers(m, n - 2 * m))
-    _chirp_burst(T[0], o, m, 2.0)
+    _chirp_burst(T[0], o, m, 5.0)
     return Workload("random-walk-small", np.ascontiguousarray(T), np.array([0, n], np.int64), np.arange(d, dtype=np.int64),
                     k=1, kind="sum", m=m, excl=m // 4, sketch_seed=sketch_seed, data_seed=data_seed,
                     precision="fp64", planted=[(0, 0, o, m)])
@@ -153,7 +155,7 @@ def make_water_treatment(scale: float = 1.0, data_seed: int = 1001, sketch_seed:
     for dim, o in zip(dims, offs):
         dim, o = int(dim), int(o)
         if dim < d_sens:
-            _chirp_burst(X[dim], o, m, 3.0)
+            _chirp_burst(X[dim], o, m, 5.0)
         else:
             t = np.arange(m)
             X[dim, o:o + m] = ((t // 10) % 2).astype(np.float64)  # square-wave chatter, period 20
@@ -238,7 +240,7 @@ def make_large_series(scale: float = 1.0, data_seed: int = 1004, sketch_seed: in
     offs = _nonoverlapping_offsets(rng, n, m, n_disc, m)
     planted = []
     for dim, o in zip(dims, offs):
-        _chirp_burst(T[int(dim)], int(o), m, 2.0)
+        _chirp_burst(T[int(dim)], int(o), m, 5.0)
         planted.append((0, int(dim), int(o), m))
     free = np.setdiff1d(np.arange(d), dims)
     rem_ids = np.sort(rng.choice(free, size=n_upd, replace=False)).astype(np.int64)

@@ -1302,9 +1302,14 @@ constexpr int kNumFp32Variants = sizeof(kFp32Variants) / sizeof(kFp32Variants[0]
 
 // Forms of the 16-bit split-precision join (BF16x3 / FP16x3): C = 0 the
 // Hankel-direct tiles (selfjoin_mixed.hip), C < 0 the blocked recurrence
-// (selfjoin_blocked.hip) held to -C waves per SIMD.
-static const Fp64Variant kMixedVariants[] = {
-    {"hankel", 0, nullptr, nullptr}, {"blocked_w2", -2, nullptr, nullptr}, {"blocked_w3", -3, nullptr, nullptr}};
+// (selfjoin_blocked.hip) with -C = 10 x (tiles per band) + (waves per SIMD).
+// Measured on the water-treatment join (BF16x3, refresh 256): 8 tiles at 2
+// waves per SIMD (215 VGPRs) 2.81 ms; 4 tiles at 3 waves (135 VGPRs, all
+// codes inline constants) 3.61 ms: the row reductions over fewer tiles cost
+// more than the occupancy returns; 8 tiles held to 3 waves spill (5.3 ms).
+static const Fp64Variant kMixedVariants[] = {{"hankel", 0, nullptr, nullptr},
+                                             {"blocked_w2", -82, nullptr, nullptr},
+                                             {"blocked_nb4_w3", -43, nullptr, nullptr}};
 constexpr int kNumMixedVariants = sizeof(kMixedVariants) / sizeof(kMixedVariants[0]);
 constexpr int kDefaultMixedVariant = 1;
 constexpr int kHankelVariant = 0;
@@ -1595,7 +1600,7 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   } else if (pl.total_units > 0) {
     StageTimer tm(SKMP_TIMER_TILES, st);
     if (blocked) {
-      rc = launch_sj_blk(prec, -var.C, s, pl.total_units, st);
+      rc = launch_sj_blk(prec, (-var.C) / 10, (-var.C) % 10, s, pl.total_units, st);
       if (rc) return rc;
     } else if (mfma) {
       rc = launch_sj_mfma(prec, s, pl.total_units, st);

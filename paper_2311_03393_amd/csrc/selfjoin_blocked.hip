@@ -25,8 +25,8 @@
 // masked out of the row operand.
 //
 // Geometry: a work unit is one (series, group), one strip of UR = 1024 rows
-// and one group of Q = 4 bands; a band is NB = 8 tiles side by side (128
-// diagonals), so a unit covers 512 diagonals.  One wave per unit walks the
+// and one group of Q bands; a band is NB tiles side by side (NB = 8: 128
+// diagonals, Q = 4; NB = 4: Q = 8), so a unit covers 512 diagonals.  One wave per unit walks the
 // bands one after the other, 16 rows per step, and the 8 tiles of a band
 // share the row operand; tile t at step s needs the column operand that tile
 // t + 1 used at step s - 1, so the column fragments rotate through registers
@@ -58,18 +58,16 @@ typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NB = BLK_NB;          // tiles per band
-constexpr int Q = BLK_Q;            // bands per unit
 constexpr int UR = BLK_UNIT_ROWS;   // rows per unit
-constexpr int NSEED = 16 * NB * Q + 15;  // seeds per period: columns J0 - 15 .. J0 + 16 NB Q - 1
+constexpr int UNIT_TILES = BLK_DIAGS / 16;  // tiles side by side per unit: NB per band x Q bands
+constexpr int NSEED = BLK_DIAGS + 15;  // seeds per period: columns J0 - 15 .. J0 + BLK_DIAGS - 1
 constexpr int SEED_PER_LANE = (NSEED + 63) / 64;
-constexpr int NCOLK = UR + 16 * NB * Q;  // columns a unit touches
+constexpr int NCOLK = UR + BLK_DIAGS;  // columns a unit touches
 constexpr int SCH = 96;                  // samples per exact-seed chunk
 constexpr uint32_t CODE_MASK = 1023u;
 constexpr uint32_t KEEP = ~CODE_MASK;
-constexpr int CODE_TOP = 16 * NB * Q - 1;  // code = CODE_TOP - (delta - first diagonal of the unit)
+constexpr int CODE_TOP = BLK_DIAGS - 1;  // code = CODE_TOP - (delta - first diagonal of the unit)
 static_assert(CODE_TOP + 15 <= (int)CODE_MASK, "unit too wide for the 10-bit diagonal code");
-static_assert(NB == 8, "the VGPR-held cell codes are laid out for 8 tiles per band");
 // 1 - rho + 2^-10 stays positive while rho <= 1 + 2^-10 (the 16-bit operand
 // error is ~1e-5 in rho); the bias shifts every key alike, so it changes no
 // ordering, and the global form adds it back (3 + 2^-10 - key = rho + 2).
@@ -155,8 +153,10 @@ __device__ __forceinline__ uint32_t key_of(float kf, uint32_t keep_v, const uint
 
 }  // namespace
 
-template <int PREC, int WPE>
+template <int PREC, int WPE, int NB>
 __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
+  static_assert(NB == 4 || NB == 8, "4 or 8 tiles per band");
+  constexpr int Q = UNIT_TILES / NB;  // bands per unit
   __shared__ uint32_t rowk[UR];
   __shared__ uint32_t colk[NCOLK];
   // the exact-seed stage (FP64 samples) and, once the seeds are computed, the
@@ -167,11 +167,15 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
   const int l16 = lane & 15, lg = lane >> 4;
   uint32_t keep_v;  // the key mask, held in a VGPR
   asm volatile("v_mov_b32 %0, %1" : "=v"(keep_v) : "i"(KEEP));
-  uint32_t codev[NCODEV];
+  uint32_t codev[NCODEV];  // codes above 64 (8 tiles per band only; 4 tiles' codes are all inline)
 #pragma unroll
   for (int q = 0; q < NCODEV; ++q) {
-    const uint32_t code = q < 3 ? 65u + q : 80u + 16u * ((q - 3) / 4) + (q - 3) % 4;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(codev[q]) : "v"(code));
+    if constexpr (NB == 8) {
+      const uint32_t code = q < 3 ? 65u + q : 80u + 16u * ((q - 3) / 4) + (q - 3) % 4;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(codev[q]) : "v"(code));
+    } else {
+      codev[q] = 0u;
+    }
   }
   const int P = st.strip;        // refresh period (rows), a divisor of UR and a multiple of 16 NB
   const int m = st.m;
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
     const SeriesPlan& sp = up.sp;
     const int n_sub = (int)sp.n_sub;
     const int n_cols = (int)sp.n_cols;
-    const int dbg = sp.d0 + up.inner * 16 * NB * Q;  // first diagonal of the unit
+    const int dbg = sp.d0 + up.inner * BLK_DIAGS;  // first diagonal of the unit
     const int I0 = up.outer * UR;                     // first row of the unit
     const int row_end = min(n_sub, n_cols - dbg);     // rows that have a partner on a diagonal >= dbg
     if (I0 >= row_end) continue;
@@ -463,15 +467,22 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
   }
 }
 
-int launch_sj_blk(int prec, int waves_per_simd, const SJState& s, int64_t total_units, hipStream_t st) {
+int launch_sj_blk(int prec, int tiles_per_band, int waves_per_simd, const SJState& s, int64_t total_units,
+                  hipStream_t st) {
   int dev = 0, ncu = 256, per_cu = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const void* fn;
-  void (*k)(SJState);
-  if (prec == SKMP_FP16X3) k = waves_per_simd == 3 ? sj_blk_kernel<SKMP_FP16X3, 3> : sj_blk_kernel<SKMP_FP16X3, 2>;
-  else k = waves_per_simd == 3 ? sj_blk_kernel<SKMP_BF16X3, 3> : sj_blk_kernel<SKMP_BF16X3, 2>;
-  fn = reinterpret_cast<const void*>(k);
+  void (*k)(SJState) = nullptr;
+#define SKMP_BLK_PICK(P, W, N) \
+  if (prec == P && waves_per_simd == W && tiles_per_band == N) k = sj_blk_kernel<P, W, N>;
+  SKMP_BLK_PICK(SKMP_BF16X3, 2, 8) SKMP_BLK_PICK(SKMP_BF16X3, 3, 4)
+  SKMP_BLK_PICK(SKMP_FP16X3, 2, 8) SKMP_BLK_PICK(SKMP_FP16X3, 3, 4)
+#undef SKMP_BLK_PICK
+  if (!k) {
+    set_error("no blocked MFMA kernel for this tile count and occupancy");
+    return SKMP_EINVAL;
+  }
+  const void* fn = reinterpret_cast<const void*>(k);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1) per_cu = 4;
   const int grid = (int)std::min<int64_t>((int64_t)ncu * per_cu, total_units);
   if (grid <= 0) return SKMP_OK;

@@ -245,14 +245,14 @@ int launch_sketch_coeffs_host(int32_t kind, int32_t k, uint64_t seed, const int6
 // loads with 32-bit offsets).
 constexpr int kBufWord3 = 0x00020000;
 
-// Blocked-recurrence MFMA self-join (selfjoin_blocked.hip): tiles per band,
-// bands per work unit, rows per work unit.  The refresh period P (rows) is one
-// of 128, 256, 512, 1024: a multiple of 16 BLK_NB that divides BLK_UNIT_ROWS.
-constexpr int BLK_NB = 8;
-constexpr int BLK_Q = 4;
+// Blocked-recurrence MFMA self-join (selfjoin_blocked.hip): rows and diagonals
+// of a work unit (bands of 4 or 8 tiles of 16 x 16).  The refresh period P
+// (rows) is one of 128, 256, 512, 1024: a multiple of 128 (16 rows per step,
+// the step loop unrolled by the band's tile count) that divides BLK_UNIT_ROWS.
 constexpr int BLK_UNIT_ROWS = 1024;
-constexpr int BLK_DIAGS = 16 * BLK_NB * BLK_Q;  // diagonals per work unit
-int launch_sj_blk(int prec, int waves_per_simd, const SJState& s, int64_t total_units, hipStream_t st);
+constexpr int BLK_DIAGS = 512;  // diagonals per work unit
+int launch_sj_blk(int prec, int tiles_per_band, int waves_per_simd, const SJState& s, int64_t total_units,
+                  hipStream_t st);
 
 // Power-of-two scale of the 16-bit operand planes of a series whose largest
 // |value| is maxabs (|df| <= max|r|, |dg| <= 4 max|r|; 4 max|r| = f 2^e,

@@ -8,7 +8,8 @@
 // total, in slabs), and uploads copy from that immutable copy; lookups go
 // through a hash index, so a call's cost does not grow with the number of
 // distinct tables seen (every streaming append has a plan of its own).  Outside capture a table
-// that does not fit any more is copied from the caller's memory as before;
+// that does not fit any more is copied from the caller's memory, and the call
+// waits for that copy;
 // under capture (where allocating is not allowed) a table that was never
 // uploaded outside capture is an error, so one eager call with the same
 // arguments must precede the capture.
@@ -113,7 +114,11 @@ int upload_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
               "same arguments before capturing");
     return SKMP_EINVAL;
   }
+  // Past the pinned cap: the source may be a temporary of the calling entry
+  // point, so the copy is enqueued in stream order and waited for before the
+  // call returns (only tables beyond 64 MiB of distinct content take this path).
   SKMP_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  SKMP_CHECK_HIP(hipStreamSynchronize(st));
   return SKMP_OK;
 }
 

@@ -182,3 +182,29 @@ def test_every_compiled_variant_matches_oracle(prec, c_oracle):
     finally:
         skmp.tuning_clear()
     assert tested == len(skmp.tile_variants(prec)) >= 3
+
+
+def test_upload_past_the_pinned_cache_cap():
+    """A host table larger than the library's 64 MiB pinned cache (the series
+    table of 2.2 million series, 70 MB) is copied from the caller's memory, in
+    stream order, and the call waits for the copy; twice in a row, the second
+    also past the cap, both right."""
+    import torch
+    import paper_2311_03393_amd as skmp
+    n_series, L, m = 2_200_000, 3, 2
+    offs = np.arange(n_series + 1, dtype=np.int64) * L
+    rng = np.random.default_rng(5)
+    P_np = rng.uniform(0.0, 3.0, size=(1, n_series * L))
+    P = torch.from_numpy(P_np).cuda()
+    _say("upload past cap", n_series)
+    for rep in range(2):
+        idx, grp, score, nf = skmp.top_discords(P, offs, 1, m, 1)
+        torch.cuda.synchronize()
+        w = P_np[0].reshape(n_series, L)[:, :L - m + 1]          # the two windows of every series
+        expect = np.argmax(w, axis=1)                            # first maximum on ties
+        assert np.array_equal(idx.cpu().numpy()[:, 0], expect), rep
+        assert np.array_equal(score.cpu().numpy()[:, 0], w[np.arange(n_series), expect])
+        assert (nf.cpu().numpy() == 1).all() and (grp.cpu().numpy()[:, 0] == 0).all()
+        P_np = P_np[:, ::-1].copy()                               # a different table of the same size next
+        P = torch.from_numpy(P_np).cuda()
+        offs = offs.copy()
