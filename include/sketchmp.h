@@ -411,12 +411,32 @@ int mp_selfjoin_append(const double* R, int64_t ldr, int64_t n_series, const int
  * empties the table.  Host-only, thread-safe.
  */
 size_t skmp_tuning_export(char* buf, size_t len);
-/* The names of the compiled tile-kernel variants of prec (SKMP_FP64 or
- * SKMP_FP32; others: none), one per line, in the form the tuning table uses;
+/* The names of the compiled tile-kernel variants of prec (any of the four
+ * precisions; others: none), one per line, in the form the tuning table uses;
  * buffer and return value as for skmp_tuning_export. */
 size_t skmp_tile_variants(int32_t prec, char* buf, size_t len);
 int skmp_tuning_import(const char* text);
 int skmp_tuning_clear(void);
+
+/*
+ * Persistent tuning cache.  skmp_tuning_save writes the table to the file
+ * `path` under a first line that stamps it with the current device's
+ * architecture (gcnArchName, feature flags included) and the HIP runtime
+ * version; the file is written beside `path` and renamed over it.
+ * skmp_tuning_load adds the file's entries to the table when its stamp equals
+ * the current one and returns the number of entries loaded: 0 when the file
+ * does not exist or carries another stamp (nothing changed), SKMP_EINVAL on a
+ * file that is not a tuning table or holds a malformed line (nothing changed),
+ * SKMP_EDEVICE when no HIP device is present to stamp against.
+ * With the environment variable SKMP_TUNING_FILE set, the process's first
+ * tuning lookup (a self-join, an autotuning run or skmp_tuning_export) loads
+ * that file, and mp_selfjoin_autotune saves the table to it after each run
+ * (its error, if the file cannot be written, is the call's).
+ * Host only; a file shared by processes that tune at the same time keeps
+ * the last writer's table.
+ */
+int skmp_tuning_save(const char* path);
+int skmp_tuning_load(const char* path);
 
 /* Workspace bytes needed by top_discords. */
 size_t top_discords_workspace(int64_t n_series, const int64_t* offsets, int32_t k, int32_t m);

@@ -45,7 +45,7 @@ EXPORTED = ("skmp_last_error", "skmp_version", "sketch_coeffs", "sketch_default_
             "mp_selfjoin_autotune", "mp_abjoin_workspace", "mp_abjoin", "dim_detect_workspace", "dim_detect",
             "sketch_append_workspace", "sketch_append", "sketch_point_update_workspace", "sketch_point_update",
             "mp_selfjoin_append_workspace", "mp_selfjoin_append", "skmp_tuning_export", "skmp_tile_variants",
-            "skmp_tuning_import", "skmp_tuning_clear",
+            "skmp_tuning_import", "skmp_tuning_clear", "skmp_tuning_save", "skmp_tuning_load",
             "top_discords_workspace", "top_discords", "top_discords_noalloc", "skmp_timing_enable",
             "skmp_timing_read")
 TIMERS = {"sketch": 0, "substats": 1, "tiles": 2, "merge": 3, "discords": 4, "dimdetect": 5}
@@ -119,6 +119,8 @@ def lib():
         L.skmp_tuning_export.argtypes = [ctypes.c_char_p, _sz]
         L.skmp_tuning_export.restype = _sz
         L.skmp_tuning_import.argtypes = [ctypes.c_char_p]
+        L.skmp_tuning_save.argtypes = [ctypes.c_char_p]
+        L.skmp_tuning_load.argtypes = [ctypes.c_char_p]
         L.skmp_tile_variants.argtypes = [_i32, ctypes.c_char_p, _sz]
         L.skmp_tile_variants.restype = _sz
         L.skmp_timing_enable.argtypes = [ctypes.c_int]
@@ -491,6 +493,18 @@ def tuning_import(text: str) -> None:
 
 def tuning_clear() -> None:
     _check(lib().skmp_tuning_clear())
+
+
+def tuning_save(path: str) -> None:
+    """Write the tuning table to `path`, stamped with the device architecture and HIP runtime version."""
+    _check(lib().skmp_tuning_save(os.fsencode(path)))
+
+
+def tuning_load(path: str) -> int:
+    """Add the entries of a tuning file written under the current stamp; returns how many (0: missing or stale)."""
+    rc = lib().skmp_tuning_load(os.fsencode(path))
+    _check(min(rc, 0))
+    return rc
 
 
 def top_discords(P, offsets, k: int, m: int, top_k: int, halfwidth: int = 0, out=None):

@@ -194,6 +194,18 @@ def test_tuning_table_round_trip_and_validation(L):
     assert skmp.tuning_export() == ""
 
 
+def test_tuning_file_without_device(L, tmp_path):
+    """The persistent tuning cache: a missing file loads nothing; saving, or
+    loading an existing file, needs a device to stamp against and says so."""
+    assert L.skmp_tuning_load(str(tmp_path / "absent.txt").encode()) == 0
+    assert L.skmp_tuning_load(b"") == -1 and L.skmp_tuning_save(None) == -1
+    (tmp_path / "t.txt").write_text("# sketchmp-tuning v1 arch=gfx950 hip=1\n")
+    assert L.skmp_tuning_load(str(tmp_path / "t.txt").encode()) == -3
+    assert b"device" in L.skmp_last_error()
+    assert L.skmp_tuning_save(str(tmp_path / "u.txt").encode()) == -3
+    assert not (tmp_path / "u.txt").exists()
+
+
 def test_autotune_rejects_bad_arguments_before_launch(L):
     a, p = _offs(0, 300)
     fake = ctypes.c_void_p(16)

@@ -8,6 +8,7 @@ input between replays.  Every replay must reproduce the eager results bit for
 bit (the kernels are deterministic: maxima of packed keys, FP64 polish).
 The eager results themselves are held to the oracle by the parity tests.
 """
+import os
 import sys
 
 import numpy as np
@@ -16,6 +17,7 @@ import pytest
 import datagen
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _say(*a):
@@ -140,6 +142,56 @@ def test_autotune_choice_is_used_and_exact(prec, c_oracle):
         assert ok.all(), err
         check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g, :n_sub], P_o, tol)
     skmp.tuning_clear()
+
+
+def test_tuning_file_round_trip_and_stamp(tmp_path):
+    """The persistent tuning cache: a saved table loads back under the same
+    device and runtime stamp, a file stamped for another device or runtime
+    loads nothing, and with SKMP_TUNING_FILE set an autotuning result made in
+    one process is the table of the next."""
+    import subprocess
+    import paper_2311_03393_amd as skmp
+    path = tmp_path / "tune.txt"
+    skmp.tuning_clear()
+    rows = "0 7 16 c8_pd2_w2_clfalse 4096 3.250000\n2 6 15 blocked_w2 256 2.000000\n"
+    skmp.tuning_import(rows)
+    skmp.tuning_save(str(path))
+    head, body = path.read_text().split("\n", 1)
+    assert head.startswith("# sketchmp-tuning v1 arch=gfx950") and " hip=" in head
+    assert sorted(body.splitlines()) == sorted(rows.splitlines())
+    skmp.tuning_clear()
+    assert skmp.tuning_load(str(path)) == 2
+    assert sorted(skmp.tuning_export().splitlines()) == sorted(rows.splitlines())
+    skmp.tuning_clear()
+    (tmp_path / "other.txt").write_text(head.replace("hip=", "hip=9") + "\n" + body)
+    assert skmp.tuning_load(str(tmp_path / "other.txt")) == 0 and skmp.tuning_export() == ""
+    (tmp_path / "bad.txt").write_text(head + "\n0 7 16 no_such_variant 4096 1.0\n")
+    with pytest.raises(skmp.SketchMPError):
+        skmp.tuning_load(str(tmp_path / "bad.txt"))
+    (tmp_path / "foreign.txt").write_text("0 7 16 c8_pd2_w2_clfalse 4096 1.0\n")
+    with pytest.raises(skmp.SketchMPError):
+        skmp.tuning_load(str(tmp_path / "foreign.txt"))
+    assert skmp.tuning_export() == ""
+    # two child processes sharing SKMP_TUNING_FILE: the first autotunes a
+    # small FP32 join, the second sees its choice without tuning
+    cache = tmp_path / "cache.txt"
+    child = (
+        "import sys, torch, numpy as np, paper_2311_03393_amd as skmp\n"
+        "if sys.argv[1] == 'tune':\n"
+        "    R = torch.from_numpy(np.random.default_rng(3).standard_normal((1, 3000))).cuda()\n"
+        "    c = skmp.mp_selfjoin_autotune(R, [0, 3000], 1, 32, 8, prec='fp32', reps=1)\n"
+        "    print('TUNED', c['variant'], flush=True)\n"
+        "print('TABLE', skmp.tuning_export().replace(chr(10), ';'), flush=True)\n")
+    env = dict(os.environ, SKMP_TUNING_FILE=str(cache))
+    outs = []
+    for mode in ("tune", "read"):
+        _say("tuning-file child", mode)
+        r = subprocess.run([sys.executable, "-c", child, mode], env=env, cwd=ROOT, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append([ln for ln in r.stdout.splitlines() if ln.startswith("TABLE")][0])
+    assert outs[0] == outs[1] and outs[0].startswith("TABLE 1 5 12 f32_")
+    assert cache.read_text().startswith(head)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
