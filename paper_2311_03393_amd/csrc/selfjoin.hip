@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <climits>
@@ -485,20 +486,20 @@ __device__ __forceinline__ void sj_run_groups(LaneState<C>& ls, StepLoad (&ring)
 // and column of a unit is thereby flushed once.  to_global(key, delta) forms
 // the global 64-bit key of a local key whose partner lies delta diagonals up.
 // The local code in a key's low bits names the cell's diagonal within the
-// band: QB = 0: code = LMAX - (t C + q) (lane t, its diagonal q); QB > 0:
-// code = (63 - t) 2^QB + (2^QB - 1 - q), decoded from its two bit fields
-// (the field may be narrower than LMAX).
+// band: QB = 0: code = LMAX - (t C + q) (lane t, its diagonal q); QB < 0:
+// code = 63 - t in the low 6 bits, naming only the lane, whose C diagonals
+// then all go up to the global key as the first of them (the key's partner
+// is one of C consecutive ones).
 template <int C, int TL, int QB = 0, typename K, typename G, typename V>
 __device__ __forceinline__ void flush_block(K* rowk, K* colk, bool last, int u0, int db, int n_rows, int n_cols, int t,
                                             unsigned long long* gro, unsigned long long* gco, K empty, G to_global,
                                             V valid) {
   constexpr int NROW = TL + 64, NCOL = TL + 64 * C;
   constexpr int RPL = (NROW + 63) / 64, CPL = (NCOL + 63) / 64;
-  constexpr uint32_t LMAX = (64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u);
+  constexpr uint32_t LMAX = (QB < 0) ? 63u : ((64 * C <= 512) ? 511u : ((64 * C <= 1024) ? 1023u : 2047u));
   auto diag = [](uint32_t code) -> int {
-    if constexpr (QB > 0) {
-      constexpr uint32_t QM = (1u << QB) - 1;
-      return (63 - (int)(code >> QB)) * C + (int)(QM - (code & QM));
+    if constexpr (QB < 0) {
+      return (63 - (int)code) * C;  // the first of the lane's C diagonals
     } else {
       return (int)(LMAX - code);
     }
@@ -657,12 +658,14 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
 // statistics and the keys in FP32: C(i+1, j+1) = C(i, j) + df_i dg_j + df_j dg_i
 // in FP32 from an exact FP64 seed recomputed at the start of every strip
 // (the strip length is the refresh period).  Keys are the bits of the FP32
-// value 1 - rho + 2^-10 in (0, 2] with the local diagonal in the low LBITS
-// bits; as positive floats they order like unsigned integers, so the nearest
-// neighbour is a 32-bit integer minimum (v_min3_u32).  Relative to rho + 2 in
-// [1, 3] this resolves candidates relative to their own distance (for
-// 1 - rho ~ 0.2 about 3e-6 in rho instead of 2.4e-4), so near ties between
-// neighbours are decided far below the tolerance.  Padded cells give NaN
+// value 1 - rho + 2^-10 in (0, 2]; as positive floats they order like
+// unsigned integers, so the nearest neighbour is a 32-bit integer minimum
+// (v_min3_u32).  What reaches LDS has the lane's code in the low 6 bits, so
+// the key keeps 17 of the 23 fraction bits: relative to its own distance,
+// 1 - rho ~ 0.2 is resolved to 2^-20 (about 1e-6; rho + 2 in [1, 3] would
+// resolve 2.4e-4), and near ties are decided far below the tolerance.  A key
+// names the lane, not its diagonal: the merge scores the lane's C diagonals
+// exactly and keeps the best (kgroup = C).  Padded cells give NaN
 // keys, whose bits lie above every real key, so the minima ignore them.
 // Flushing converts a key f to the global form 3 + 2^-10 - f = rho + 2 (maxima).
 // The bias 2^-10 keeps the key positive while rho <= 1 + 2^-10: FP32 drift
@@ -717,18 +720,17 @@ struct LaneStateF {
   uint32_t colacc[C];
 };
 
-// Bits of the diagonal q (of the lane's C) in the FP32 local codes: the key of
-// a cell carries 2^QB - 1 - q, a compile-time constant, and the lane's bits
-// (63 - t) 2^QB are ORed in once per step, when the row minimum and the
-// retiring column minimum go to LDS (every key they combine is the lane's own).
-template <int C>
-constexpr int fp32_qbits() { return C <= 2 ? 1 : (C <= 4 ? 2 : (C <= 8 ? 3 : 4)); }
-
+// A cell's key is the bare bits of its FP32 value: which of the lane's C
+// diagonals it came from is not recorded.  The lane's row minimum of a step
+// and a retiring column minimum (every key they combine is the lane's own)
+// have their low 6 bits replaced by the lane's code 63 - t once, on their way
+// to LDS; the merge later finds the partner among the lane's C diagonals.
+// Truncating the low bits is monotone, so the truncated minimum is the
+// minimum of the truncated keys.
 template <int C, int PD>
 __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], uint32_t lcode,
                                                uint32_t keep, int ngroups, int u0, int db, const StatRsrcF& R,
                                                uint32_t* rowk, uint32_t* colk, int t) {
-  constexpr uint32_t QM = (1u << fp32_qbits<C>()) - 1;
   for (int gidx = 0; gidx < ngroups; ++gidx) {
 #pragma unroll
     for (int p = 0; p < C; ++p) {
@@ -751,15 +753,15 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
         // 1 - rho (+ 2^-10 so FP32 rounding never makes it negative): a positive
         // float, resolved relative to itself, so close candidates stay apart
         const float kf = __builtin_fmaf(-a, cur.rinv, KEY_ONE);
-        const uint32_t key = (__float_as_uint(kf) & keep) | (QM - q);  // padded cells: NaN bits, above every key
+        const uint32_t key = __float_as_uint(kf);  // padded cells: NaN bits, above every key
         rowp = (q == 0) ? key : min(rowp, key);
         if (q == C - 1) ls.colacc[sl] = key;
         else ls.colacc[sl] = min(ls.colacc[sl], key);
         ls.Cq[q] = __builtin_fmaf(cur.rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = __builtin_fmaf(ls.cdf[sl], cur.rs.y, ls.Cq[q]);
       }
-      atomicMin(&rowk[us + 63 - t], rowp | lcode);
-      atomicMin(&colk[us + t * (C - 1)], ls.colacc[p] | lcode);
+      atomicMin(&rowk[us + 63 - t], (rowp & keep) | lcode);
+      atomicMin(&colk[us + t * (C - 1)], (ls.colacc[p] & keep) | lcode);
     }
   }
 }
@@ -768,10 +770,9 @@ template <int C, int TL, int PD, int WPE>
 __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   constexpr int NROW = TL + 64;
   constexpr int NCOL = TL + 64 * C;
-  constexpr int LBITS = (64 * C <= 512) ? 9 : ((64 * C <= 1024) ? 10 : 11);
-  constexpr uint32_t LMAX = (1u << LBITS) - 1;
+  constexpr uint32_t LMAX = 63u;  // local code: the lane
   static_assert(TL % C == 0, "tile length must be a multiple of C");
-  static_assert(C >= 2 && 64 * C <= 1024, "C diagonals per lane, local codes of at most 10 bits");
+  static_assert(C >= 2 && C <= 16, "C diagonals per lane (the merge searches at most 16)");
   constexpr int MCH = seed_chunk<C, WPE>();
   __shared__ __align__(16) uint32_t lds[tile_lds_bytes<uint32_t, NROW, NCOL, C, MCH>() / 4];
   uint32_t* rowk = lds;
@@ -779,9 +780,7 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   double* sseed = reinterpret_cast<double*>(lds);
   const int t = threadIdx.x;
   const uint32_t keep = ~LMAX;
-  constexpr int QB = fp32_qbits<C>();
-  static_assert((64u << QB) - 1 <= LMAX, "lane and diagonal bits fit the local code");
-  const uint32_t lcode = (uint32_t)(63 - t) << QB;
+  const uint32_t lcode = (uint32_t)(63 - t);
   const unsigned long long GMAX = (1ull << st.key_bits) - 1;
   const int m = st.m;
 
@@ -856,9 +855,10 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
       const bool last = (u0 + TL >= u_end);
       if (last) {
 #pragma unroll
-        for (int q = 0; q < C - 1; ++q) atomicMin(&colk[ngroups * C + t * (C - 1) + q], ls.colacc[q] | lcode);
+        for (int q = 0; q < C - 1; ++q)
+          atomicMin(&colk[ngroups * C + t * (C - 1) + q], (ls.colacc[q] & keep) | lcode);
       }
-      flush_block<C, TL, QB>(
+      flush_block<C, TL, -1>(
           rowk, colk, last, u0, db, n_sub, n_cols, t, gro, gco, 0xFFFFFFFFu,
           [GMAX](uint32_t key, int delta) {
             // local keys order by 1 - rho + 2^-10 (min); the global ones by
@@ -978,8 +978,79 @@ __global__ __launch_bounds__(256) void append_direct_kernel(SJState st) {
   if ((int)threadIdx.x < A && ckey[threadIdx.x] != 0ull) atomicMax(st.colkey + sbase + keep + threadIdx.x, ckey[threadIdx.x]);
 }
 
+// The partner named by a key of a tile kernel that records only a lane's
+// group of G <= 16 consecutive diagonals: the candidates are p0 + dir q,
+// q < G (dir = +1: row key, partners above; -1: column key, partners below).
+// Each admissible candidate (a window of the column series, at least pexcl
+// from x, with finite statistics, and at or after `keep` when x is an old
+// window of an append) is scored by the exact FP64 correlation of the centred
+// windows; a flat candidate scores the flat distance sqrt(m).  The best
+// squared distance wins, ties to the smaller index; -1 if none is admissible.
+// The 16 correlations are one sliding product: the partner samples pass
+// through a ring of 16 registers, each sample loaded once.  Buffer loads
+// (global only, so they stay in flight across the LDS reads of the window's
+// own samples) read zeros past the column series' end: candidates there are
+// discarded.  The 16 scored positions start at the group's first candidate
+// or at 0, whichever is larger, so no offset is ever negative: the compiler
+// folds parts of an index into the loads' immediate offsets, and a negative
+// register offset fails the buffer's range check even where the immediate
+// brings the sum back into range.
+__device__ int64_t best_in_group(const double* wx, double mx, double ix, const double* rc, int64_t cn,
+                                 const double* cmu, const double* cinvn, int64_t n_cols, int64_t x, int64_t p0, int dir,
+                                 int G, int pexcl, int64_t keep, int m) {
+  const int64_t glo = dir > 0 ? p0 : p0 - (G - 1), ghi = glo + G - 1;  // the group's candidates
+  const int64_t lo = glo < 0 ? 0 : glo;
+  const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc((void*)rc, 0, (int)(cn * 8), kBufWord3);
+  auto sample = [&](int64_t i) -> double {  // i >= 0
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(yr, (int)i * 8, 0, 0));
+  };
+  const double shift = sample(p0 < 0 ? 0 : (p0 >= cn ? cn - 1 : p0));
+  double yw[16], acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    yw[q] = sample(lo + q) - shift;
+    acc[q] = 0.0;
+  }
+  double se = 0.0;
+  // no branches inside a block of 16 samples (past m the window's samples
+  // read as zero: the stage holds 16 zeros after the last window), so each
+  // load has a whole block of products to arrive
+  for (int s0 = 0; s0 < m; s0 += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int sidx = s0 + u;
+      const double e = sidx < m ? wx[sidx] - mx : 0.0;
+      se += e;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = fma(e, yw[(q + u) & 15], acc[q]);
+      yw[u] = sample(lo + sidx + 16) - shift;  // slot u next holds sample lo + s + 16
+    }
+  }
+  const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc((void*)cinvn, 0, (int)(n_cols * 8), kBufWord3);
+  const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc((void*)cmu, 0, (int)(n_cols * 8), kBufWord3);
+  int64_t arg = -1;
+  double best = INFINITY;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int64_t p = lo + q;
+    const double ip = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ir, (int)p * 8, 0, 0));
+    const double mp = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(mr, (int)p * 8, 0, 0));
+    const bool ok = p <= ghi && p < n_cols && (p > x ? p - x : x - p) >= pexcl && !(x < keep && p < keep) &&
+                    !isnan(ip);
+    const double rho = (acc[q] - (mp - shift) * se) * ix * ip;
+    const double d2 = ip == 0.0 ? (double)m : 2.0 * m * (1.0 - rho);
+    if (ok && d2 < best) {  // ascending p: a tie keeps the smaller index
+      best = d2;
+      arg = p;
+    }
+  }
+  return arg;
+}
+
 __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
-  extern __shared__ double sh_w[];  // samples [x0, x0 + 256 + m - 1) of the chunk: the block's own windows
+  // samples [x0, x0 + 256 + m - 1) of the chunk (the block's own windows),
+  // then 16 zeros read by the group search past the last window's samples
+  extern __shared__ double sh_w[];
   const ChunkPos c = decode_chunk(st, blockIdx.x);
   const SeriesPlan& sp = st.plan[c.s];
   if (sp.p0 == nullptr) return;  // this series' profile is not wanted
@@ -987,9 +1058,9 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   const int m = st.m;
   const int g = st.groups.g[c.gi];
   const double* r = sp.r0 + (int64_t)g * sp.ldr;
-  for (int q = threadIdx.x; q < 256 + m - 1; q += 256) {
+  for (int q = threadIdx.x; q < 256 + m - 1 + 16; q += 256) {
     const int64_t t = c.x0 + q;
-    sh_w[q] = (t >= 0 && t < sp.n) ? r[t] : 0.0;
+    sh_w[q] = (q < 256 + m - 1 && t >= 0 && t < sp.n) ? r[t] : 0.0;
   }
   __syncthreads();
   if (x < 0 || x >= sp.n_sub) return;
@@ -1015,8 +1086,17 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   }
   const unsigned long long rk = st.rowkey[sbase + x], ck = st.colkey[sbase + x];
   int64_t partner = -1;
-  if (ck != 0ull && ck >= rk) partner = x - (int64_t)(GMAX - (ck & GMAX));
-  else if (rk != 0ull) partner = x + (int64_t)(GMAX - (rk & GMAX));
+  int dir = 0;
+  if (ck != 0ull && ck >= rk) {
+    partner = x - (int64_t)(GMAX - (ck & GMAX));
+    dir = -1;
+  } else if (rk != 0ull) {
+    partner = x + (int64_t)(GMAX - (rk & GMAX));
+    dir = 1;
+  }
+  if (st.kgroup > 1 && dir != 0 && invn[x] != 0.0)
+    partner = best_in_group(sh_w + threadIdx.x, mu[x], invn[x], rc, sp.cn, cmu, cinvn, n_cols, x, partner, dir,
+                            st.kgroup, pexcl, sp.keep, m);
 
   const double sqrt_m = sqrt((double)m);
   const int64_t sg = (int64_t)sp.cs * st.groups.count + c.gi;
@@ -1387,7 +1467,10 @@ static const Fp64Variant* variants_of(int prec, int* count) {
   return kFp64Variants;
 }
 
+static void tuning_file_autoload();
+
 static void select_config(int prec, int refresh, const TuneKey& key, int* vidx, int* strip) {
+  tuning_file_autoload();
   static const int env64 = env_int("SKMP_FP64_VARIANT", 0, kNumFp64Variants - 1);
   static const int env32 = env_int("SKMP_FP32_VARIANT", 0, kNumFp32Variants - 1);
   static const int envmx = env_int("SKMP_MIXED_VARIANT", 0, kNumMixedVariants - 1);
@@ -1564,6 +1647,7 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
   s.total_units = pl.total_units;
   s.total_chunks = pl.total_chunks;
   s.strip = strip;
+  s.kgroup = 1;
 
   const dim3 fb(256);
   {
@@ -1608,12 +1692,13 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
     } else {
       const int grid = (int)std::min<int64_t>(grid_for(var.fn, 64, 0), pl.total_units);
       var.launch(dim3(grid), st, s);
+      if (prec == SKMP_FP32) s.kgroup = var.C;  // its keys name a lane's C diagonals
     }
   }
   SKMP_CHECK_HIP(hipGetLastError());
   {
     StageTimer tm(SKMP_TIMER_MERGE, st);
-    hipLaunchKernelGGL(merge_kernel, cg, fb, sizeof(double) * (256 + m - 1), st, s);
+    hipLaunchKernelGGL(merge_kernel, cg, fb, sizeof(double) * (256 + m - 1 + 16), st, s);
   }
   SKMP_CHECK_HIP(hipGetLastError());
   return SKMP_OK;
@@ -1775,6 +1860,7 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   SKMP_REQUIRE(k <= 64, "autotuning takes at most 64 groups (tune on a block of them)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   SKMP_REQUIRE(!stream_capturing(st), "autotuning waits for the GPU and cannot run under graph capture");
+  tuning_file_autoload();
   GroupList gl;
   active_groups(k, k < 64 ? (1ull << k) - 1 : ~0ull, gl);
   int nv = 0;
@@ -1830,6 +1916,9 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(prec, m, n_series, offsets)] = TuneChoice{best_v, best_s, best};
   }
+  if (const char* f = getenv("SKMP_TUNING_FILE")) {
+    if (*f && (rc = skmp_tuning_save(f)) != SKMP_OK) return rc;
+  }
   if (variant) *variant = best_v;
   if (strip) *strip = best_s;
   if (best_ms) *best_ms = best;
@@ -1851,21 +1940,25 @@ extern "C" size_t skmp_tile_variants(int32_t prec, char* buf, size_t len) {
   return text.size() + 1;
 }
 
-extern "C" size_t skmp_tuning_export(char* buf, size_t len) {
+static std::string tuning_text() {
   std::string text;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (const auto& kv : g_tune) {
-      // variants are named, not numbered: a table stays valid across builds
-      // whose variant lists differ
-      int nv = 0;
-      const Fp64Variant* vs = variants_of(kv.first.prec, &nv);
-      char line[200];
-      snprintf(line, sizeof(line), "%d %d %d %s %d %.6f\n", kv.first.prec, kv.first.mlog, kv.first.nlog,
-               vs[kv.second.variant].name, kv.second.strip, kv.second.ms);
-      text += line;
-    }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& kv : g_tune) {
+    // variants are named, not numbered: a table stays valid across builds
+    // whose variant lists differ
+    int nv = 0;
+    const Fp64Variant* vs = variants_of(kv.first.prec, &nv);
+    char line[200];
+    snprintf(line, sizeof(line), "%d %d %d %s %d %.6f\n", kv.first.prec, kv.first.mlog, kv.first.nlog,
+             vs[kv.second.variant].name, kv.second.strip, kv.second.ms);
+    text += line;
   }
+  return text;
+}
+
+extern "C" size_t skmp_tuning_export(char* buf, size_t len) {
+  tuning_file_autoload();
+  const std::string text = tuning_text();
   if (buf && len > 0) {
     const size_t n = std::min(len - 1, text.size());
     memcpy(buf, text.data(), n);
@@ -1914,3 +2007,84 @@ extern "C" int skmp_tuning_clear(void) {
   g_tune.clear();
   return SKMP_OK;
 }
+
+// The stamp a tuning file is written under: the current device's
+// architecture (with its feature flags) and the HIP runtime version.  A file
+// whose stamp differs was measured on other hardware or software and is not
+// loaded.
+static int tuning_stamp(std::string& out) {
+  int dev = 0, rt = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      hipRuntimeGetVersion(&rt) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("tuning file: no HIP device to stamp the table with");
+    return SKMP_EDEVICE;
+  }
+  char line[320];
+  snprintf(line, sizeof(line), "# sketchmp-tuning v1 arch=%s hip=%d", prop.gcnArchName, rt);
+  out = line;
+  return SKMP_OK;
+}
+
+extern "C" int skmp_tuning_save(const char* path) {
+  clear_error();
+  SKMP_REQUIRE(path && *path, "null or empty path");
+  std::string stamp;
+  if (int rc = tuning_stamp(stamp)) return rc;
+  const std::string text = stamp + "\n" + tuning_text();
+  // written beside the target and renamed over it, so a reader never sees a
+  // partial file
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) {
+    set_error("tuning file: cannot write " + tmp);
+    return SKMP_EINVAL;
+  }
+  const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+  if (fclose(f) != 0 || !ok || rename(tmp.c_str(), path) != 0) {
+    (void)remove(tmp.c_str());
+    set_error(std::string("tuning file: cannot write ") + path);
+    return SKMP_EINVAL;
+  }
+  return SKMP_OK;
+}
+
+extern "C" int skmp_tuning_load(const char* path) {
+  clear_error();
+  SKMP_REQUIRE(path && *path, "null or empty path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return 0;  // no cache yet
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  fclose(f);
+  std::string stamp;
+  if (int rc = tuning_stamp(stamp)) return rc;
+  const size_t eol = text.find('\n');
+  const std::string first = text.substr(0, eol);
+  if (first.rfind("# sketchmp-tuning ", 0) != 0) {
+    set_error(std::string("tuning file: not a tuning table: ") + path);
+    return SKMP_EINVAL;
+  }
+  if (first != stamp) return 0;  // measured under another device or runtime
+  const std::string body = eol == std::string::npos ? std::string() : text.substr(eol + 1);
+  if (int rc = skmp_tuning_import(body.c_str())) return rc;
+  int lines = 0;
+  for (char c : body) lines += (c == '\n');
+  return lines;
+}
+
+// With SKMP_TUNING_FILE set, the first tuning lookup of the process loads
+// that file (a missing or stale file loads nothing, an unreadable one is
+// ignored), and every autotuning result is saved to it.
+namespace skmp {
+static void tuning_file_autoload() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const char* f = getenv("SKMP_TUNING_FILE");
+    if (f && *f) (void)skmp_tuning_load(f);
+  });
+}
+}  // namespace skmp

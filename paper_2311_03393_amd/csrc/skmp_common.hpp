@@ -145,6 +145,8 @@ struct SJState {
   int32_t walk_stats;   // 1: substats also writes what the diagonal walks read (df, dg in both layouts, FP32 copies)
   uint16_t* bplanes;    // blocked MFMA form: 16-bit hi / lo operand planes of df, dg (NULL when unused)
   int32_t bprec;        // their format: SKMP_BF16X3 or SKMP_FP16X3
+  int32_t kgroup;       // 1: a key's diagonal is its partner's; G > 1: the first of G consecutive
+                        // diagonals, one of which holds the partner (the merge finds it exactly)
 };
 
 __device__ __forceinline__ int find_series(const SeriesPlan* plan, int n_series, int64_t key,
