@@ -339,10 +339,22 @@ __device__ __forceinline__ void exact_seeds(double* stage, const double* __restr
   double sa = 0.0;
 #pragma unroll
   for (int q = 0; q < C; ++q) acc[q] = 0.0;
+  constexpr int NR = (64 + MCH + 63) / 64, NCS = (64 * C + MCH + 63) / 64;
   for (int x0 = 0; x0 < m; x0 += MCH) {
+    // every load of the chunk is issued before the first store (clamped
+    // indices: all in bounds), so their latencies overlap
+    double vr[NR], vc[NCS];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) vr[k] = r[min(rbase + x0 + t + 64 * k, nlast)];
+#pragma unroll
+    for (int k = 0; k < NCS; ++k) vc[k] = rc[min(cbase + x0 + t + 64 * k, nlast_c)];
     __syncthreads();  // the previous chunk (or the caller's use of the stage) is done
-    for (int i = t; i < 64 + MCH; i += 64) srow[i] = r[min(rbase + x0 + i, nlast)];
-    for (int i = t; i < 64 * C + MCH; i += 64) scol[i] = rc[min(cbase + x0 + i, nlast_c)];
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if (t + 64 * k < 64 + MCH) srow[t + 64 * k] = vr[k];
+#pragma unroll
+    for (int k = 0; k < NCS; ++k)
+      if (t + 64 * k < 64 * C + MCH) scol[t + 64 * k] = vc[k];
     __syncthreads();
     const int xe = min(MCH, m - x0);
     int xx = 0;
@@ -365,8 +377,11 @@ __device__ __forceinline__ void exact_seeds(double* stage, const double* __restr
       for (int q = 0; q < C; ++q) acc[q] = fma(a, scol[co + xx + q], acc[q]);
     }
   }
+  double mq[C];
 #pragma unroll
-  for (int q = 0; q < C; ++q) acc[q] = (j0 + q < n_cols) ? fma(-muc[min(j0 + q, n_cols - 1)], sa, acc[q]) : 0.0;
+  for (int q = 0; q < C; ++q) mq[q] = muc[min(j0 + q, n_cols - 1)];
+#pragma unroll
+  for (int q = 0; q < C; ++q) acc[q] = (j0 + q < n_cols) ? fma(-mq[q], sa, acc[q]) : 0.0;
 }
 
 template <int C>
