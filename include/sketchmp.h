@@ -180,8 +180,9 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  *            covariance (0 = the larger of 256 and 2.5 m rounded up to a
  *            multiple of 256).  BF16x3 / FP16x3, blocked form: the period is
  *            the largest of 128, 256, 512, 1024 rows not above `refresh`
- *            (0 = 256); a refresh below 128 selects the Hankel-direct form,
- *            which walks no rows.  Ignored by SKMP_FP64.
+ *            (0 = the smallest of 256, 512, 1024 that is at least 4 m; 1024
+ *            above m = 256); a refresh below 128 selects the Hankel-direct
+ *            form, which walks no rows.  Ignored by SKMP_FP64.
  *   k        1 <= k <= 128; more than 64 groups are joined in blocks of 64
  *            (one launch sequence per block, in stream order) and then need
  *            group_mask = ~0.

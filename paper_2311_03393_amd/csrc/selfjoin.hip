@@ -1410,10 +1410,15 @@ constexpr int kDefaultMixedVariant = 1;
 constexpr int kHankelVariant = 0;
 
 // Refresh period of the blocked form: the largest of 128, 256, 512, 1024 rows
-// not above `refresh` (0: 256).  Periods must be multiples of 16 BLK_NB that
-// divide the unit's BLK_UNIT_ROWS.
-static int blk_period(int refresh) {
-  if (refresh <= 0) return 256;
+// not above `refresh`; 0: the smallest of 256, 512, 1024 that is at least
+// 4 m (1024 above m = 256), so the exact FP64 seeds (m FP64 FMAs per diagonal
+// per period) stay near a quarter FMA per cell.  Measured: transportation
+// (m = 288) 39.1 ms at 256 rows, 33.6 at 512, 30.7 at 1024 (FP64 path 41 ms);
+// the error against the FP64 path stays at 6-7e-4 (it comes from the 16-bit
+// operands, not from the walk's length).  Periods must be multiples of 16
+// BLK_NB that divide the unit's BLK_UNIT_ROWS.
+static int blk_period(int refresh, int m) {
+  if (refresh <= 0) return 4 * m <= 256 ? 256 : (4 * m <= 512 ? 512 : 1024);
   int p = 128;
   while (p * 2 <= refresh && p * 2 <= BLK_UNIT_ROWS) p *= 2;
   return p;
@@ -1501,7 +1506,7 @@ static void select_config(int prec, int refresh, const TuneKey& key, int* vidx, 
     }
     if (envmx >= 0) v = envmx;
     *vidx = v;
-    *strip = blk_period(refresh);
+    *strip = blk_period(refresh, key.m);
     return;
   }
   int v = (prec == SKMP_FP32) ? kDefaultFp32Variant : kDefaultFp64Variant;
@@ -1883,7 +1888,7 @@ extern "C" int mp_selfjoin_autotune(const double* R, int64_t ldr, int64_t n_seri
   std::vector<int> strips;
   const bool mixed = (prec == SKMP_BF16X3 || prec == SKMP_FP16X3);
   if (prec == SKMP_FP32) strips.push_back(refresh > 0 ? refresh : default_refresh(m));
-  else if (mixed) strips.push_back(blk_period(refresh));
+  else if (mixed) strips.push_back(blk_period(refresh, m));
   else strips.assign(std::begin(kTuneStrips), std::end(kTuneStrips));
   hipEvent_t e0, e1;
   SKMP_CHECK_HIP(hipEventCreate(&e0));
