@@ -1353,6 +1353,7 @@ struct Fp64Variant {
   int C;
   const void* fn;
   void (*launch)(dim3 grid, hipStream_t st, const SJState& s);
+  int group;  // diagonals a local key names (0 or 1: its own)
 };
 
 // tile length: the largest multiple of C not above 256
@@ -1385,7 +1386,7 @@ static void launch_fp32(dim3 grid, hipStream_t st, const SJState& s) {
 #define SKMP_FP32_V(C, PD, WPE)                                                                              \
   {                                                                                                          \
     "f32_c" #C "_pd" #PD "_w" #WPE, C, reinterpret_cast<const void*>(&sj_fp32_kernel<C, tl_for(C), PD, WPE>), \
-        &launch_fp32<C, PD, WPE>                                                                             \
+        &launch_fp32<C, PD, WPE>, C                                                                          \
   }
 static const Fp64Variant kFp32Variants[] = {
     SKMP_FP32_V(8, 1, 2), SKMP_FP32_V(16, 1, 2), SKMP_FP32_V(8, 1, 3), SKMP_FP32_V(12, 1, 2), SKMP_FP32_V(8, 2, 3),
@@ -1712,7 +1713,7 @@ static int run_join(int64_t n_series, const int64_t* offsets, bool ab, const Joi
     } else {
       const int grid = (int)std::min<int64_t>(grid_for(var.fn, 64, 0), pl.total_units);
       var.launch(dim3(grid), st, s);
-      if (prec == SKMP_FP32) s.kgroup = var.C;  // its keys name a lane's C diagonals
+      if (var.group > 1) s.kgroup = var.group;  // its keys name a lane's group of diagonals
     }
   }
   SKMP_CHECK_HIP(hipGetLastError());
