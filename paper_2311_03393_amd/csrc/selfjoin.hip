@@ -1109,7 +1109,20 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
     partner = x + (int64_t)(GMAX - (rk & GMAX));
     dir = 1;
   }
-  if (st.kgroup > 1 && dir != 0 && invn[x] != 0.0)
+  // an append's old window whose new candidate, judged by its key, cannot
+  // beat the stored distance keeps it without a polish (nor, for grouped
+  // keys, the search of the group).  The 32-bit keys resolve 1 - rho to
+  // better than 1.2e-4 relative plus 1.2e-7 absolute, the FP64 keys far
+  // better; a flat partner is covered by the flat-window rule below.
+  bool worse = false;
+  if (dir != 0 && x < sp.keep && invn[x] != 0.0 && (st.kgroup > 1 || cinvn[partner] != 0.0)) {
+    const unsigned long long kk = dir < 0 ? ck : rk;
+    const double rho = __longlong_as_double((long long)(kk & ~GMAX)) - 2.0;
+    const double d2 = 2.0 * m * (1.0 - rho);
+    const double po = sp.p0[(int64_t)g * sp.ldp + x];
+    worse = d2 > po * po * (1.0 + 1e-3) + 2e-4 * m;
+  }
+  if (!worse && st.kgroup > 1 && dir != 0 && invn[x] != 0.0)
     partner = best_in_group(sh_w + threadIdx.x, mu[x], invn[x], rc, sp.cn, cmu, cinvn, n_cols, x, partner, dir,
                             st.kgroup, pexcl, sp.keep, m);
 
@@ -1139,18 +1152,6 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   } else {
     best = INFINITY;
     arg = -1;
-    // an append's old window whose new candidate, judged by its key, cannot
-    // beat the stored distance keeps it without a polish (the 32-bit keys
-    // resolve 1 - rho to about 1.2e-4 relative plus 1.2e-7 absolute, the
-    // FP64 keys far better)
-    bool worse = false;
-    if (partner >= 0 && x < sp.keep && cinvn[partner] != 0.0) {
-      const unsigned long long kk = (ck != 0ull && ck >= rk) ? ck : rk;
-      const double rho = __longlong_as_double((long long)(kk & ~GMAX)) - 2.0;
-      const double d2 = 2.0 * m * (1.0 - rho);
-      const double po = sp.p0[(int64_t)g * sp.ldp + x];
-      worse = d2 > po * po * (1.0 + 1e-3) + 2e-4 * m;
-    }
     if (partner >= 0 && !worse) {
       if (cinvn[partner] == 0.0) {
         best = sqrt_m;
