@@ -16,7 +16,7 @@ import pytest
 
 import datagen
 from oracle import sketchmp_oracle as O
-from tests.helpers import certified_top, check_neighbours, discords_equivalent, fp64_tol, profile_close
+from tests.helpers import certified_top, check_neighbours, discords_equivalent, fp64_tol, mixed_tol, profile_close
 
 pytestmark = pytest.mark.gpu
 
@@ -239,8 +239,9 @@ def test_count_sketch_more_than_64_groups(dev, c_oracle):
     assert int(nf[0]) == 5 and all(0 <= g < k for _, g, _ in got)
 
 
-@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
-def test_nonfinite_input_is_marked_without_the_check_flag(dev, c_oracle, bad):
+@pytest.mark.parametrize("bad,prec", [(np.nan, "fp64"), (np.inf, "fp64"), (-np.inf, "fp64"), (np.nan, "fp32"),
+                                      (np.inf, "bf16x3")])
+def test_nonfinite_input_is_marked_without_the_check_flag(dev, c_oracle, bad, prec):
     """Without SKMP_FLAG_CHECK_FINITE (no host read-back: capture-safe) a NaN
     or Inf sample is never dropped silently: its dimension's statistics come
     back as (NaN, NaN), the sketch of that series is NaN, its windows get
@@ -254,7 +255,7 @@ def test_nonfinite_input_is_marked_without_the_check_flag(dev, c_oracle, bad):
     T = np.concatenate([datagen.tiny_series(300 + q, 4, L) for q, L in enumerate(lens)], axis=1)
     T[1, offsets[1] + 517] = bad          # series 1, dimension 1
     R, stats = skmp.sketch_build(_to_dev(torch, T, dev), offsets, k, "gauss", 9)
-    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl)
+    P, I = skmp.mp_selfjoin(R, offsets, k, m, excl, prec=prec)
     idx, grp, score, nf = skmp.top_discords(P, offsets, k, m, 5)
     torch.cuda.synchronize()
     st = stats.cpu().numpy()
@@ -269,10 +270,12 @@ def test_nonfinite_input_is_marked_without_the_check_flag(dev, c_oracle, bad):
     R_o, _, _, _ = O.build(T[:, :offsets[1]], "gauss", k, 9)
     assert np.max(np.abs(Rn[:, :offsets[1]] - R_o)) < 1e-12 * np.max(np.abs(R_o))
     n_sub0 = lens[0] - m + 1
+    tol = fp64_tol(m) if prec == "fp64" else mixed_tol(m)
     for g in range(k):
         P_o, _ = c_oracle.profile(R_o[g], m, excl)
-        ok, err = profile_close(P[g, :n_sub0], P_o, m, fp64_tol(m))
+        ok, err = profile_close(P[g, :n_sub0], P_o, m, tol)
         assert ok.all(), err
+        check_neighbours(c_oracle, R_o[g], m, excl, np.arange(n_sub0), I[g, :n_sub0], P_o, tol)
     assert int(nf[0]) == 5
 
 
