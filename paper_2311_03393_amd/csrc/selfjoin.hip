@@ -231,8 +231,12 @@ __global__ __launch_bounds__(256) void substats_kernel(SJState st) {
   st.invn[sidx] = iv;
   st.mu[sidx] = mu;
   if (st.bplanes) {
-    blk_write_planes(st, 8 * gbase, sp.lpad, xp, df, dg, blk_scale(scale, st.bprec));
-    st.finvn[sidx] = (float)iv;
+    // the blocked MFMA form's covariance carries the operands' power-of-two
+    // scale squared; its FP32 norms carry 1 / scale each, so a cell's product
+    // of the two norms removes it (exactly: powers of two)
+    const double bs = blk_scale(scale, st.bprec);
+    blk_write_planes(st, 8 * gbase, sp.lpad, xp, df, dg, bs);
+    st.finvn[sidx] = (float)(iv / bs);
   }
   if (st.walk_stats) {
     st.dfdg[sidx] = make_double2(df, dg);

@@ -134,9 +134,11 @@ __device__ __forceinline__ uint32_t row16_min(uint32_t x) {
 }
 
 // Codes of the cells: 16 (NB - 1 - t) + v for tile t, row v of the lane's
-// four.  Those above 64 (not inline constants) are held in VGPRs, index:
+// four.  Those above 64 (not inline constants) of tiles t >= 1 are held in
+// VGPRs, index below; tile 0's come with the band's edge mask folded in
+// (code0 in the kernel).
 constexpr int code_slot(uint32_t code) { return code <= 67 ? (int)code - 65 : 3 + ((int)code / 16 - 5) * 4 + (int)code % 16; }
-constexpr int NCODEV = 15;
+constexpr int NCODEV = 11;
 
 // Key of a cell: the bits of kf with the low 10 bits replaced by the cell's
 // code CODE, one v_and_or_b32 (gfx9 VOP3 takes no literal, so the mask and
@@ -148,6 +150,13 @@ __device__ __forceinline__ uint32_t key_of(float kf, uint32_t keep_v, const uint
     asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(__float_as_uint(kf)), "v"(keep_v), "i"(CODE));
   else
     asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(__float_as_uint(kf)), "v"(keep_v), "v"(codev[code_slot(CODE)]));
+  return r;
+}
+
+// The same with the code in a VGPR (tile 0: the code with the edge mask).
+__device__ __forceinline__ uint32_t key_with(float kf, uint32_t keep_v, uint32_t code_v) {
+  uint32_t r;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(__float_as_uint(kf)), "v"(keep_v), "v"(code_v));
   return r;
 }
 
@@ -206,7 +215,6 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
     const double* __restrict__ mu = st.mu + gbase + PADL;
     const double* __restrict__ muc = st.mu + cgbase + PADL;
     const double sc = blk_scale(st.scale[(int64_t)up.s * st.groups.count + gi], PREC);
-    const float inv_sc2 = (float)(1.0 / (sc * sc));
     // operand planes and FP32 window norms of the rows and of the columns
     const __amdgpu_buffer_rsrc_t pa =
         __builtin_amdgcn_make_buffer_rsrc((void*)(st.bplanes + 8 * gbase), 0, (int)(sp.lpad * 16), kBufWord3);
@@ -300,10 +308,12 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
         const int lane_base = 16 * NB * (Q - 1 - b) + 15 - l16 + 4 * lg;
         // band 0 of the first unit: its tile 0 holds cells below the first
         // diagonal (j - i < d0, trivial matches) at every step
+        // (those cells' keys get KEY_NONE in the same AND-OR that embeds tile 0's code)
         const bool edge = (up.inner == 0 && b == 0);
-        uint32_t emask[4];
+        uint32_t code0[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) emask[v] = (edge && l16 < 4 * lg + v) ? KEY_NONE : 0u;
+        for (int v = 0; v < 4; ++v)
+          code0[v] = (uint32_t)(16 * (NB - 1) + v) | ((edge && l16 < 4 * lg + v) ? KEY_NONE : 0u);
         const int soB0 = (Ip + db) * 2;                // column tile c at soffset soB0 + 32 (c + 1)
         // column fragments of tiles c = -1 .. NB - 2 (slot (c + NB) % NB)
         u32x4 bh[NB], bl[NB];
@@ -353,9 +363,9 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
           for (int rr = 0; rr < NB; ++rr) {
             const int s = s0 + rr;
             const int I = Ip + 16 * s;
-            float rs_[4];  // 1 / (sqrt(m) sigma) of the lane's rows, times 1 / scale^2
-#pragma unroll
-            for (int v = 0; v < 4; ++v) rs_[v] = ri[v] * inv_sc2;
+            // 1 / (sqrt(m) sigma scale) of the lane's rows (the column norms ci
+            // carry 1 / scale too: together they remove the covariance's scale^2)
+            const f32x4 rs_ = ri;
             u32x4 ahn, aln;
             f32x4 rin;
             uint32_t rowm[4], kprev[4];
@@ -373,8 +383,10 @@ __global__ __launch_bounds__(64, WPE) void sj_blk_kernel(SJState st) {
                 static_for<4>([&](auto vc) {
                   constexpr int v = decltype(vc)::value;
                   const float kf = __builtin_fmaf(-(acc[t][v] * ci[sl]), rs_[v], KEY_ONE);
-                  key[v] = key_of<(uint32_t)(16 * (NB - 1 - t) + v)>(kf, keep_v, codev);
-                  if (t == 0) key[v] |= emask[v];  // cells below the first diagonal
+                  if constexpr (t == 0)
+                    key[v] = key_with(kf, keep_v, code0[v]);  // cells below the first diagonal: KEY_NONE
+                  else
+                    key[v] = key_of<(uint32_t)(16 * (NB - 1 - t) + v)>(kf, keep_v, codev);
                 });
                 // column tile (slot sl): its four rows of this step
                 col[sl] = min3u(col[sl], key[0], key[1]);
