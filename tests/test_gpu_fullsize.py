@@ -12,7 +12,10 @@ brute-force rows, with their neighbours; every window's reported distance is
 the exact distance of its reported neighbour; and the top-10 discords equal
 the certified exact top-10 (upper bounds from the GPU's neighbours, exact rows
 in descending bound order until the greedy list is fixed), near ties accepted
-as an epsilon-greedy sequence on the exact values.
+as an epsilon-greedy sequence on the exact values.  Whole profiles (every
+window) are compared with the oracle's diagonal double-double reference
+(itself pinned to the brute force): all 8 water-treatment groups, and the
+first transportation group.
 """
 import sys
 
@@ -110,3 +113,46 @@ def test_transportation_full_size_sketch(transport):
 def test_transportation_full_size(transport, c_oracle, prec):
     w, R, R_np = transport
     _check_join(c_oracle, w, R, R_np, prec, 0, 24, 2)
+
+
+@pytest.fixture(scope="module")
+def water_ref(water, c_oracle):
+    w, R, R_np = water
+    _say("diagonal reference, water-treatment, 8 groups")
+    return [c_oracle.profile_diag(R_np[g], w.m, w.excl) for g in range(w.k)]
+
+
+def _check_whole(c_oracle, w, R, R_np, ref, prec, refresh, groups):
+    import torch
+    import paper_2311_03393_amd as skmp
+    m, excl, k = w.m, w.excl, w.k
+    _say("whole profile", prec, "refresh", refresh, "groups", list(groups))
+    P, I = skmp.mp_selfjoin(R, w.offsets, k, m, excl, prec=prec, refresh=refresh)
+    torch.cuda.synchronize()
+    n_sub = w.T.shape[1] - m + 1
+    P, I = P.cpu().numpy()[:, :n_sub], I.cpu().numpy()[:, :n_sub]
+    tol = mixed_tol(m) if prec != "fp64" else fp64_tol(m)
+    for g, (P_o, _) in zip(groups, ref):
+        ok, err = profile_close(P[g], P_o, m, tol)
+        assert ok.all(), (prec, g, np.count_nonzero(~ok), err)
+        check_neighbours(c_oracle, R_np[g], m, excl, np.arange(n_sub), I[g], P_o, tol)
+    _say("whole profile ok", prec)
+
+
+@pytest.mark.parametrize("prec,refresh", [("fp32", 256), ("bf16x3", 0), ("fp64", 0)])
+def test_water_treatment_whole_profile(water, water_ref, c_oracle, prec, refresh):
+    w, R, R_np = water
+    _check_whole(c_oracle, w, R, R_np, water_ref, prec, refresh, range(w.k))
+
+
+@pytest.fixture(scope="module")
+def transport_ref(transport, c_oracle):
+    w, R, R_np = transport
+    _say("diagonal reference, transportation, group 0")
+    return [c_oracle.profile_diag(R_np[0], w.m, w.excl)]
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_transportation_whole_profile_of_group_0(transport, transport_ref, c_oracle, prec):
+    w, R, R_np = transport
+    _check_whole(c_oracle, w, R, R_np, transport_ref, prec, 0, [0])

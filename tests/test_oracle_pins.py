@@ -217,6 +217,30 @@ def test_pair_dist_reproduces_every_profile_entry(seed, excl, c_oracle):
         assert abs(O.dist(r[i:i + m], r[I[i]:I[i] + m], scale) - P[i]) < 1e-12
 
 
+@pytest.mark.parametrize("seed,excl", [(11, 3), (12, 12), (13, 1), (14, 230), (15, 262)])
+def test_diagonal_reference_equals_brute_force(seed, excl, c_oracle):
+    """The full-size reference (QT carried down each diagonal in double-double,
+    exact recompute every 64 rows) against the brute force, on series with flat
+    stretches, a near-flat window, affine copies at rho = +1 and -1, and
+    exclusion zones that leave fewer admissible diagonals than one vector
+    step of 8 (and rows without any partner): every profile entry within
+    1e-12 * 2 sqrt(m) (squared distances near 0), every reported neighbour
+    exactly as near as the brute force's, the same rows without a partner."""
+    r, m = _pair_series(seed)
+    P, I = c_oracle.profile(r, m, excl)
+    Pd, Id = c_oracle.profile_diag(r, m, excl)
+    fin = np.isfinite(P)
+    assert np.array_equal(fin, np.isfinite(Pd)) and np.array_equal(Id < 0, ~fin)
+    tol = 1e-12 * 2 * math.sqrt(m)
+    err = np.abs(Pd[fin] - P[fin])
+    sq = np.abs(Pd[fin] ** 2 - P[fin] ** 2)
+    assert np.all((err <= tol) | (sq <= 2 * math.sqrt(m) * tol)), float(err.max())
+    rows = np.arange(P.size)[fin]
+    d = c_oracle.pair_dist(r, m, rows, Id[fin])
+    assert np.all(np.abs(d - P[fin]) <= 1e-9), float(np.max(np.abs(d - P[fin])))
+    assert np.all(np.abs(rows - Id[fin]) >= excl)
+
+
 def test_pair_dist_matches_scipy_cdist_on_random_pairs(c_oracle):
     """pair_dist against scipy cdist of explicitly normalised windows, on
     random pairs that include flat and near-flat windows; d(x, -x) = 2 sqrt(m)."""
