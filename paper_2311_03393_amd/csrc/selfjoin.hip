@@ -1115,9 +1115,10 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   }
   // an append's old window whose new candidate, judged by its key, cannot
   // beat the stored distance keeps it without a polish (nor, for grouped
-  // keys, the search of the group).  The 32-bit keys resolve 1 - rho to
-  // better than 1.2e-4 relative plus 1.2e-7 absolute, the FP64 keys far
-  // better; a flat partner is covered by the flat-window rule below.
+  // keys, the search of the group).  Appends run in FP64 or FP32: the FP32
+  // keys resolve 1 - rho to better than 1.2e-4 relative plus 1.2e-7
+  // absolute, the FP64 keys far better; a flat partner is covered by the
+  // flat-window rule below.
   bool worse = false;
   if (dir != 0 && x < sp.keep && invn[x] != 0.0 && (st.kgroup > 1 || cinvn[partner] != 0.0)) {
     const unsigned long long kk = dir < 0 ? ck : rk;

@@ -32,7 +32,7 @@
 // t + 1 used at step s - 1, so the column fragments rotate through registers
 // (the step loop is unrolled by NB) and each step loads one new fragment.
 // Epilogue per cell: normalise (rho = C / (m sigma_i sigma_j)), key = bits of
-// 1 - rho + 2^-10 (a positive float, ordered like an unsigned integer) with
+// 1 - rho + 2^-6 (a positive float, ordered like an unsigned integer) with
 // the cell's diagonal within the unit in the low 10 bits, row minima over the
 // band's tiles (then over the 16 lanes of a row) and column minima over the
 // steps a column spends in the band (then over the 4 lane groups).  Both go to
@@ -68,11 +68,15 @@ constexpr uint32_t CODE_MASK = 1023u;
 constexpr uint32_t KEEP = ~CODE_MASK;
 constexpr int CODE_TOP = BLK_DIAGS - 1;  // code = CODE_TOP - (delta - first diagonal of the unit)
 static_assert(CODE_TOP + 15 <= (int)CODE_MASK, "unit too wide for the 10-bit diagonal code");
-// 1 - rho + 2^-10 stays positive while rho <= 1 + 2^-10 (the 16-bit operand
-// error is ~1e-5 in rho); the bias shifts every key alike, so it changes no
-// ordering, and the global form adds it back (3 + 2^-10 - key = rho + 2).
-constexpr float KEY_ONE = 1.0f + 9.765625e-4f;
-constexpr double KEY_BACK = 3.0 + 9.765625e-4;
+// 1 - rho + 2^-6 stays positive while rho <= 1 + 2^-6: the 16-bit operands'
+// error in rho (about 1e-5, up to ~1e-3 across large variance changes inside
+// a period) cannot turn the best match of a row into a negative key, which
+// would read as padding.  The bias shifts every key alike, so it changes no
+// ordering; keys keep 13 fraction bits (relative resolution 2^-13 above the
+// bias, about 2e-6 absolute in rho below it), and the global form adds it
+// back (3 + 2^-6 - key = rho + 2).
+constexpr float KEY_ONE = 1.0f + 0.015625f;
+constexpr double KEY_BACK = 3.0 + 0.015625;
 // Invalid cells: above every real key and every NaN key, with room for the
 // lane's part of the code to be added without wrapping.
 constexpr uint32_t KEY_NONE = 0xFF000000u;
