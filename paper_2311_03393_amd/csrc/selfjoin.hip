@@ -694,11 +694,10 @@ __global__ __launch_bounds__(64, WPE) void sj_fp64_kernel(SJState st) {
 constexpr float KEY_ONE = 1.0f + 9.765625e-4f;  // 1 + 2^-10
 constexpr double KEY_BACK = 3.0 + 9.765625e-4;
 
+// Statistics of a row, fetched PD steps ahead.
 struct StepLoadF {
   float2 rs;
   float rinv;
-  float2 cs;
-  float cinv;
 };
 
 struct StatRsrcF {
@@ -719,17 +718,25 @@ __device__ __forceinline__ StatRsrcF make_rsrc_f(const SJState& st, int64_t gbas
 }
 
 template <int C>
-__device__ __forceinline__ StepLoadF load_step_f(const StatRsrcF& R, int u, int U, int t) {
+__device__ __forceinline__ StepLoadF load_row_f(const StatRsrcF& R, int u, int t) {
   StepLoadF l;
   const int rs_el = u + PADL - 63;
   const int vrow = 63 - t;
   l.rs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.rd, vrow * 8, rs_el * 8, 0));
   l.rinv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ri, vrow * 4, rs_el * 4, 0));
+  return l;
+}
+
+// Statistics of the column U (lane 0's; lane t's is U + t (C - 1)), loaded
+// straight into the registers of a column slot.
+template <int C>
+__device__ __forceinline__ void load_col_f(const StatRsrcF& R, int U, int t, float& df, float& dg, float& inv) {
   const int up = U + PADL;
   const int el = (up % (C - 1)) * R.plane + up / (C - 1);
-  l.cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
-  l.cinv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
-  return l;
+  const float2 cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
+  df = cs.x;
+  dg = cs.y;
+  inv = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
 }
 
 template <int C>
@@ -746,6 +753,12 @@ struct LaneStateF {
 // to LDS; the merge later finds the partner among the lane's C diagonals.
 // Truncating the low bits is monotone, so the truncated minimum is the
 // minimum of the truncated keys.
+// Column slots: the column of a step's diagonal 0 is used for the last time
+// by that step's first cell, and the column entering at the next step (its
+// diagonal C - 1, computed last) takes over its slot.  Its statistics are
+// loaded right after that first cell, into the slot's own registers: about
+// two steps of latency cover, and no register copies where the unrolled
+// walk wraps around.
 template <int C, int PD>
 __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ring)[PD], uint32_t lcode,
                                                uint32_t keep, int ngroups, int u0, int db, const StatRsrcF& R,
@@ -754,16 +767,11 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
 #pragma unroll
     for (int p = 0; p < C; ++p) {
       const int us = gidx * C + p;
-      const int ua = u0 + us + PD;
-      const StepLoadF ahead = load_step_f<C>(R, ua, ua + db + C - 1, t);
+      const StepLoadF ahead = load_row_f<C>(R, u0 + us + PD, t);
       const StepLoadF cur = ring[0];
 #pragma unroll
       for (int k = 0; k + 1 < PD; ++k) ring[k] = ring[k + 1];
       ring[PD - 1] = ahead;
-      const int sn = (p + C - 1) % C;
-      ls.cdf[sn] = cur.cs.x;
-      ls.cdg[sn] = cur.cs.y;
-      ls.cinv[sn] = cur.cinv;
       uint32_t rowp = 0u;
 #pragma unroll
       for (int q = 0; q < C; ++q) {
@@ -778,6 +786,7 @@ __device__ __forceinline__ void sjf_run_groups(LaneStateF<C>& ls, StepLoadF (&ri
         else ls.colacc[sl] = min(ls.colacc[sl], key);
         ls.Cq[q] = __builtin_fmaf(cur.rs.x, ls.cdg[sl], ls.Cq[q]);
         ls.Cq[q] = __builtin_fmaf(ls.cdf[sl], cur.rs.y, ls.Cq[q]);
+        if (q == 0) load_col_f<C>(R, u0 + us + db + C, t, ls.cdf[sl], ls.cdg[sl], ls.cinv[sl]);
       }
       atomicMin(&rowk[us + 63 - t], (rowp & keep) | lcode);
       atomicMin(&colk[us + t * (C - 1)], (ls.colacc[p] & keep) | lcode);
@@ -793,6 +802,8 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
   static_assert(TL % C == 0, "tile length must be a multiple of C");
   static_assert(C >= 2 && C <= 16, "C diagonals per lane (the merge searches at most 16)");
   constexpr int MCH = seed_chunk<C, WPE>();
+  static_assert(WPE < 4 || tile_lds_bytes<uint32_t, NROW, NCOL, C, MCH>() <= 10240,
+                "16 workgroups of one wave per CU share its 160 KB of LDS");
   __shared__ __align__(16) uint32_t lds[tile_lds_bytes<uint32_t, NROW, NCOL, C, MCH>() / 4];
   uint32_t* rowk = lds;
   uint32_t* colk = lds + NROW;
@@ -852,22 +863,16 @@ __global__ __launch_bounds__(64, WPE) void sj_fp32_kernel(SJState st) {
     }
     refill_keys(lds, NROW + NCOL, 0xFFFFFFFFu, t);
     const StatRsrcF R = make_rsrc_f<C>(st, gbase, sp.lpad, cgbase, sp.clpad);
-    {
-      const int up = u_begin + db + PADL;
+    // the first step's columns: diagonal q in slot q (C - 1 enters with it)
 #pragma unroll
-      for (int q = 0; q < C - 1; ++q) {
-        const int el = ((up + q) % (C - 1)) * R.plane + (up + q) / (C - 1);
-        const float2 cs = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(R.cd, t * 8, el * 8, 0));
-        ls.cdf[q] = cs.x;
-        ls.cdg[q] = cs.y;
-        ls.cinv[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.ci, t * 4, el * 4, 0));
-        ls.colacc[q] = 0xFFFFFFFFu;
-      }
+    for (int q = 0; q < C; ++q) {
+      load_col_f<C>(R, u_begin + db + q, t, ls.cdf[q], ls.cdg[q], ls.cinv[q]);
+      ls.colacc[q] = 0xFFFFFFFFu;
     }
     __builtin_amdgcn_s_setprio(1);
     StepLoadF ring[PD];
 #pragma unroll
-    for (int k = 0; k < PD; ++k) ring[k] = load_step_f<C>(R, u_begin + k, u_begin + k + db + C - 1, t);
+    for (int k = 0; k < PD; ++k) ring[k] = load_row_f<C>(R, u_begin + k, t);
     for (int u0 = u_begin; u0 < u_end; u0 += TL) {
       const int ngroups = (min(TL, u_end - u0) + C - 1) / C;
       sjf_run_groups<C, PD>(ls, ring, lcode, keep, ngroups, u0, db, R, rowk, colk, t);
