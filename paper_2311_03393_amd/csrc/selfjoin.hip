@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(256) void append_direct_kernel(SJState st) {
 // brings the sum back into range.
 __device__ int64_t best_in_group(const double* wx, double mx, double ix, const double* rc, int64_t cn,
                                  const double* cmu, const double* cinvn, int64_t n_cols, int64_t x, int64_t p0, int dir,
-                                 int G, int pexcl, int64_t keep, int m) {
+                                 int G, int pexcl, int64_t keep, int m, double& d2_best) {
   const int64_t glo = dir > 0 ? p0 : p0 - (G - 1), ghi = glo + G - 1;  // the group's candidates
   const int64_t lo = glo < 0 ? 0 : glo;
   const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc((void*)rc, 0, (int)(cn * 8), kBufWord3);
@@ -1068,8 +1068,14 @@ __device__ int64_t best_in_group(const double* wx, double mx, double ix, const d
       arg = p;
     }
   }
+  d2_best = best;
   return arg;
 }
+
+// Squared distances (in units of m) from which the FP32 keys' group search
+// result is reported directly; nearer partners get the explicit-difference
+// distance, which keeps full precision down to d = 0.
+constexpr double kPolishFromCorr = 0.01;
 
 __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
   // samples [x0, x0 + 256 + m - 1) of the chunk (the block's own windows),
@@ -1132,9 +1138,10 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
     const double po = sp.p0[(int64_t)g * sp.ldp + x];
     worse = d2 > po * po * (1.0 + 1e-3) + 2e-4 * m;
   }
+  double d2_group = -1.0;  // the group search's squared distance of its choice (-1: no search)
   if (!worse && st.kgroup > 1 && dir != 0 && invn[x] != 0.0)
     partner = best_in_group(sh_w + threadIdx.x, mu[x], invn[x], rc, sp.cn, cmu, cinvn, n_cols, x, partner, dir,
-                            st.kgroup, pexcl, sp.keep, m);
+                            st.kgroup, pexcl, sp.keep, m, d2_group);
 
   const double sqrt_m = sqrt((double)m);
   const int64_t sg = (int64_t)sp.cs * st.groups.count + c.gi;
@@ -1165,6 +1172,12 @@ __global__ __launch_bounds__(256) void merge_kernel(SJState st) {
     if (partner >= 0 && !worse) {
       if (cinvn[partner] == 0.0) {
         best = sqrt_m;
+      } else if (d2_group >= kPolishFromCorr * m) {
+        // the group search scored the partner by its exact FP64 centred
+        // correlation: d^2 = 2 m (1 - rho) carries an absolute error of about
+        // m eps (|e| / sigma) (|y| / sigma) in d^2, below 1e-10 in d this far
+        // from zero, so the explicit-difference pass is not repeated
+        best = sqrt(fmin(d2_group, 4.0 * m));
       } else {
         // exact distance from explicit differences of the normalised windows
         const double ax = invn[x] * sqrt_m, ap = cinvn[partner] * sqrt_m;
