@@ -1,6 +1,6 @@
 """GPU parity at the documented limits of the C-ABI: the longest subsequences
 (m = 2048 for the FP64 and FP32 paths, 1024 for the MFMA paths), the largest
-group count (k = 64), and appends at m = 2048 (the direct short-append kernel
+group count of a join (k = 64, every precision), and appends at m = 2048 (the direct short-append kernel
 stages its longest windows there).  Rows are sampled where the oracle's brute
 force would take minutes; the reported neighbour must attain the oracle's
 nearest-neighbour distance and the reported distance must be its exact one.
@@ -58,13 +58,15 @@ def test_longest_subsequences(dev, c_oracle, prec, m):
     _check_rows(c_oracle, R_np, m, excl, P, I, rows, tol, f"{prec} m={m}")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_most_groups(dev, c_oracle, prec):
     """k = 64 sketch groups (a count sketch of 200 dimensions), every group's
-    full profile against the oracle."""
+    full profile against the oracle, in every precision (the 16-bit paths in
+    their default blocked MFMA form)."""
     import torch
     import paper_2311_03393_amd as skmp
     n, m, excl, k = 1200, 16, 4, 64
+    _say("most groups", prec, k)
     T = datagen.tiny_series(310, 200, n)
     Tt = torch.from_numpy(T).to(dev)
     R, _ = skmp.sketch_build(Tt, [0, n], k, "count", 31)
