@@ -198,7 +198,11 @@ size_t mp_selfjoin_workspace(int64_t n_series, const int64_t* offsets, int32_t k
  * Subsequence statistics use the population sigma; a subsequence whose sigma
  * is <= 1e-10 * max|R^(g)| over its series is flat and normalises to the zero
  * vector (dist(flat, flat) = 0, dist(flat, other) = sqrt(m)).  Reported P values
- * are recomputed in FP64 from explicit differences for the reported neighbour.
+ * are recomputed in FP64 for the reported neighbour: from explicit differences
+ * of the normalised subsequences, or (SKMP_FP32, where d^2 >= 0.01 m) from the
+ * neighbour's exact FP64 centred correlation, d^2 = 2 m (1 - rho), which the
+ * search of its diagonal group has just computed (within 1e-10 of the former
+ * at that distance).
  * SKMP_EINVAL (message in skmp_last_error) when the join needs more than
  * 2^32 - 2^20 work units (groups x bands of 64 C diagonals x strips of
  * `refresh` rows, C = 16 in FP32 and 8 in FP64; one series of 12 million
